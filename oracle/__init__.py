@@ -1,0 +1,285 @@
+"""FP64 CPU oracle of the Free-Energy Machine step (arXiv 2412.09285).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package; the product path
+(``paper_2412_09285_amd``) never does.  The arithmetic lives in the plain C
+file ``fem_oracle.c`` (double precision, single thread, loops in the paper's
+order); this module only marshals NumPy arrays to it.
+
+Pinned by ``tests/test_oracle_pins.py``: brute-force expectations over all
+configurations, central finite differences of F, closed forms at special
+points, the mean-field fixed point, schedule endpoints, Adam against
+``torch.optim.Adam`` in float64, brute-force optima and closed-form optimum
+families.  The MPNN reference (``oracle.mpnn``) is pinned by finite
+differences of its own loss; its training quality is parity unpinned.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fem_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_fem_oracle.so")
+_lib = None
+
+KIND_MAXCUT, KIND_BMINCUT, KIND_MAXSAT = 0, 1, 2
+SCHED_LINEAR, SCHED_EXP, SCHED_INVPROP = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math) into ``_fem_oracle.so``."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("n", C.c_int32), ("q", C.c_int32), ("R", C.c_int32),
+        ("T", C.c_int32), ("sched", C.c_int32), ("lam_ramp", C.c_int32),
+        ("ne", C.c_int64),
+        ("eu", C.c_void_p), ("ev", C.c_void_p), ("w", C.c_void_p),
+        ("off", C.c_void_p), ("lits", C.c_void_p),
+        ("beta_min", C.c_double), ("beta_max", C.c_double), ("lam", C.c_double),
+        ("lr", C.c_double), ("b1", C.c_double), ("b2", C.c_double),
+        ("eps", C.c_double), ("wd", C.c_double),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        L.orc_beta.restype = C.c_double
+        L.orc_beta.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32]
+        L.orc_lambda.restype = C.c_double
+        L.orc_lambda.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_int32]
+        L.orc_maxcut_grad.restype = C.c_int
+        L.orc_maxcut_grad.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, C.c_double, P, P, P]
+        L.orc_bmincut_grad.restype = C.c_int
+        L.orc_bmincut_grad.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, C.c_double,
+                                       C.c_int32, P, C.c_double, P, P, P]
+        L.orc_maxsat_grad.restype = C.c_int
+        L.orc_maxsat_grad.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P, C.c_double, P, P, P]
+        L.orc_adam.restype = None
+        L.orc_adam.argtypes = [C.c_int64, P, P, P, P, C.c_double, C.c_double, C.c_double,
+                               C.c_double, C.c_double, C.c_int64]
+        L.orc_round.restype = None
+        L.orc_round.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P]
+        L.orc_cut.restype = None
+        L.orc_cut.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, P]
+        L.orc_group_sizes.restype = None
+        L.orc_group_sizes.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P]
+        L.orc_unsat.restype = None
+        L.orc_unsat.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P, P]
+        L.orc_run.restype = C.c_int
+        L.orc_run.argtypes = [C.POINTER(_Problem), C.c_int32, C.c_int32, P, P, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+# --------------------------------------------------------------------------
+# schedules
+# --------------------------------------------------------------------------
+def beta(sched: int, bmin: float, bmax: float, T: int, t: int) -> float:
+    return lib().orc_beta(sched, bmin, bmax, T, t)
+
+
+def lam(ramp: int, lam_max: float, T: int, t: int) -> float:
+    return lib().orc_lambda(int(ramp), lam_max, T, t)
+
+
+# --------------------------------------------------------------------------
+# per-step gradient and energies (one call = one evaluation at fixed h, beta)
+# --------------------------------------------------------------------------
+def maxcut_grad(n, u, v, w, h, beta_, want_grad=True):
+    """h: [n][R] float64.  Returns (g [n][R] or None, U [R], S [R])."""
+    h = _f64(h)
+    R = h.shape[1]
+    u, v, w = _i32(u), _i32(v), _f64(w)
+    g = np.zeros_like(h) if want_grad else None
+    U = np.zeros(R)
+    S = np.zeros(R)
+    rc = lib().orc_maxcut_grad(n, u.shape[0], _p(u), _p(v), _p(w), R, _p(h), beta_, _p(g), _p(U), _p(S))
+    if rc:
+        raise MemoryError(rc)
+    return g, U, S
+
+
+def bmincut_grad(n, u, v, w, q, lam_, h, beta_, want_grad=True):
+    """h: [n][R][q] float64."""
+    h = _f64(h)
+    R = h.shape[1]
+    u, v, w = _i32(u), _i32(v), _f64(w)
+    g = np.zeros_like(h) if want_grad else None
+    U = np.zeros(R)
+    S = np.zeros(R)
+    rc = lib().orc_bmincut_grad(n, u.shape[0], _p(u), _p(v), _p(w), q, lam_, R, _p(h), beta_,
+                                _p(g), _p(U), _p(S))
+    if rc:
+        raise MemoryError(rc)
+    return g, U, S
+
+
+def maxsat_grad(n, off, lits, h, beta_, want_grad=True):
+    h = _f64(h)
+    R = h.shape[1]
+    off, lits = _i64(off), _i32(lits)
+    g = np.zeros_like(h) if want_grad else None
+    U = np.zeros(R)
+    S = np.zeros(R)
+    rc = lib().orc_maxsat_grad(n, off.shape[0] - 1, _p(off), _p(lits), R, _p(h), beta_, _p(g), _p(U), _p(S))
+    if rc:
+        raise MemoryError(rc)
+    return g, U, S
+
+
+def adam(g, h, m1, m2, lr, b1, b2, eps, wd, n_step):
+    """In-place Adam on float64 arrays h, m1, m2 (all contiguous)."""
+    for a in (h, m1, m2):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib().orc_adam(h.size, _p(g), _p(h), _p(m1), _p(m2), lr, b1, b2, eps, wd, int(n_step))
+
+
+# --------------------------------------------------------------------------
+# read-out and integer evaluation
+# --------------------------------------------------------------------------
+def round_(h, q: int = 1):
+    """sigma [R][n] int32 from fields h ([n][R] if q == 1 else [n][R][q])."""
+    h = _f64(h)
+    n, R = h.shape[0], h.shape[1]
+    sigma = np.zeros((R, n), dtype=np.int32)
+    lib().orc_round(n, R, q, _p(h), _p(sigma))
+    return sigma
+
+
+def cut(n, u, v, w, sigma):
+    sigma = _i32(sigma)
+    R = sigma.shape[0]
+    u, v, w = _i32(u), _i32(v), _f64(w)
+    out = np.zeros(R)
+    lib().orc_cut(n, u.shape[0], _p(u), _p(v), _p(w), R, _p(sigma), _p(out))
+    return out
+
+
+def group_sizes(n, q, sigma):
+    sigma = _i32(sigma)
+    R = sigma.shape[0]
+    out = np.zeros((R, q), dtype=np.int64)
+    lib().orc_group_sizes(n, q, R, _p(sigma), _p(out))
+    return out
+
+
+def unsat(n, off, lits, sigma):
+    sigma = _i32(sigma)
+    R = sigma.shape[0]
+    off, lits = _i64(off), _i32(lits)
+    out = np.zeros(R, dtype=np.int64)
+    lib().orc_unsat(n, off.shape[0] - 1, _p(off), _p(lits), R, _p(sigma), _p(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# the annealing loop
+# --------------------------------------------------------------------------
+@dataclass
+class Params:
+    R: int
+    T: int
+    beta_min: float = 0.01
+    beta_max: float = 5.0
+    sched: int = SCHED_LINEAR
+    lr: float = 0.1
+    b1: float = 0.9
+    b2: float = 0.999
+    eps: float = 1e-8
+    wd: float = 0.0
+    lam: float = 0.0
+    lam_ramp: int = 0
+
+
+class Run:
+    """Holds one FP64 FEM run: h, m1, m2 and the step counter t."""
+
+    def __init__(self, kind, params: Params, h0, *, n, q=1, u=None, v=None, w=None, off=None, lits=None):
+        self.kind, self.p, self.n, self.q = kind, params, n, q
+        self.h = _f64(h0).copy()
+        self.m1 = np.zeros_like(self.h)
+        self.m2 = np.zeros_like(self.h)
+        self.t = 0
+        self._keep = []
+        pb = _Problem()
+        pb.kind, pb.n, pb.q, pb.R, pb.T = kind, n, q, params.R, params.T
+        pb.sched, pb.lam_ramp = params.sched, int(params.lam_ramp)
+        if kind == KIND_MAXSAT:
+            off, lits = _i64(off), _i32(lits)
+            self._keep += [off, lits]
+            pb.ne = off.shape[0] - 1
+            pb.off, pb.lits = off.ctypes.data, lits.ctypes.data
+        else:
+            u, v, w = _i32(u), _i32(v), _f64(w)
+            self._keep += [u, v, w]
+            pb.ne = u.shape[0]
+            pb.eu, pb.ev, pb.w = u.ctypes.data, v.ctypes.data, w.ctypes.data
+        pb.beta_min, pb.beta_max, pb.lam = params.beta_min, params.beta_max, params.lam
+        pb.lr, pb.b1, pb.b2, pb.eps, pb.wd = params.lr, params.b1, params.b2, params.eps, params.wd
+        self._pb = pb
+
+    def step(self, n_steps: int, record: bool = False):
+        """Advance n_steps; with record, return (g_hist, U_hist, S_hist) of
+        the evaluated steps (gradient and energies at h(t) before each
+        update)."""
+        R = self.p.R
+        vals = self.h.size
+        gh = np.zeros((n_steps,) + self.h.shape) if record else None
+        Uh = np.zeros((n_steps, R)) if record else None
+        Sh = np.zeros((n_steps, R)) if record else None
+        rc = lib().orc_run(C.byref(self._pb), self.t, n_steps, _p(self.h), _p(self.m1), _p(self.m2),
+                           _p(gh), _p(Uh), _p(Sh))
+        if rc:
+            raise MemoryError(rc)
+        assert vals == self.h.size
+        self.t += n_steps
+        return (gh, Uh, Sh) if record else None
+
+    def sigma(self):
+        return round_(self.h, 1 if self.kind != KIND_BMINCUT else self.q)
+
+
+def maxcut_run(graph, params: Params, h0):
+    return Run(KIND_MAXCUT, params, h0, n=graph.n, u=graph.u, v=graph.v, w=graph.w)
+
+
+def bmincut_run(graph, q, params: Params, h0):
+    return Run(KIND_BMINCUT, params, h0, n=graph.n, q=q, u=graph.u, v=graph.v, w=graph.w)
+
+
+def maxsat_run(cnf, params: Params, h0):
+    return Run(KIND_MAXSAT, params, h0, n=cnf.n_vars, off=cnf.clause_off, lits=cnf.lits)

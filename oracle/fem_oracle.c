@@ -1,0 +1,455 @@
+/*
+ * fem_oracle.c -- plain, slow, FP64 CPU reference of the Free-Energy Machine
+ * (FEM) step, written from the paper (Shen et al., "Free-Energy Machine for
+ * Combinatorial Optimization", arXiv 2412.09285).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header or table with the HIP
+ * library: it works directly from undirected edge lists and clause lists,
+ * never from the library's CSR / incidence structures.
+ *
+ * Everything is double precision and single-threaded.  Loops follow the
+ * definitions in the paper's order; no blocking, fusion or reordering.
+ *
+ * Readings of the paper taken here (each is listed in the design notes):
+ *  - Edge sums run over ordered pairs: each undirected edge {i,j} appears as
+ *    (i,j) and (j,i).  This is the convention under which the explicit
+ *    gradients printed in the supplementary section "The explicit gradients
+ *    and manipulated gradients" are derivatives of F, and under which the
+ *    stationary points reproduce the mean-field equation m = tanh(beta J m).
+ *  - MaxCut and Max-k-SAT use one logit per variable, P_i = sigmoid(h_i)
+ *    (supplementary section "Simplification of FEM for solving the MaxCut
+ *    problem"); balanced min-cut uses q logits and a softmax (Results,
+ *    "Free-Energy Machine").
+ *  - The balance term of bMinCut is lambda * sum_s [C(s)^2 - sum_i P_i(s)^2]
+ *    with C(s) = sum_i P_i(s), i.e. the sum over i != j of the Methods
+ *    free energy (the literal sum over all i,j of its second term would
+ *    subtract N copies of the self term).
+ *  - In Max-k-SAT a repeated literal counts once and a clause holding both x
+ *    and not-x is dropped (always satisfied).
+ *  - Adam follows PyTorch's torch.optim.Adam (coupled L2 weight decay, eps
+ *    outside the square root of the bias-corrected second moment, step count
+ *    starting at 1), as the paper uses PyTorch's optimisers (Methods,
+ *    "Hyperparameter tuning of different optimizers").
+ *
+ * Layouts: h, g, m1, m2 are [n][R] for one-logit problems and [n][R][q] for
+ * Potts, node-major with the replica (then the state) index fastest.
+ * Integer configurations sigma are [R][n] (replica-major), states 0..q-1; for
+ * one-logit problems sigma_i = 1 means P_i (sigmoid of h_i) is the larger
+ * marginal, i.e. h_i > 0.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Small numeric helpers                                                      */
+/* ------------------------------------------------------------------------- */
+
+/* ln(sigmoid(x)) without overflow: -log(1 + e^{-x}). */
+static double log_sigmoid(double x)
+{
+    if (x >= 0.0) return -log1p(exp(-x));
+    return x - log1p(exp(x));
+}
+
+static double sigmoid(double x)
+{
+    if (x >= 0.0) return 1.0 / (1.0 + exp(-x));
+    double e = exp(x);
+    return e / (1.0 + e);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Annealing schedules (Methods, "Different annealing schedules for the      */
+/* inverse temperature").                                                     */
+/*   sched 0: linear in beta, beta(0)=beta_min, beta(T-1)=beta_max           */
+/*   sched 1: exponential scheduling                                         */
+/*   sched 2: inverse-proportional scheduling (linear in temperature)        */
+/* ------------------------------------------------------------------------- */
+double orc_beta(int32_t sched, double bmin, double bmax, int32_t T, int32_t t)
+{
+    double x = (T > 1) ? (double)t / (double)(T - 1) : 0.0;
+    if (sched == 1) return exp((log(bmax) - log(bmin)) * x + log(bmin));
+    if (sched == 2) return 1.0 / ((1.0 / bmax - 1.0 / bmin) * x + 1.0 / bmin);
+    return bmin + (bmax - bmin) * x;
+}
+
+/* lambda(t): constant, or increased linearly from 0 to lambda_max over the
+ * annealing steps (supplementary "Demonstration of FEM solving the bMinCut
+ * problem"), with the same endpoint convention as the beta schedules. */
+double orc_lambda(int32_t ramp, double lam, int32_t T, int32_t t)
+{
+    if (!ramp) return lam;
+    return (T > 1) ? lam * (double)t / (double)(T - 1) : lam;
+}
+
+/* ------------------------------------------------------------------------- */
+/* MaxCut (Results, "Applications to the Maximum-Cut problem"; free energy   */
+/* in Methods; explicit gradient in the supplementary "The MaxCut problem";  */
+/* q = 2 reduction in "Simplification of FEM ...").                          */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * For every replica r: marginals P_i(+) = sigmoid(h_i), P_i(-) = 1 - P_i(+);
+ *   U = -sum_{ordered (i,j)} W_ij sum_s P_i(s) [1 - P_j(s)]
+ *   S = -sum_i sum_s P_i(s) ln P_i(s)
+ *   g^p_i(s) = sum_j W_ij [2 P_j(s) - 1] + (ln P_i(s) + 1) / beta
+ *   g^h_i    = [g^p_i(+) - g^p_i(-)] P_i(+) P_i(-)
+ * g may be NULL (energies only); U, S may be NULL.
+ */
+int orc_maxcut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
+                    const double* w, int32_t R, const double* h, double beta,
+                    double* g, double* U, double* S)
+{
+    double* P = (double*)malloc(sizeof(double) * (size_t)n);
+    double* Wsum = (double*)malloc(sizeof(double) * (size_t)n);   /* sum_j W_ij [2P_j(+)-1] */
+    if (!P || !Wsum) { free(P); free(Wsum); return -2; }
+    for (int32_t r = 0; r < R; ++r) {
+        for (int32_t i = 0; i < n; ++i) P[i] = sigmoid(h[(size_t)i * R + r]);
+        double u_acc = 0.0, s_acc = 0.0;
+        for (int32_t i = 0; i < n; ++i) Wsum[i] = 0.0;
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t i = eu[e], j = ev[e];
+            double pi = P[i], pj = P[j];
+            /* the two orderings (i,j) and (j,i) of the undirected edge */
+            double same_ij = pi * pj + (1.0 - pi) * (1.0 - pj);
+            u_acc += -w[e] * (1.0 - same_ij);   /* (i,j): sum_s P_i(s)[1-P_j(s)] */
+            u_acc += -w[e] * (1.0 - same_ij);   /* (j,i) */
+            /* sum_j W_ij [2 P_j(+) - 1] minus the same for state (-):
+               [2P_j(+)-1] - [2P_j(-)-1] = 2(2P_j(+)-1) */
+            Wsum[i] += w[e] * (2.0 * pj - 1.0);
+            Wsum[j] += w[e] * (2.0 * pi - 1.0);
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            double x = h[(size_t)i * R + r];
+            double lp = log_sigmoid(x), lm = log_sigmoid(-x);
+            double pp = P[i], pm = 1.0 - P[i];
+            s_acc += -(pp * lp + pm * lm);
+            if (g) {
+                /* state (+): sum_j W_ij[2P_j(+)-1]; state (-): sum_j W_ij[2P_j(-)-1] = -(...) */
+                double gp_plus = Wsum[i] + (lp + 1.0) / beta;
+                double gp_minus = -Wsum[i] + (lm + 1.0) / beta;
+                /* sigmoid(x) sigmoid(-x) without cancellation */
+                double pq = exp(lp + lm);
+                g[(size_t)i * R + r] = (gp_plus - gp_minus) * pq;
+            }
+        }
+        if (U) U[r] = u_acc;
+        if (S) S[r] = s_acc;
+    }
+    free(P);
+    free(Wsum);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Balanced min-cut with q Potts states (Results, "Applications to the       */
+/* q-way balanced minimum cut problem"; free energy in Methods; explicit     */
+/* gradient in the supplementary "The bMinCut problem"; softmax chain rule   */
+/* in "The explicit gradient formulations").                                 */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * For every replica r: P_i(s) = softmax_s h_i(s), C(s) = sum_j P_j(s);
+ *   U = sum_{ordered (i,j)} W_ij sum_s P_i(s)[1 - P_j(s)]
+ *     + lam * sum_s [C(s)^2 - sum_i P_i(s)^2]
+ *   S = -sum_i sum_s P_i(s) ln P_i(s)
+ *   g^p_i(s) = -2 sum_j W_ij P_j(s) + 2 lam [C(s) - P_i(s)] + (ln P_i(s) + 1)/beta
+ *   g^h_i(s) = [g^p_i(s) - sum_s' P_i(s') g^p_i(s')] P_i(s)
+ */
+int orc_bmincut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
+                     const double* w, int32_t q, double lam, int32_t R,
+                     const double* h, double beta, double* g, double* U, double* S)
+{
+    size_t nq = (size_t)n * (size_t)q;
+    double* P = (double*)malloc(sizeof(double) * nq);
+    double* lnP = (double*)malloc(sizeof(double) * nq);
+    double* Phi = (double*)malloc(sizeof(double) * nq);
+    double* C = (double*)malloc(sizeof(double) * (size_t)q);
+    double* gp = (double*)malloc(sizeof(double) * (size_t)q);
+    if (!P || !lnP || !Phi || !C || !gp) {
+        free(P); free(lnP); free(Phi); free(C); free(gp);
+        return -2;
+    }
+    for (int32_t r = 0; r < R; ++r) {
+        /* softmax per node, with the maximum subtracted before exponentiating */
+        for (int32_t i = 0; i < n; ++i) {
+            const double* hi = h + ((size_t)i * R + r) * q;
+            double mx = hi[0];
+            for (int32_t s = 1; s < q; ++s) if (hi[s] > mx) mx = hi[s];
+            double Z = 0.0;
+            for (int32_t s = 0; s < q; ++s) Z += exp(hi[s] - mx);
+            double lz = log(Z);
+            for (int32_t s = 0; s < q; ++s) {
+                lnP[(size_t)i * q + s] = hi[s] - mx - lz;
+                P[(size_t)i * q + s] = exp(lnP[(size_t)i * q + s]);
+            }
+        }
+        for (int32_t s = 0; s < q; ++s) C[s] = 0.0;
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t s = 0; s < q; ++s) C[s] += P[(size_t)i * q + s];
+        for (size_t k = 0; k < nq; ++k) Phi[k] = 0.0;
+        double cut_acc = 0.0;
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t i = eu[e], j = ev[e];
+            double dot = 0.0;
+            for (int32_t s = 0; s < q; ++s) {
+                dot += P[(size_t)i * q + s] * P[(size_t)j * q + s];
+                Phi[(size_t)i * q + s] += w[e] * P[(size_t)j * q + s];
+                Phi[(size_t)j * q + s] += w[e] * P[(size_t)i * q + s];
+            }
+            /* sum_s P_i(s)[1-P_j(s)] = 1 - P_i.P_j, once per ordering */
+            cut_acc += w[e] * (1.0 - dot);
+            cut_acc += w[e] * (1.0 - dot);
+        }
+        double bal = 0.0;
+        for (int32_t s = 0; s < q; ++s) {
+            double self = 0.0;
+            for (int32_t i = 0; i < n; ++i) self += P[(size_t)i * q + s] * P[(size_t)i * q + s];
+            bal += C[s] * C[s] - self;
+        }
+        double s_acc = 0.0;
+        for (size_t k = 0; k < nq; ++k) s_acc += -P[k] * lnP[k];
+        if (U) U[r] = cut_acc + lam * bal;
+        if (S) S[r] = s_acc;
+        if (g) {
+            for (int32_t i = 0; i < n; ++i) {
+                double avg = 0.0;
+                for (int32_t s = 0; s < q; ++s) {
+                    size_t k = (size_t)i * q + s;
+                    gp[s] = -2.0 * Phi[k] + 2.0 * lam * (C[s] - P[k]) + (lnP[k] + 1.0) / beta;
+                    avg += P[k] * gp[s];
+                }
+                for (int32_t s = 0; s < q; ++s) {
+                    size_t k = (size_t)i * q + s;
+                    g[((size_t)i * R + r) * q + s] = (gp[s] - avg) * P[k];
+                }
+            }
+        }
+    }
+    free(P); free(lnP); free(Phi); free(C); free(gp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Max-k-SAT (Results, "Application to the Max k-SAT problem"; free energy   */
+/* in Methods; explicit gradient in the supplementary "The MaxSAT problem",  */
+/* whose product index is read as P_k(W_mk), the literal of variable k in    */
+/* clause m).                                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Canonical clause: distinct variables with their literal signs. Returns the
+ * number of distinct variables, or -1 for a clause holding x and not-x. */
+static int canon_clause(const int32_t* lit, int64_t len, int32_t* var, int32_t* pos)
+{
+    int k = 0;
+    for (int64_t a = 0; a < len; ++a) {
+        int32_t L = lit[a];
+        int32_t x = (L > 0 ? L : -L) - 1;
+        int32_t sp = L > 0;
+        int seen = 0;
+        for (int b = 0; b < k; ++b) {
+            if (var[b] == x) {
+                if (pos[b] != sp) return -1; /* tautology */
+                seen = 1;
+            }
+        }
+        if (!seen) { var[k] = x; pos[k] = sp; ++k; }
+    }
+    return k;
+}
+
+/*
+ * W_mi = 1 for a positive literal; P_i(1) = sigmoid(h_i).  For every replica:
+ *   U = sum_m prod_{i in dm} [1 - P_i(W_mi)]
+ *   S = -sum_i sum_s P_i(s) ln P_i(s)
+ *   g^p_i(s) = -sum_m delta(s, W_mi) prod_{k in dm, k != i} [1 - P_k(W_mk)]
+ *              + (ln P_i(s) + 1)/beta
+ *   g^h_i = [g^p_i(1) - g^p_i(0)] P_i(1) P_i(0)
+ */
+int orc_maxsat_grad(int32_t n, int64_t M, const int64_t* off, const int32_t* lits,
+                    int32_t R, const double* h, double beta, double* g, double* U, double* S)
+{
+    int64_t kmax = 0;
+    for (int64_t m = 0; m < M; ++m) if (off[m + 1] - off[m] > kmax) kmax = off[m + 1] - off[m];
+    int32_t* var = (int32_t*)malloc(sizeof(int32_t) * (size_t)(kmax + 1));
+    int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (size_t)(kmax + 1));
+    double* ufalse = (double*)malloc(sizeof(double) * (size_t)(kmax + 1));
+    double* gp1 = (double*)malloc(sizeof(double) * (size_t)n);  /* energy part of g^p_i(1) */
+    double* gp0 = (double*)malloc(sizeof(double) * (size_t)n);  /* energy part of g^p_i(0) */
+    if (!var || !pos || !ufalse || !gp1 || !gp0) {
+        free(var); free(pos); free(ufalse); free(gp1); free(gp0);
+        return -2;
+    }
+    for (int32_t r = 0; r < R; ++r) {
+        for (int32_t i = 0; i < n; ++i) { gp1[i] = 0.0; gp0[i] = 0.0; }
+        double u_acc = 0.0;
+        for (int64_t m = 0; m < M; ++m) {
+            int k = canon_clause(lits + off[m], off[m + 1] - off[m], var, pos);
+            if (k < 0) continue;
+            for (int a = 0; a < k; ++a) {
+                double p1 = sigmoid(h[(size_t)var[a] * R + r]);
+                /* 1 - P_i(W_mi): the probability that this literal is false */
+                ufalse[a] = pos[a] ? 1.0 - p1 : p1;
+            }
+            double prod = 1.0;
+            for (int a = 0; a < k; ++a) prod *= ufalse[a];
+            u_acc += prod;
+            for (int a = 0; a < k; ++a) {
+                double cav = 1.0;
+                for (int b = 0; b < k; ++b) if (b != a) cav *= ufalse[b];
+                if (pos[a]) gp1[var[a]] -= cav; else gp0[var[a]] -= cav;
+            }
+        }
+        double s_acc = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            double x = h[(size_t)i * R + r];
+            double l1 = log_sigmoid(x), l0 = log_sigmoid(-x);
+            double p1 = exp(l1), p0 = exp(l0);
+            s_acc += -(p1 * l1 + p0 * l0);
+            if (g) {
+                double a1 = gp1[i] + (l1 + 1.0) / beta;
+                double a0 = gp0[i] + (l0 + 1.0) / beta;
+                g[(size_t)i * R + r] = (a1 - a0) * exp(l1 + l0);
+            }
+        }
+        if (U) U[r] = u_acc;
+        if (S) S[r] = s_acc;
+    }
+    free(var); free(pos); free(ufalse); free(gp1); free(gp0);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adam (Kingma & Ba), PyTorch semantics: n_step counts from 1.              */
+/* ------------------------------------------------------------------------- */
+void orc_adam(int64_t count, const double* g_in, double* h, double* m1, double* m2,
+              double lr, double b1, double b2, double eps, double wd, int64_t n_step)
+{
+    double bc1 = 1.0 - pow(b1, (double)n_step);
+    double bc2 = 1.0 - pow(b2, (double)n_step);
+    for (int64_t k = 0; k < count; ++k) {
+        double g = g_in[k] + wd * h[k];
+        m1[k] = b1 * m1[k] + (1.0 - b1) * g;
+        m2[k] = b2 * m2[k] + (1.0 - b2) * g * g;
+        double mhat = m1[k] / bc1;
+        double vhat = m2[k] / bc2;
+        h[k] -= lr * mhat / (sqrt(vhat) + eps);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Read-out (Results, "Free-Energy Machine": argmax of each replica's         */
+/* marginals, then the replica of lowest energy).                             */
+/* ------------------------------------------------------------------------- */
+
+/* sigma[r][i] = argmax_s P_i(s) with ties to the lowest state index.  For
+ * q == 1 (one logit) the two states are 0 (P = 1 - sigmoid(h)) and 1
+ * (P = sigmoid(h)), so sigma = 1 iff h > 0. */
+void orc_round(int32_t n, int32_t R, int32_t q, const double* h, int32_t* sigma)
+{
+    for (int32_t r = 0; r < R; ++r)
+        for (int32_t i = 0; i < n; ++i) {
+            if (q == 1) {
+                sigma[(size_t)r * n + i] = h[(size_t)i * R + r] > 0.0 ? 1 : 0;
+            } else {
+                const double* hi = h + ((size_t)i * R + r) * q;
+                int32_t best = 0;
+                for (int32_t s = 1; s < q; ++s) if (hi[s] > hi[best]) best = s;
+                sigma[(size_t)r * n + i] = best;
+            }
+        }
+}
+
+/* Cut value sum over undirected edges of W_ij [sigma_i != sigma_j] (each edge
+ * once, the listing's cut(W, s)/2).  Works for any number of states. */
+void orc_cut(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev, const double* w,
+             int32_t R, const int32_t* sigma, double* cut)
+{
+    for (int32_t r = 0; r < R; ++r) {
+        const int32_t* sg = sigma + (size_t)r * n;
+        double c = 0.0;
+        for (int64_t e = 0; e < ne; ++e)
+            if (sg[eu[e]] != sg[ev[e]]) c += w[e];
+        cut[r] = c;
+    }
+}
+
+/* Group sizes |Pi_s| = #{i : sigma_i = s} per replica, [R][q]. */
+void orc_group_sizes(int32_t n, int32_t q, int32_t R, const int32_t* sigma, int64_t* sizes)
+{
+    for (int32_t r = 0; r < R; ++r) {
+        for (int32_t s = 0; s < q; ++s) sizes[(size_t)r * q + s] = 0;
+        for (int32_t i = 0; i < n; ++i) sizes[(size_t)r * q + sigma[(size_t)r * n + i]] += 1;
+    }
+}
+
+/* Number of unsatisfied clauses (every literal false) per replica; sigma is
+ * 0/1 per variable.  A tautological clause is always satisfied. */
+void orc_unsat(int32_t n, int64_t M, const int64_t* off, const int32_t* lits, int32_t R,
+               const int32_t* sigma, int64_t* unsat)
+{
+    for (int32_t r = 0; r < R; ++r) {
+        const int32_t* sg = sigma + (size_t)r * n;
+        int64_t c = 0;
+        for (int64_t m = 0; m < M; ++m) {
+            int sat = 0;
+            for (int64_t a = off[m]; a < off[m + 1]; ++a) {
+                int32_t L = lits[a];
+                int32_t x = (L > 0 ? L : -L) - 1;
+                if ((L > 0 && sg[x] == 1) || (L < 0 && sg[x] == 0)) { sat = 1; break; }
+            }
+            if (!sat) ++c;
+        }
+        unsat[r] = c;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* The annealing loop (Methods listing and Fig. 2 workflow): for each step    */
+/* t, beta = beta(t), gradient of F at h(t), Adam update with step count     */
+/* t+1.  kind 0 = MaxCut, 1 = bMinCut, 2 = Max-k-SAT.  Runs steps t0 ..      */
+/* t0+n_steps-1 of a T-step schedule.  Optional histories (NULL to skip):    */
+/* g_hist [n_steps][vals], U_hist/S_hist [n_steps][R].                        */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t kind, n, q, R, T, sched, lam_ramp;
+    int64_t ne;             /* edges (graphs) or clauses (SAT) */
+    const int32_t* eu;      /* graphs */
+    const int32_t* ev;
+    const double* w;
+    const int64_t* off;     /* SAT */
+    const int32_t* lits;
+    double beta_min, beta_max, lam, lr, b1, b2, eps, wd;
+} orc_problem;
+
+int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, double* m1,
+            double* m2, double* g_hist, double* U_hist, double* S_hist)
+{
+    int32_t Q = pb->kind == 1 ? pb->q : 1;
+    size_t vals = (size_t)pb->n * (size_t)pb->R * (size_t)Q;
+    double* g = (double*)malloc(sizeof(double) * vals);
+    if (!g) return -2;
+    for (int32_t k = 0; k < n_steps; ++k) {
+        int32_t t = t0 + k;
+        double beta = orc_beta(pb->sched, pb->beta_min, pb->beta_max, pb->T, t);
+        double* U = U_hist ? U_hist + (size_t)k * pb->R : NULL;
+        double* S = S_hist ? S_hist + (size_t)k * pb->R : NULL;
+        int rc;
+        if (pb->kind == 0)
+            rc = orc_maxcut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->R, h, beta, g, U, S);
+        else if (pb->kind == 1)
+            rc = orc_bmincut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->q,
+                                  orc_lambda(pb->lam_ramp, pb->lam, pb->T, t), pb->R, h, beta, g, U, S);
+        else
+            rc = orc_maxsat_grad(pb->n, pb->ne, pb->off, pb->lits, pb->R, h, beta, g, U, S);
+        if (rc) { free(g); return rc; }
+        if (g_hist) memcpy(g_hist + (size_t)k * vals, g, sizeof(double) * vals);
+        orc_adam((int64_t)vals, g, h, m1, m2, pb->lr, pb->b1, pb->b2, pb->eps, pb->wd, (int64_t)t + 1);
+    }
+    free(g);
+    return 0;
+}
