@@ -1,0 +1,226 @@
+/*
+ * fem.h -- C ABI of the MI355X (gfx950) Free-Energy Machine hot path.
+ *
+ * The Free-Energy Machine (FEM; Shen et al., arXiv 2412.09285) minimises,
+ * for R independent replicas at once, the variational mean-field free energy
+ *     F = U_MF - S_MF / beta
+ * (supplementary "Derivation of variational mean-field free energy
+ * formulations") by gradient steps with Adam on the fields h while beta is
+ * annealed upwards (Methods, "Different annealing schedules"), then rounds
+ * every replica to a configuration and keeps the best one (Results,
+ * "Free-Energy Machine", the two read-out equations).
+ *
+ * Conventions (fixed for every call):
+ *  - Ids are 0-based.  Graphs are given as undirected edge lists, each edge
+ *    {u,v} once; energies sum over ordered pairs (each edge both ways), which
+ *    is the convention under which the paper's explicit gradients are the
+ *    derivatives of F.  Reported integer cuts count each edge once.
+ *  - MaxCut and Max-k-SAT carry one logit per variable (P = sigmoid(h), the
+ *    paper's q = 2 reduction); balanced min-cut carries q logits per node
+ *    (softmax).  Q below is 1 or q accordingly.
+ *  - Field-shaped device/host buffers are float32, node-row and replica
+ *    contiguous: h[n][R] (Q = 1) or h[n][R][q], state index fastest.
+ *  - Configurations sigma are int32 [R][n] (replica-major) with states
+ *    0..q-1; for one-logit problems sigma_i = 1 iff h_i > 0 (ties to 0).
+ *  - For a batch of B instances (fem_batch_create) per-instance outputs are
+ *    laid out [B][R] and node ids run over the concatenation of the parts.
+ *
+ * Ownership: host arrays passed in are borrowed for the duration of the call
+ * (copied).  Problems and solvers own their device memory.  A pointer flagged
+ * on_device is caller-owned device memory on the solver's device, accessed
+ * only inside the call, ordered on the solver's stream.
+ *
+ * Errors: every call returns a fem_status; nothing throws, aborts or exits.
+ * The text of the last failure on the calling thread is fem_last_error().
+ * Kernels run asynchronously: fem_step / fem_run only enqueue work, and a
+ * failure inside a kernel surfaces at the next call that synchronises
+ * (fem_sync and every getter).  A solver is not thread-safe; distinct
+ * solvers may run concurrently on distinct streams.
+ */
+#ifndef FEM_H
+#define FEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FEM_OK = 0,
+    FEM_E_INVAL = -1,        /* malformed argument or input (message says which) */
+    FEM_E_NOMEM = -2,        /* host or device allocation failed */
+    FEM_E_HIP = -3,          /* HIP runtime error (message holds hipGetErrorString) */
+    FEM_E_STATE = -4,        /* call not valid in the object's current state */
+    FEM_E_NUMERIC = -5,      /* a non-finite energy or field was detected */
+    FEM_E_UNSUPPORTED = -6   /* valid request outside what this build supports */
+} fem_status;
+
+enum { FEM_MAXCUT = 0, FEM_BMINCUT = 1, FEM_MAXSAT = 2 };
+/* beta schedules: linear in beta; exponential (Methods); inverse-proportional,
+ * i.e. linear in temperature (Methods).  All give beta(0) = beta_min and
+ * beta(steps-1) = beta_max. */
+enum { FEM_SCHED_LINEAR = 0, FEM_SCHED_EXP = 1, FEM_SCHED_INVPROP = 2 };
+/* storage type of the marginal copy that neighbours gather */
+enum { FEM_F32 = 0, FEM_BF16 = 1 };
+
+const char* fem_status_str(int status);
+const char* fem_last_error(void);
+/* ABI version, bumped on any incompatible change of this header. */
+int32_t fem_abi_version(void);
+
+typedef struct fem_problem fem_problem;   /* immutable, device resident */
+typedef struct fem_solver fem_solver;     /* R replicas: h, Adam moments, marginals, t */
+
+/* ---------------------------------------------------------------- problems */
+
+/* MaxCut (Results, "Applications to the Maximum-Cut problem"):
+ * E(sigma) = -sum_{(i,j) in E} W_ij [1 - delta(sigma_i, sigma_j)].
+ * u, v: n_edges endpoints (host, 0 <= u,v < n, u != v, no duplicate pair);
+ * w: host weights or NULL for all +1.  Self-loops, duplicate edges,
+ * out-of-range ids, non-finite weights and n < 1 give FEM_E_INVAL. */
+fem_status fem_maxcut_create(int device, int32_t n, int64_t n_edges, const int32_t* u,
+                             const int32_t* v, const float* w, fem_problem** out);
+
+/* q-way balanced min-cut (Results, the bMinCut energy with the soft balance
+ * term lambda * sum_i sum_{j != i} delta(sigma_i, sigma_j)).  Same edge rules
+ * as MaxCut; weights must be > 0.  q must be one of 2, 4, 8, 16, 32 (other
+ * q >= 2 give FEM_E_UNSUPPORTED).  lambda is a solver parameter. */
+fem_status fem_bmincut_create(int device, int32_t n, int64_t n_edges, const int32_t* u,
+                              const int32_t* v, const float* w, int32_t q, fem_problem** out);
+
+/* Max-k-SAT (Results, "Application to the Max k-SAT problem"): energy = number
+ * of unsatisfied clauses.  DIMACS-style literals +(x+1) / -(x+1) on host;
+ * clause_off has n_clauses+1 nondecreasing entries starting at 0.  A repeated
+ * literal counts once; a clause holding x and not-x is always satisfied and is
+ * dropped; an empty clause, a zero literal or an out-of-range variable gives
+ * FEM_E_INVAL; a clause of more than 4 distinct variables gives
+ * FEM_E_UNSUPPORTED. */
+fem_status fem_maxsat_create(int device, int32_t n_vars, int64_t n_clauses,
+                             const int64_t* clause_off, const int32_t* lits, fem_problem** out);
+
+/* Block-diagonal union of n problems of one kind (and one q) on one device:
+ * one solver then runs every instance in the same launches, with per-instance
+ * energies, read-out and best replica.  The parts stay owned by the caller and
+ * may be destroyed afterwards. */
+fem_status fem_batch_create(int32_t n, fem_problem* const* parts, fem_problem** out);
+
+/* kind, total nodes/variables, q (2 for one-logit kinds), directed adjacency
+ * entries (2 x edges) or literal incidences, number of instances.  Any output
+ * pointer may be NULL. */
+fem_status fem_problem_info(const fem_problem* p, int32_t* kind, int32_t* n, int32_t* q,
+                            int64_t* nnz, int32_t* n_instances);
+/* node offsets of the instances, n_instances+1 entries (host). */
+fem_status fem_problem_instance_offsets(const fem_problem* p, int32_t* offsets);
+void fem_problem_destroy(fem_problem* p);
+
+/* ------------------------------------------------------------------ solver */
+typedef struct {
+    int32_t replicas;          /* R >= 1 */
+    int32_t steps;             /* annealing length T >= 1 */
+    int32_t schedule;          /* FEM_SCHED_* */
+    double beta_min, beta_max; /* 0 < beta_min <= beta_max */
+    double lr, adam_b1, adam_b2, adam_eps, weight_decay;   /* torch.optim.Adam semantics */
+    double lambda;             /* bMinCut balance weight (lambda_max when ramped) */
+    int32_t lambda_ramp;       /* 0: constant; 1: lambda(t) = lambda * t / (T-1) */
+    int32_t marginal_dtype;    /* FEM_F32 | FEM_BF16 */
+    int32_t energy_every;      /* per-replica U, S, F every k-th step (0 = never) */
+    int32_t record_energies;   /* keep the energies of every evaluated step */
+    int32_t eval_every;        /* anytime read-out every k steps (0 = only on request) */
+    int32_t keep_grad;         /* keep the last gradient for fem_last_grad */
+} fem_params;
+
+/* Adam 0.9 / 0.999 / 1e-8, lr 0.1, no weight decay, linear beta 0.01 -> 5,
+ * R = 16, T = 500, F32 marginals, energies every step, no recording. */
+void fem_params_default(fem_params* p);
+
+/* hip_stream: a hipStream_t on the problem's device (NULL = the null stream). */
+fem_status fem_solver_create(const fem_problem* p, const fem_params* prm, void* hip_stream,
+                             fem_solver** out);
+void fem_solver_destroy(fem_solver* s);
+
+/* Initial fields h0 ([n][R] or [n][R][q] float32, host or device).  Resets the
+ * Adam moments to zero, the step counter t to 0, the anytime bests, and
+ * recomputes the marginal copy. */
+fem_status fem_set_fields(fem_solver* s, const float* h, int on_device);
+
+/* Enqueue n_steps annealing steps t -> t+1 (t + n_steps <= T).  Step t uses
+ * beta(t), lambda(t) and Adam step count t+1; its gradient and energies are
+ * evaluated at h(t). */
+fem_status fem_step(fem_solver* s, int32_t n_steps);
+/* Enqueue the remaining steps up to T as one captured HIP graph (replayed on
+ * later calls from the same t). */
+fem_status fem_run(fem_solver* s);
+/* Enqueue steps [t, t_end) as one captured HIP graph. */
+fem_status fem_run_until(fem_solver* s, int32_t t_end);
+/* Capture (and instantiate) the graph of steps [t, t_end) without running it,
+ * so that a later fem_run_until(s, t_end) from the same t only launches it.
+ * Needs a non-null stream. */
+fem_status fem_capture(fem_solver* s, int32_t t_end);
+fem_status fem_sync(fem_solver* s);
+/* current step counter t */
+fem_status fem_get_step(const fem_solver* s, int32_t* t);
+
+fem_status fem_get_fields(fem_solver* s, float* h, int on_device);
+/* gradient dF/dh of the last step (needs keep_grad), layout of h. */
+fem_status fem_last_grad(fem_solver* s, float* g, int on_device);
+/* U, S, F of the last evaluated step, [B][R] each (any may be NULL).  Gives
+ * FEM_E_STATE if no step evaluated energies, FEM_E_NUMERIC if a value is not
+ * finite. */
+fem_status fem_energies(fem_solver* s, double* U, double* S, double* F);
+/* energies recorded at steps t0, t0+k, ... (record_energies), count entries of
+ * [B][R] each. */
+fem_status fem_energy_history(fem_solver* s, int32_t first, int32_t count, double* U,
+                              double* S, double* F);
+
+/* sigma = argmax of the current fields (host [R][n]). */
+fem_status fem_round(fem_solver* s, int32_t* sigma);
+/* Integer evaluation of host configurations sigma [R][n]: value[B][R] is the
+ * cut (MaxCut, bMinCut; each edge once) or the number of unsatisfied clauses
+ * (Max-k-SAT); sizes[B][R][q] the group sizes for bMinCut (may be NULL).
+ * Exact for integral weights (|total| < 2^53). */
+fem_status fem_eval_int(const fem_problem* p, int32_t R, const int32_t* sigma, int64_t* value,
+                        int64_t* sizes);
+/* Round the current fields, evaluate, and return per instance the best
+ * replica (max cut; min unsat; min 2*cut + lambda*sum_s |Pi_s|(|Pi_s|-1) for
+ * bMinCut; ties to the lowest replica index), its value, and (if sigma is not
+ * NULL) its configuration as int32 over all n nodes.  replica, value: [B]. */
+fem_status fem_best(fem_solver* s, int32_t* replica, int64_t* value, int32_t* sigma);
+/* Best value seen by the anytime read-out so far, [B][R] (eval_every > 0):
+ * the cut (MaxCut; -inf before the first read-out), the number of unsatisfied
+ * clauses (Max-k-SAT) or the integer energy 2*cut + lambda*sum_s
+ * |Pi_s|(|Pi_s|-1) (bMinCut); +inf before the first read-out otherwise. */
+fem_status fem_anytime_best(fem_solver* s, double* value);
+
+/* Checkpoint: bytes needed / write / restore (h, Adam moments, t).  Resuming
+ * from a checkpoint reproduces an uninterrupted run bit for bit. */
+fem_status fem_state_size(const fem_solver* s, size_t* bytes);
+fem_status fem_get_state(fem_solver* s, void* buf, size_t bytes);
+fem_status fem_set_state(fem_solver* s, const void* buf, size_t bytes);
+
+/* --------------------------------------------------------------- tiling */
+/* Launch shape of the step kernels.  vec: values per lane along the replica
+ * axis (1, 2, 4, 8; Potts uses q); waves: wavefronts per workgroup (1..16);
+ * rows: rows per team per tile (1..64).  All shapes give bit-identical fields. */
+typedef struct {
+    int32_t vec, waves, rows;
+} fem_tile;
+fem_status fem_get_tile(const fem_solver* s, fem_tile* t);
+fem_status fem_set_tile(fem_solver* s, const fem_tile* t);
+/* Autotune: time every valid shape for trial_steps steps (state is restored
+ * afterwards), keep the fastest, and cache it on disk under the key (kind, n,
+ * nnz, R, q, dtype) in $FEM_TUNE_CACHE (default ~/.cache/femx/tune.txt).
+ * use_cache = 1 returns a cached choice without timing. */
+fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_tile* chosen);
+
+/* Average duration in milliseconds of the step kernel over the last
+ * fem_step/fem_run call, measured with HIP events on the solver's stream
+ * (0 if not measured).  Enabled by fem_profile(s, 1). */
+fem_status fem_profile(fem_solver* s, int32_t on);
+fem_status fem_profile_result(fem_solver* s, double* step_kernel_ms, int32_t* n_kernels);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEM_H */

@@ -1,0 +1,1504 @@
+// Host runtime and C ABI of the FEM library: problem builders (CSR and
+// Max-k-SAT incidence records, block-diagonal batches), the solver (state,
+// schedules, step sequencing, HIP-graph capture), read-out, checkpoints and
+// the tile autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cerrno>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <new>
+#include <string>
+#include <sys/stat.h>
+#include <utility>
+#include <vector>
+
+#include "../../include/fem.h"
+#include "fem_internal.h"
+
+using namespace fem;
+
+// ------------------------------------------------------------------ errors --
+static thread_local std::string g_err;
+
+static fem_status fail(fem_status st, const char* fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            if (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation)              \
+                return fail(FEM_E_NOMEM, "%s: %s", #expr, hipGetErrorString(e_));         \
+            return fail(FEM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));               \
+        }                                                                                 \
+    } while (0)
+
+#define STCHK(expr)                      \
+    do {                                 \
+        fem_status s_ = (expr);          \
+        if (s_ != FEM_OK) return s_;     \
+    } while (0)
+
+template <typename T>
+static hipError_t dalloc(T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) return hipSuccess;
+    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+template <typename T>
+static void dfree(T*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+// ---------------------------------------------------------------- problems --
+struct fem_problem {
+    Problem p;
+};
+
+static void free_problem_device(Problem& p)
+{
+    dfree(p.row_off);
+    dfree(p.adj);
+    dfree(p.inc2);
+    dfree(p.inc4);
+    dfree(p.wdeg);
+}
+
+static fem_status upload_problem(Problem& p)
+{
+    HIPCHK(hipSetDevice(p.device));
+    HIPCHK(dalloc(&p.row_off, p.h_row_off.size()));
+    HIPCHK(hipMemcpy(p.row_off, p.h_row_off.data(), p.h_row_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (!p.h_adj.empty()) {
+        HIPCHK(dalloc(&p.adj, p.h_adj.size()));
+        HIPCHK(hipMemcpy(p.adj, p.h_adj.data(), p.h_adj.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
+    if (!p.h_inc2.empty()) {
+        HIPCHK(dalloc(&p.inc2, p.h_inc2.size()));
+        HIPCHK(hipMemcpy(p.inc2, p.h_inc2.data(), p.h_inc2.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
+    if (!p.h_inc4.empty()) {
+        HIPCHK(dalloc(&p.inc4, p.h_inc4.size()));
+        HIPCHK(hipMemcpy(p.inc4, p.h_inc4.data(), p.h_inc4.size() * sizeof(int4), hipMemcpyHostToDevice));
+    }
+    if (!p.h_wdeg.empty()) {
+        HIPCHK(dalloc(&p.wdeg, p.h_wdeg.size()));
+        HIPCHK(hipMemcpy(p.wdeg, p.h_wdeg.data(), p.h_wdeg.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return FEM_OK;
+}
+
+static fem_status check_device(int device)
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return fail(FEM_E_HIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (device < 0 || device >= count) return fail(FEM_E_INVAL, "device %d out of range (%d devices)", device, count);
+    return FEM_OK;
+}
+
+// Symmetric CSR of an undirected edge list: each edge {u,v} appears in row u
+// and row v; columns sorted within a row.
+static fem_status build_graph(int kind, int device, int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v,
+                              const float* w, int32_t q, fem_problem** out)
+{
+    if (!out) return fail(FEM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1) return fail(FEM_E_INVAL, "n must be >= 1 (got %d)", n);
+    if (n_edges < 0) return fail(FEM_E_INVAL, "n_edges must be >= 0");
+    if (n_edges > 0 && (!u || !v)) return fail(FEM_E_INVAL, "u and v must not be NULL");
+    if (2 * n_edges > (int64_t)INT32_MAX * 8) return fail(FEM_E_UNSUPPORTED, "too many edges");
+    std::vector<uint64_t> keys((size_t)n_edges);
+    double wtot = 0.0;
+    bool integral = true;
+    for (int64_t e = 0; e < n_edges; ++e) {
+        const int32_t a = u[e], b = v[e];
+        if (a < 0 || a >= n || b < 0 || b >= n)
+            return fail(FEM_E_INVAL, "edge %lld: endpoint out of range [0, %d)", (long long)e, n);
+        if (a == b) return fail(FEM_E_INVAL, "edge %lld: self-loop on node %d", (long long)e, a);
+        const float we = w ? w[e] : 1.0f;
+        if (!std::isfinite(we)) return fail(FEM_E_INVAL, "edge %lld: weight is not finite", (long long)e);
+        if (kind == KIND_BMINCUT && !(we > 0.0f))
+            return fail(FEM_E_INVAL, "edge %lld: balanced min-cut weights must be > 0", (long long)e);
+        if (we != std::rint(we)) integral = false;
+        wtot += we;
+        const uint64_t lo = (uint64_t)std::min(a, b), hi = (uint64_t)std::max(a, b);
+        keys[(size_t)e] = (lo << 32) | hi;
+    }
+    {
+        std::vector<uint64_t> srt(keys);
+        std::sort(srt.begin(), srt.end());
+        for (size_t k = 1; k < srt.size(); ++k)
+            if (srt[k] == srt[k - 1])
+                return fail(FEM_E_INVAL, "duplicate edge {%u, %u}", (unsigned)(srt[k] >> 32),
+                            (unsigned)(srt[k] & 0xffffffffu));
+    }
+    STCHK(check_device(device));
+    auto* fp = new (std::nothrow) fem_problem;
+    if (!fp) return fail(FEM_E_NOMEM, "host allocation failed");
+    Problem& p = fp->p;
+    p.device = device;
+    p.kind = kind;
+    p.n = n;
+    p.q = (kind == KIND_BMINCUT) ? q : 2;
+    p.nnz = 2 * n_edges;
+    p.integral = integral;
+    p.inst_off = {0, n};
+    p.inst_wtot = {wtot};
+    std::vector<int64_t>& ro = p.h_row_off;
+    ro.assign((size_t)n + 1, 0);
+    for (int64_t e = 0; e < n_edges; ++e) {
+        ro[(size_t)u[e] + 1]++;
+        ro[(size_t)v[e] + 1]++;
+    }
+    for (int32_t i = 0; i < n; ++i) ro[(size_t)i + 1] += ro[(size_t)i];
+    std::vector<int64_t> fill(ro.begin(), ro.end() - 1);
+    p.h_adj.resize((size_t)p.nnz);
+    for (int64_t e = 0; e < n_edges; ++e) {
+        const float we = w ? w[e] : 1.0f;
+        int bits;
+        std::memcpy(&bits, &we, 4);
+        p.h_adj[(size_t)fill[(size_t)u[e]]++] = make_int2(v[e], bits);
+        p.h_adj[(size_t)fill[(size_t)v[e]]++] = make_int2(u[e], bits);
+    }
+    for (int32_t i = 0; i < n; ++i)
+        std::sort(p.h_adj.begin() + ro[(size_t)i], p.h_adj.begin() + ro[(size_t)i + 1],
+                  [](const int2& a, const int2& b) { return a.x < b.x; });
+    if (kind == KIND_BMINCUT) {
+        p.h_wdeg.assign((size_t)n, 0.0f);
+        for (int32_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t k = ro[(size_t)i]; k < ro[(size_t)i + 1]; ++k) {
+                float we;
+                std::memcpy(&we, &p.h_adj[(size_t)k].y, 4);
+                s += we;
+            }
+            p.h_wdeg[(size_t)i] = (float)s;
+        }
+    }
+    fem_status st = upload_problem(p);
+    if (st != FEM_OK) {
+        free_problem_device(p);
+        delete fp;
+        return st;
+    }
+    *out = fp;
+    return FEM_OK;
+}
+
+static inline uint32_t sat_slot(int32_t var, bool pos) { return (uint32_t)var | (pos ? SAT_POS : 0u); }
+
+static fem_status build_sat(int device, int32_t n_vars, int64_t n_clauses, const int64_t* off, const int32_t* lits,
+                            fem_problem** out)
+{
+    if (!out) return fail(FEM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n_vars < 1) return fail(FEM_E_INVAL, "n_vars must be >= 1 (got %d)", n_vars);
+    if (n_vars >= (int32_t)SAT_NONE) return fail(FEM_E_UNSUPPORTED, "too many variables");
+    if (n_clauses < 0) return fail(FEM_E_INVAL, "n_clauses must be >= 0");
+    if (!off) return fail(FEM_E_INVAL, "clause_off must not be NULL");
+    if (off[0] != 0) return fail(FEM_E_INVAL, "clause_off[0] must be 0");
+    for (int64_t m = 0; m < n_clauses; ++m)
+        if (off[m + 1] < off[m]) return fail(FEM_E_INVAL, "clause_off must be nondecreasing (clause %lld)", (long long)m);
+    if (off[n_clauses] > 0 && !lits) return fail(FEM_E_INVAL, "lits must not be NULL");
+    // canonical clauses: distinct variables, tautologies dropped
+    struct Cl {
+        int32_t var[4];
+        bool pos[4];
+        int k;
+    };
+    std::vector<Cl> cls;
+    cls.reserve((size_t)n_clauses);
+    int kmax = 0;
+    for (int64_t m = 0; m < n_clauses; ++m) {
+        if (off[m + 1] == off[m]) return fail(FEM_E_INVAL, "clause %lld is empty", (long long)m);
+        Cl c;
+        c.k = 0;
+        bool taut = false;
+        for (int64_t a = off[m]; a < off[m + 1]; ++a) {
+            const int32_t L = lits[a];
+            if (L == 0 || L > n_vars || L < -n_vars)
+                return fail(FEM_E_INVAL, "clause %lld: literal %d out of range", (long long)m, L);
+            const int32_t x = (L > 0 ? L : -L) - 1;
+            const bool ps = L > 0;
+            bool seen = false;
+            for (int b = 0; b < c.k; ++b)
+                if (c.var[b] == x) {
+                    seen = true;
+                    if (c.pos[b] != ps) taut = true;
+                }
+            if (!seen && !taut) {
+                if (c.k == 4) return fail(FEM_E_UNSUPPORTED, "clause %lld has more than 4 distinct variables", (long long)m);
+                c.var[c.k] = x;
+                c.pos[c.k] = ps;
+                ++c.k;
+            }
+        }
+        if (taut) continue;
+        kmax = std::max(kmax, c.k);
+        cls.push_back(c);
+    }
+    STCHK(check_device(device));
+    auto* fp = new (std::nothrow) fem_problem;
+    if (!fp) return fail(FEM_E_NOMEM, "host allocation failed");
+    Problem& p = fp->p;
+    p.device = device;
+    p.kind = KIND_MAXSAT;
+    p.n = n_vars;
+    p.q = 2;
+    p.n_clauses = (int64_t)cls.size();
+    p.sat_width = kmax <= 3 ? 2 : 3;
+    p.inst_off = {0, n_vars};
+    p.inst_wtot = {0.0};
+    std::vector<int64_t>& ro = p.h_row_off;
+    ro.assign((size_t)n_vars + 1, 0);
+    for (const Cl& c : cls)
+        for (int a = 0; a < c.k; ++a) ro[(size_t)c.var[a] + 1]++;
+    for (int32_t i = 0; i < n_vars; ++i) ro[(size_t)i + 1] += ro[(size_t)i];
+    p.nnz = ro[(size_t)n_vars];
+    std::vector<int64_t> fill(ro.begin(), ro.end() - 1);
+    if (p.sat_width == 2) p.h_inc2.resize((size_t)p.nnz);
+    else p.h_inc4.resize((size_t)p.nnz);
+    for (const Cl& c : cls) {
+        for (int a = 0; a < c.k; ++a) {
+            uint32_t slot[3] = {SAT_NONE, SAT_NONE, SAT_NONE};
+            int s = 0;
+            for (int b = 0; b < c.k; ++b)
+                if (b != a) slot[s++] = sat_slot(c.var[b], c.pos[b]);
+            const bool owner = (a == 0);
+            const size_t at = (size_t)fill[(size_t)c.var[a]]++;
+            if (p.sat_width == 2) {
+                const uint32_t x = slot[0] | (c.pos[a] ? SAT_FLAG : 0u);
+                const uint32_t y = slot[1] | (owner ? SAT_FLAG : 0u);
+                p.h_inc2[at] = make_int2((int)x, (int)y);
+            } else {
+                p.h_inc4[at] = make_int4((int)slot[0], (int)slot[1], (int)slot[2], (c.pos[a] ? 1 : 0) | (owner ? 2 : 0));
+            }
+        }
+    }
+    fem_status st = upload_problem(p);
+    if (st != FEM_OK) {
+        free_problem_device(p);
+        delete fp;
+        return st;
+    }
+    *out = fp;
+    return FEM_OK;
+}
+
+// ------------------------------------------------------------------ solver --
+struct fem_solver {
+    const Problem* prob = nullptr;
+    fem_params prm{};
+    hipStream_t stream = nullptr;
+    int kind = 0, dtype = 0;
+    int32_t n = 0, R = 0, Q = 1, q = 2, n_inst = 1;
+    size_t vals = 0;
+    int32_t t = 0;
+    bool fields_set = false;
+    // state
+    float* h = nullptr;
+    float* m1 = nullptr;
+    float* m2 = nullptr;
+    float* grad = nullptr;
+    void* marg[2] = {nullptr, nullptr};
+    // tiling
+    TileShape shape;
+    LaunchGeom geo{};
+    LaunchGeom egeo{};   // evaluation kernels: one replica per lane
+    int lanes_log2 = 0;
+    Tile* d_tiles = nullptr;
+    int n_tiles = 0, n_chunks = 0;
+    int32_t* d_chunk_off = nullptr;
+    int32_t* d_inst_chunk_off = nullptr;
+    // energies
+    int NE = 2;
+    double* epart = nullptr;
+    double* etmp = nullptr;
+    double* eraw = nullptr;
+    double* eout = nullptr;    // last energies [inst][3][R]
+    double* ehist = nullptr;   // [records][inst][3][R]
+    int n_records = 0;
+    int last_energy_step = -1;
+    double* d_wtot = nullptr;
+    // bMinCut column sums
+    long long* cpart = nullptr;
+    long long* ctmp = nullptr;
+    long long* cfix = nullptr;
+    double* csum = nullptr;
+    float* ctil = nullptr;
+    // evaluation
+    uint8_t* sigma = nullptr;
+    double* vpart = nullptr;
+    double* vtmp = nullptr;
+    double* vout = nullptr;
+    int* spart = nullptr;
+    int* stmp = nullptr;
+    int* sint = nullptr;
+    long long* sout = nullptr;
+    double* best = nullptr;
+    // schedules
+    std::vector<double> beta, lam;
+    // graphs keyed by (t0, t1)
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    // profiling of the step kernel
+    bool profile = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    size_t prof_used = 0;
+    bool capturing = false;
+};
+
+static int pow2ceil(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+static LaunchGeom make_geom(int per_lane, int R, int waves)
+{
+    LaunchGeom g{};
+    const int need = (R + per_lane - 1) / per_lane;
+    g.lanes = std::min(64, pow2ceil(need));
+    g.nseg = (need + g.lanes - 1) / g.lanes;
+    g.teams_per_block = waves * (64 / g.lanes);
+    return g;
+}
+
+// workgroup LDS used by the reductions: waves * lanes * values-per-lane * 8 B
+static const size_t LDS_LIMIT = 64 * 1024;
+
+static bool valid_shape(const fem_solver* s, const TileShape& t)
+{
+    if (t.waves < 1 || t.waves > 16 || t.rows < 1 || t.rows > 64) return false;
+    const int per_lane = (s->kind == KIND_BMINCUT) ? 1 : t.vec;
+    if (s->kind != KIND_BMINCUT) {
+        if (t.vec != 1 && t.vec != 2 && t.vec != 4 && t.vec != 8) return false;
+        if (s->R % t.vec != 0) return false;
+    }
+    const LaunchGeom g = make_geom(per_lane, s->R, t.waves);
+    const LaunchGeom ge = make_geom(1, s->R, t.waves);
+    const int k_step = (s->kind == KIND_BMINCUT) ? std::max(s->q, 3) : 2 * t.vec;
+    const int k_eval = (s->kind == KIND_BMINCUT) ? s->q : 1;
+    if ((size_t)t.waves * g.lanes * k_step * 8 > LDS_LIMIT) return false;
+    if ((size_t)t.waves * ge.lanes * k_eval * 8 > LDS_LIMIT) return false;
+    return true;
+}
+
+static void free_tiling(fem_solver* s)
+{
+    dfree(s->d_tiles);
+    dfree(s->d_chunk_off);
+    dfree(s->d_inst_chunk_off);
+    dfree(s->epart);
+    dfree(s->etmp);
+    dfree(s->cpart);
+    dfree(s->ctmp);
+    dfree(s->vpart);
+    dfree(s->vtmp);
+    dfree(s->spart);
+    dfree(s->stmp);
+}
+
+static void drop_graphs(fem_solver* s)
+{
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    s->graphs.clear();
+}
+
+// Tiles of tile_rows rows per instance; chunks of <= 64 consecutive tiles of
+// one instance (first reduction stage).  Dispatch order interleaves the tile
+// list so that the tiles a given XCD receives (block b goes to XCD b mod 8)
+// form one contiguous row range.
+static fem_status setup_tiling(fem_solver* s, const TileShape& shape)
+{
+    const Problem& p = *s->prob;
+    free_tiling(s);
+    drop_graphs(s);
+    s->shape = shape;
+    const int per_lane = (s->kind == KIND_BMINCUT) ? 1 : shape.vec;
+    s->geo = make_geom(per_lane, s->R, shape.waves);
+    s->lanes_log2 = 0;
+    while ((1 << s->lanes_log2) < s->geo.lanes) ++s->lanes_log2;
+    const int tile_rows = s->geo.teams_per_block * shape.rows;
+    std::vector<Tile> tiles;
+    std::vector<int32_t> chunk_off{0}, inst_chunk_off{0};
+    for (int b = 0; b < s->n_inst; ++b) {
+        const int32_t r0 = p.inst_off[(size_t)b], r1 = p.inst_off[(size_t)b + 1];
+        int in_chunk = 0;
+        for (int32_t r = r0; r < r1; r += tile_rows) {
+            Tile t;
+            t.inst = b;
+            t.row_begin = r;
+            t.row_end = std::min(r1, r + tile_rows);
+            t.slot = (int32_t)tiles.size();
+            tiles.push_back(t);
+            if (++in_chunk == 64) {
+                chunk_off.push_back((int32_t)tiles.size());
+                in_chunk = 0;
+            }
+        }
+        if (in_chunk) chunk_off.push_back((int32_t)tiles.size());
+        inst_chunk_off.push_back((int32_t)chunk_off.size() - 1);
+    }
+    s->n_tiles = (int)tiles.size();
+    s->n_chunks = (int)chunk_off.size() - 1;
+    // XCD-aware dispatch order: position pos runs on XCD pos % 8; XCD x gets
+    // the contiguous tile range [start_x, start_x + cnt_x), cnt_x differing by
+    // at most one between XCDs, so every position holds exactly one tile.
+    std::vector<Tile> order(tiles.size());
+    {
+        const size_t nt = tiles.size(), X = 8;
+        size_t start[8];
+        size_t acc = 0;
+        for (size_t x = 0; x < X; ++x) {
+            start[x] = acc;
+            acc += nt / X + (x < nt % X ? 1 : 0);
+        }
+        for (size_t pos = 0; pos < nt; ++pos) order[pos] = tiles[start[pos % X] + pos / X];
+    }
+    s->geo.n_tiles = s->n_tiles;
+    s->egeo = make_geom(1, s->R, shape.waves);
+    s->egeo.n_tiles = s->n_tiles;
+    HIPCHK(dalloc(&s->d_tiles, order.size()));
+    HIPCHK(hipMemcpy(s->d_tiles, order.data(), order.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    HIPCHK(dalloc(&s->d_chunk_off, chunk_off.size()));
+    HIPCHK(hipMemcpy(s->d_chunk_off, chunk_off.data(), chunk_off.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(dalloc(&s->d_inst_chunk_off, inst_chunk_off.size()));
+    HIPCHK(hipMemcpy(s->d_inst_chunk_off, inst_chunk_off.data(), inst_chunk_off.size() * 4, hipMemcpyHostToDevice));
+    const size_t R = (size_t)s->R;
+    HIPCHK(dalloc(&s->epart, (size_t)s->n_tiles * s->NE * R));
+    HIPCHK(dalloc(&s->etmp, (size_t)s->n_chunks * s->NE * R));
+    HIPCHK(dalloc(&s->vpart, (size_t)s->n_tiles * R));
+    HIPCHK(dalloc(&s->vtmp, (size_t)s->n_chunks * R));
+    if (s->kind == KIND_BMINCUT) {
+        HIPCHK(dalloc(&s->cpart, (size_t)s->n_tiles * R * s->q));
+        HIPCHK(dalloc(&s->ctmp, (size_t)s->n_chunks * R * s->q));
+        HIPCHK(dalloc(&s->spart, (size_t)s->n_tiles * R * s->q));
+        HIPCHK(dalloc(&s->stmp, (size_t)s->n_chunks * R * s->q));
+    }
+    return FEM_OK;
+}
+
+static double sched_beta(const fem_params& p, int T, int t)
+{
+    const double x = (T > 1) ? (double)t / (double)(T - 1) : 0.0;
+    switch (p.schedule) {
+    case FEM_SCHED_EXP: return std::exp(std::log(p.beta_min) + (std::log(p.beta_max) - std::log(p.beta_min)) * x);
+    case FEM_SCHED_INVPROP: return 1.0 / (1.0 / p.beta_min + (1.0 / p.beta_max - 1.0 / p.beta_min) * x);
+    default: return p.beta_min + (p.beta_max - p.beta_min) * x;
+    }
+}
+
+static StepScalars step_scalars(const fem_solver* s, int t)
+{
+    const fem_params& p = s->prm;
+    const double nstep = (double)t + 1.0;
+    StepScalars sc;
+    sc.inv_beta = (float)(1.0 / s->beta[(size_t)t]);
+    sc.lam = (float)s->lam[(size_t)t];
+    sc.step_size = (float)(p.lr / (1.0 - std::pow(p.adam_b1, nstep)));
+    sc.bc2_sqrt = (float)std::sqrt(1.0 - std::pow(p.adam_b2, nstep));
+    sc.b1 = (float)p.adam_b1;
+    sc.one_m_b1 = (float)(1.0 - p.adam_b1);
+    sc.b2 = (float)p.adam_b2;
+    sc.one_m_b2 = (float)(1.0 - p.adam_b2);
+    sc.eps = (float)p.adam_eps;
+    sc.wd = (float)p.weight_decay;
+    return sc;
+}
+
+static StepArgs base_args(const fem_solver* s)
+{
+    const Problem& p = *s->prob;
+    StepArgs a{};
+    a.row_off = p.row_off;
+    a.adj = p.adj;
+    a.inc2 = p.inc2;
+    a.inc4 = p.inc4;
+    a.wdeg = p.wdeg;
+    a.tiles = s->d_tiles;
+    a.h = s->h;
+    a.m1 = s->m1;
+    a.m2 = s->m2;
+    a.grad = s->prm.keep_grad ? s->grad : nullptr;
+    a.ctil = s->ctil;
+    a.cpart = s->cpart;
+    a.R = s->R;
+    a.q = s->q;
+    a.lanes_log2 = s->lanes_log2;
+    return a;
+}
+
+static bool energy_due(const fem_solver* s, int t) { return s->prm.energy_every > 0 && t % s->prm.energy_every == 0; }
+static bool eval_due(const fem_solver* s, int t_after)
+{
+    return s->prm.eval_every > 0 && (t_after % s->prm.eval_every == 0 || t_after == s->prm.steps);
+}
+
+static double* energy_slot(fem_solver* s, int t)
+{
+    if (s->ehist) return s->ehist + (size_t)(t / s->prm.energy_every) * s->n_inst * 3 * s->R;
+    return s->eout;
+}
+
+// bMinCut: C(s), C~(s) of the marginal copy currently in cpart
+static fem_status finish_colsums(fem_solver* s)
+{
+    HIPCHK(launch_seg_reduce<long long>(s->cpart, s->R * s->q, s->d_chunk_off, s->n_chunks, s->d_inst_chunk_off,
+                                        s->n_inst, s->ctmp, s->cfix, s->stream));
+    HIPCHK(launch_colsum_combine(s->R, s->q, s->n_inst, s->cfix, s->csum, s->ctil, s->stream));
+    return FEM_OK;
+}
+
+// round the current fields, evaluate, update the anytime bests (all on device)
+static fem_status readout_eval(fem_solver* s, const uint8_t* sigma_in, bool update_best)
+{
+    const Problem& p = *s->prob;
+    if (!sigma_in) {
+        HIPCHK(launch_round(s->kind, s->n, s->R, s->q, s->h, s->sigma, s->stream));
+        sigma_in = s->sigma;
+    }
+    HIPCHK(launch_eval(p, s->egeo, s->shape.waves, s->d_tiles, s->R, sigma_in, s->vpart, s->spart, s->stream));
+    HIPCHK(launch_seg_reduce<double>(s->vpart, s->R, s->d_chunk_off, s->n_chunks, s->d_inst_chunk_off, s->n_inst,
+                                     s->vtmp, s->vout, s->stream));
+    if (s->kind == KIND_BMINCUT) {
+        HIPCHK(launch_seg_reduce<int>(s->spart, s->R * s->q, s->d_chunk_off, s->n_chunks, s->d_inst_chunk_off,
+                                      s->n_inst, s->stmp, s->sint, s->stream));
+        HIPCHK(launch_sizes_widen((size_t)s->n_inst * s->R * s->q, s->sint, s->sout, s->stream));
+    }
+    if (update_best)
+        HIPCHK(launch_best_update(s->kind, s->R, s->n_inst, s->q, s->prm.lambda, s->vout, s->sout, s->best,
+                                  s->stream));
+    return FEM_OK;
+}
+
+static fem_status do_step(fem_solver* s)
+{
+    const int t = s->t;
+    StepArgs a = base_args(s);
+    a.marg_cur = s->marg[t & 1];
+    a.marg_nxt = s->marg[(t + 1) & 1];
+    a.sc = step_scalars(s, t);
+    const bool en = energy_due(s, t);
+    a.epart = en ? s->epart : nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s->profile && !s->capturing) {
+        if (s->prof_used == s->prof_events.size()) {
+            hipEvent_t x, y;
+            HIPCHK(hipEventCreate(&x));
+            HIPCHK(hipEventCreate(&y));
+            s->prof_events.emplace_back(x, y);
+        }
+        e0 = s->prof_events[s->prof_used].first;
+        e1 = s->prof_events[s->prof_used].second;
+        ++s->prof_used;
+        HIPCHK(hipEventRecord(e0, s->stream));
+    }
+    HIPCHK(launch_step(s->kind, s->dtype, s->shape.vec, s->geo, s->shape.waves, a, s->stream));
+    if (e1) HIPCHK(hipEventRecord(e1, s->stream));
+    if (en) {
+        double* slot = energy_slot(s, t);
+        HIPCHK(launch_seg_reduce<double>(s->epart, s->NE * s->R, s->d_chunk_off, s->n_chunks, s->d_inst_chunk_off,
+                                         s->n_inst, s->etmp, s->eraw, s->stream));
+        HIPCHK(launch_energy_combine(s->kind, s->R, s->q, s->n_inst, s->eraw, s->d_wtot, s->csum, s->lam[(size_t)t],
+                                     s->beta[(size_t)t], slot, s->stream));
+        s->last_energy_step = t;
+    }
+    if (s->kind == KIND_BMINCUT) STCHK(finish_colsums(s));
+    s->t = t + 1;
+    if (eval_due(s, s->t)) STCHK(readout_eval(s, nullptr, true));
+    return FEM_OK;
+}
+
+static fem_status init_marginals(fem_solver* s)
+{
+    StepArgs a = base_args(s);
+    a.marg_nxt = s->marg[s->t & 1];
+    HIPCHK(launch_init_marginals(s->kind, s->dtype, s->geo, s->shape.waves, a, s->vals, s->stream));
+    if (s->kind == KIND_BMINCUT) STCHK(finish_colsums(s));
+    return FEM_OK;
+}
+
+static fem_status reset_best(fem_solver* s)
+{
+    std::vector<double> inf((size_t)s->n_inst * s->R, std::numeric_limits<double>::infinity());
+    HIPCHK(hipMemcpyAsync(s->best, inf.data(), inf.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return FEM_OK;
+}
+
+static void destroy_solver(fem_solver* s)
+{
+    if (!s) return;
+    if (s->prob) (void)hipSetDevice(s->prob->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graphs(s);
+    for (auto& ev : s->prof_events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    free_tiling(s);
+    dfree(s->h);
+    dfree(s->m1);
+    dfree(s->m2);
+    dfree(s->grad);
+    void* m0 = s->marg[0];
+    void* m1v = s->marg[1];
+    if (m0) (void)hipFree(m0);
+    if (m1v) (void)hipFree(m1v);
+    dfree(s->eraw);
+    dfree(s->eout);
+    dfree(s->ehist);
+    dfree(s->d_wtot);
+    dfree(s->cfix);
+    dfree(s->csum);
+    dfree(s->ctil);
+    dfree(s->sigma);
+    dfree(s->vout);
+    dfree(s->sint);
+    dfree(s->sout);
+    dfree(s->best);
+    delete s;
+}
+
+static TileShape default_shape(int kind, int R)
+{
+    TileShape t;
+    t.waves = 4;
+    t.rows = 4;
+    if (kind == KIND_BMINCUT) {
+        t.vec = 1;
+        return t;
+    }
+    if (R % 4 == 0 && R >= 128) t.vec = 4;
+    else if (R % 2 == 0 && R >= 64) t.vec = 2;
+    else t.vec = 1;
+    return t;
+}
+
+// ================================================================== C ABI ==
+extern "C" {
+
+const char* fem_status_str(int status)
+{
+    switch (status) {
+    case FEM_OK: return "FEM_OK";
+    case FEM_E_INVAL: return "FEM_E_INVAL";
+    case FEM_E_NOMEM: return "FEM_E_NOMEM";
+    case FEM_E_HIP: return "FEM_E_HIP";
+    case FEM_E_STATE: return "FEM_E_STATE";
+    case FEM_E_NUMERIC: return "FEM_E_NUMERIC";
+    case FEM_E_UNSUPPORTED: return "FEM_E_UNSUPPORTED";
+    default: return "unknown fem_status";
+    }
+}
+
+const char* fem_last_error(void) { return g_err.c_str(); }
+int32_t fem_abi_version(void) { return 1; }
+
+fem_status fem_maxcut_create(int device, int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v,
+                             const float* w, fem_problem** out)
+{
+    return build_graph(KIND_MAXCUT, device, n, n_edges, u, v, w, 2, out);
+}
+
+fem_status fem_bmincut_create(int device, int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v,
+                              const float* w, int32_t q, fem_problem** out)
+{
+    if (q < 2) return fail(FEM_E_INVAL, "q must be >= 2 (got %d)", q);
+    if (q != 2 && q != 4 && q != 8 && q != 16 && q != 32)
+        return fail(FEM_E_UNSUPPORTED, "q = %d: this build supports q in {2, 4, 8, 16, 32}", q);
+    return build_graph(KIND_BMINCUT, device, n, n_edges, u, v, w, q, out);
+}
+
+fem_status fem_maxsat_create(int device, int32_t n_vars, int64_t n_clauses, const int64_t* clause_off,
+                             const int32_t* lits, fem_problem** out)
+{
+    return build_sat(device, n_vars, n_clauses, clause_off, lits, out);
+}
+
+fem_status fem_batch_create(int32_t nparts, fem_problem* const* parts, fem_problem** out)
+{
+    if (!out) return fail(FEM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (nparts < 1 || !parts) return fail(FEM_E_INVAL, "need at least one part");
+    const Problem& p0 = parts[0]->p;
+    int64_t ntot = 0;
+    for (int b = 0; b < nparts; ++b) {
+        if (!parts[b]) return fail(FEM_E_INVAL, "part %d is NULL", b);
+        const Problem& pb = parts[b]->p;
+        if (pb.kind != p0.kind || pb.q != p0.q || pb.device != p0.device)
+            return fail(FEM_E_INVAL, "part %d differs in kind, q or device", b);
+        ntot += pb.n;
+    }
+    if (ntot > INT32_MAX / 2) return fail(FEM_E_UNSUPPORTED, "batch too large");
+    auto* fp = new (std::nothrow) fem_problem;
+    if (!fp) return fail(FEM_E_NOMEM, "host allocation failed");
+    Problem& p = fp->p;
+    p.device = p0.device;
+    p.kind = p0.kind;
+    p.q = p0.q;
+    p.integral = true;
+    p.sat_width = 2;
+    for (int b = 0; b < nparts; ++b) p.sat_width = std::max(p.sat_width, parts[b]->p.sat_width);
+    p.inst_off.assign(1, 0);
+    p.h_row_off.assign(1, 0);
+    for (int b = 0; b < nparts; ++b) {
+        const Problem& pb = parts[b]->p;
+        for (size_t k = 0; k + 1 < pb.inst_off.size(); ++k) {
+            p.inst_off.push_back(p.n + pb.inst_off[k + 1]);
+            p.inst_wtot.push_back(pb.inst_wtot[k]);
+        }
+        const int64_t base = p.nnz;
+        const int32_t noff = p.n;
+        for (int32_t i = 0; i < pb.n; ++i) p.h_row_off.push_back(base + pb.h_row_off[(size_t)i + 1]);
+        for (const int2& e : pb.h_adj) p.h_adj.push_back(make_int2(e.x + noff, e.y));
+        auto shift = [&](uint32_t x) -> uint32_t {
+            if ((x & SAT_VAR_MASK) == SAT_NONE) return x;
+            return (x & ~SAT_VAR_MASK) | ((x & SAT_VAR_MASK) + (uint32_t)noff);
+        };
+        if (p.kind == KIND_MAXSAT) {
+            for (const int2& r : pb.h_inc2) {
+                if (p.sat_width == 2) p.h_inc2.push_back(make_int2((int)shift((uint32_t)r.x), (int)shift((uint32_t)r.y)));
+                else {
+                    const uint32_t x = (uint32_t)r.x, y = (uint32_t)r.y;
+                    const int flags = ((x & SAT_FLAG) ? 1 : 0) | ((y & SAT_FLAG) ? 2 : 0);
+                    p.h_inc4.push_back(make_int4((int)shift(x & ~SAT_FLAG), (int)shift(y & ~SAT_FLAG), (int)SAT_NONE, flags));
+                }
+            }
+            for (const int4& r : pb.h_inc4)
+                p.h_inc4.push_back(make_int4((int)shift((uint32_t)r.x), (int)shift((uint32_t)r.y), (int)shift((uint32_t)r.z), r.w));
+            p.n_clauses += pb.n_clauses;
+        }
+        p.h_wdeg.insert(p.h_wdeg.end(), pb.h_wdeg.begin(), pb.h_wdeg.end());
+        p.integral = p.integral && pb.integral;
+        p.n += pb.n;
+        p.nnz += pb.nnz;
+    }
+    p.n_inst = (int32_t)p.inst_off.size() - 1;
+    fem_status st = upload_problem(p);
+    if (st != FEM_OK) {
+        free_problem_device(p);
+        delete fp;
+        return st;
+    }
+    *out = fp;
+    return FEM_OK;
+}
+
+fem_status fem_problem_info(const fem_problem* fp, int32_t* kind, int32_t* n, int32_t* q, int64_t* nnz,
+                            int32_t* n_instances)
+{
+    if (!fp) return fail(FEM_E_INVAL, "problem is NULL");
+    if (kind) *kind = fp->p.kind;
+    if (n) *n = fp->p.n;
+    if (q) *q = fp->p.q;
+    if (nnz) *nnz = fp->p.nnz;
+    if (n_instances) *n_instances = fp->p.n_inst;
+    return FEM_OK;
+}
+
+fem_status fem_problem_instance_offsets(const fem_problem* fp, int32_t* offsets)
+{
+    if (!fp || !offsets) return fail(FEM_E_INVAL, "NULL argument");
+    std::copy(fp->p.inst_off.begin(), fp->p.inst_off.end(), offsets);
+    return FEM_OK;
+}
+
+void fem_problem_destroy(fem_problem* fp)
+{
+    if (!fp) return;
+    (void)hipSetDevice(fp->p.device);
+    free_problem_device(fp->p);
+    delete fp;
+}
+
+void fem_params_default(fem_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->replicas = 16;
+    p->steps = 500;
+    p->schedule = FEM_SCHED_LINEAR;
+    p->beta_min = 0.01;
+    p->beta_max = 5.0;
+    p->lr = 0.1;
+    p->adam_b1 = 0.9;
+    p->adam_b2 = 0.999;
+    p->adam_eps = 1e-8;
+    p->weight_decay = 0.0;
+    p->lambda = 0.0;
+    p->lambda_ramp = 0;
+    p->marginal_dtype = FEM_F32;
+    p->energy_every = 1;
+    p->record_energies = 0;
+    p->eval_every = 0;
+    p->keep_grad = 0;
+}
+
+fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void* hip_stream, fem_solver** out)
+{
+    if (!out) return fail(FEM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!fp || !prm) return fail(FEM_E_INVAL, "problem and params must not be NULL");
+    const fem_params& P = *prm;
+    if (P.replicas < 1) return fail(FEM_E_INVAL, "replicas must be >= 1");
+    if (P.steps < 1) return fail(FEM_E_INVAL, "steps must be >= 1");
+    if (P.schedule < 0 || P.schedule > 2) return fail(FEM_E_INVAL, "unknown schedule %d", P.schedule);
+    if (!(P.beta_min > 0.0) || !(P.beta_max >= P.beta_min) || !std::isfinite(P.beta_max))
+        return fail(FEM_E_INVAL, "need 0 < beta_min <= beta_max < inf");
+    if (!(P.lr > 0.0) || !(P.adam_b1 >= 0.0 && P.adam_b1 < 1.0) || !(P.adam_b2 >= 0.0 && P.adam_b2 < 1.0) ||
+        !(P.adam_eps >= 0.0) || !(P.weight_decay >= 0.0))
+        return fail(FEM_E_INVAL, "invalid Adam hyper-parameters");
+    if (!std::isfinite(P.lambda) || P.lambda < 0.0) return fail(FEM_E_INVAL, "lambda must be finite and >= 0");
+    if (P.marginal_dtype != FEM_F32 && P.marginal_dtype != FEM_BF16) return fail(FEM_E_INVAL, "unknown marginal dtype");
+    if (P.energy_every < 0 || P.eval_every < 0) return fail(FEM_E_INVAL, "energy_every and eval_every must be >= 0");
+    const Problem& p = fp->p;
+    if ((int64_t)p.n * P.replicas * (p.kind == KIND_BMINCUT ? p.q : 1) > ((int64_t)1 << 40))
+        return fail(FEM_E_NOMEM, "state of %lld values does not fit", (long long)p.n * P.replicas);
+    auto* s = new (std::nothrow) fem_solver;
+    if (!s) return fail(FEM_E_NOMEM, "host allocation failed");
+    s->prob = &p;
+    s->prm = P;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    s->kind = p.kind;
+    s->dtype = P.marginal_dtype;
+    s->n = p.n;
+    s->R = P.replicas;
+    s->q = p.q;
+    s->Q = (p.kind == KIND_BMINCUT) ? p.q : 1;
+    s->n_inst = p.n_inst;
+    s->vals = (size_t)s->n * s->R * s->Q;
+    s->NE = (p.kind == KIND_BMINCUT) ? 3 : 2;
+    s->beta.resize((size_t)P.steps);
+    s->lam.resize((size_t)P.steps);
+    for (int t = 0; t < P.steps; ++t) {
+        s->beta[(size_t)t] = sched_beta(P, P.steps, t);
+        s->lam[(size_t)t] = P.lambda_ramp ? (P.steps > 1 ? P.lambda * t / (double)(P.steps - 1) : P.lambda) : P.lambda;
+    }
+    auto bail = [&](fem_status st) {
+        std::string keep = g_err;
+        destroy_solver(s);
+        g_err = keep;
+        return st;
+    };
+    hipError_t e = hipSetDevice(p.device);
+    if (e != hipSuccess) return bail(fail(FEM_E_HIP, "hipSetDevice: %s", hipGetErrorString(e)));
+    const size_t msz = s->dtype == FEM_BF16 ? 2 : 4;
+    const size_t IR = (size_t)s->n_inst * s->R;
+#define ALLOC(ptr, cnt)                                                                                    \
+    do {                                                                                                   \
+        hipError_t ee = dalloc(&(ptr), (cnt));                                                             \
+        if (ee != hipSuccess)                                                                              \
+            return bail(fail(FEM_E_NOMEM, "device allocation of %s (%zu elements): %s", #ptr, (size_t)(cnt), \
+                             hipGetErrorString(ee)));                                                      \
+    } while (0)
+    ALLOC(s->h, s->vals);
+    ALLOC(s->m1, s->vals);
+    ALLOC(s->m2, s->vals);
+    if (P.keep_grad) ALLOC(s->grad, s->vals);
+    for (int k = 0; k < 2; ++k) {
+        e = hipMalloc(&s->marg[k], s->vals * msz);
+        if (e != hipSuccess) return bail(fail(FEM_E_NOMEM, "device allocation of the marginal copy: %s", hipGetErrorString(e)));
+    }
+    ALLOC(s->eraw, IR * s->NE);
+    ALLOC(s->eout, IR * 3);
+    if (P.record_energies && P.energy_every > 0) {
+        s->n_records = (P.steps + P.energy_every - 1) / P.energy_every;
+        ALLOC(s->ehist, (size_t)s->n_records * IR * 3);
+    }
+    ALLOC(s->d_wtot, (size_t)s->n_inst);
+    ALLOC(s->sigma, (size_t)s->n * s->R);
+    ALLOC(s->vout, IR);
+    ALLOC(s->best, IR);
+    if (s->kind == KIND_BMINCUT) {
+        ALLOC(s->cfix, IR * s->q);
+        ALLOC(s->csum, IR * s->q);
+        ALLOC(s->ctil, IR * s->q);
+        ALLOC(s->sint, IR * s->q);
+        ALLOC(s->sout, IR * s->q);
+    }
+#undef ALLOC
+    e = hipMemcpy(s->d_wtot, p.inst_wtot.data(), sizeof(double) * s->n_inst, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(fail(FEM_E_HIP, "copy of instance weights: %s", hipGetErrorString(e)));
+    TileShape sh = default_shape(s->kind, s->R);
+    while (!valid_shape(s, sh) && sh.waves > 1) sh.waves /= 2;
+    while (!valid_shape(s, sh) && sh.vec > 1) sh.vec /= 2;
+    if (!valid_shape(s, sh)) return bail(fail(FEM_E_UNSUPPORTED, "no launch shape fits R = %d, q = %d", s->R, s->q));
+    fem_status st = setup_tiling(s, sh);
+    if (st != FEM_OK) return bail(st);
+    st = reset_best(s);
+    if (st != FEM_OK) return bail(st);
+    *out = s;
+    return FEM_OK;
+}
+
+void fem_solver_destroy(fem_solver* s) { destroy_solver(s); }
+
+fem_status fem_set_fields(fem_solver* s, const float* h, int on_device)
+{
+    if (!s || !h) return fail(FEM_E_INVAL, "NULL argument");
+    HIPCHK(hipSetDevice(s->prob->device));
+    HIPCHK(hipMemcpyAsync(s->h, h, s->vals * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemsetAsync(s->m1, 0, s->vals * 4, s->stream));
+    HIPCHK(hipMemsetAsync(s->m2, 0, s->vals * 4, s->stream));
+    s->t = 0;
+    s->last_energy_step = -1;
+    STCHK(init_marginals(s));
+    STCHK(reset_best(s));
+    s->fields_set = true;
+    return FEM_OK;
+}
+
+fem_status fem_step(fem_solver* s, int32_t n_steps)
+{
+    if (!s) return fail(FEM_E_INVAL, "solver is NULL");
+    if (!s->fields_set) return fail(FEM_E_STATE, "fem_set_fields (or fem_set_state) must come first");
+    if (n_steps < 0 || (int64_t)s->t + n_steps > s->prm.steps)
+        return fail(FEM_E_STATE, "step range [%d, %lld) exceeds the schedule of %d steps", s->t,
+                    (long long)s->t + n_steps, s->prm.steps);
+    HIPCHK(hipSetDevice(s->prob->device));
+    for (int32_t k = 0; k < n_steps; ++k) STCHK(do_step(s));
+    return FEM_OK;
+}
+
+fem_status fem_capture(fem_solver* s, int32_t t_end);
+
+fem_status fem_run_until(fem_solver* s, int32_t t_end)
+{
+    if (!s) return fail(FEM_E_INVAL, "solver is NULL");
+    if (!s->fields_set) return fail(FEM_E_STATE, "fem_set_fields (or fem_set_state) must come first");
+    if (t_end < s->t || t_end > s->prm.steps)
+        return fail(FEM_E_STATE, "t_end %d outside [%d, %d]", t_end, s->t, s->prm.steps);
+    if (t_end == s->t) return FEM_OK;
+    HIPCHK(hipSetDevice(s->prob->device));
+    const int t0 = s->t;
+    if (!s->stream) {
+        // graph capture needs a non-null stream: run eagerly on the null stream
+        for (int k = t0; k < t_end; ++k) STCHK(do_step(s));
+        return FEM_OK;
+    }
+    STCHK(fem_capture(s, t_end));
+    auto it = s->graphs.find(std::make_pair(t0, (int)t_end));
+    HIPCHK(hipGraphLaunch(it->second, s->stream));
+    s->t = t_end;
+    // host bookkeeping equal to the eager sequence
+    if (s->prm.energy_every > 0) {
+        int last = -1;
+        for (int k = t_end - 1; k >= t0; --k)
+            if (energy_due(s, k)) { last = k; break; }
+        if (last >= 0) s->last_energy_step = last;
+    }
+    return FEM_OK;
+}
+
+fem_status fem_capture(fem_solver* s, int32_t t_end)
+{
+    if (!s) return fail(FEM_E_INVAL, "solver is NULL");
+    if (!s->fields_set) return fail(FEM_E_STATE, "fem_set_fields (or fem_set_state) must come first");
+    if (t_end < s->t || t_end > s->prm.steps)
+        return fail(FEM_E_STATE, "t_end %d outside [%d, %d]", t_end, s->t, s->prm.steps);
+    if (!s->stream) return fail(FEM_E_STATE, "graph capture needs a non-null stream");
+    if (t_end == s->t || s->graphs.count(std::make_pair((int)s->t, (int)t_end))) return FEM_OK;
+    HIPCHK(hipSetDevice(s->prob->device));
+    const int t0 = s->t;
+    const int last = s->last_energy_step;
+    HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    s->capturing = true;
+    fem_status st = FEM_OK;
+    for (int k = t0; k < t_end && st == FEM_OK; ++k) st = do_step(s);
+    s->capturing = false;
+    s->t = t0;
+    s->last_energy_step = last;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->stream, &g);
+    if (st != FEM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(FEM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(FEM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    s->graphs.emplace(std::make_pair(t0, (int)t_end), ge);
+    return FEM_OK;
+}
+
+fem_status fem_run(fem_solver* s)
+{
+    if (!s) return fail(FEM_E_INVAL, "solver is NULL");
+    return fem_run_until(s, s->prm.steps);
+}
+
+fem_status fem_sync(fem_solver* s)
+{
+    if (!s) return fail(FEM_E_INVAL, "solver is NULL");
+    HIPCHK(hipSetDevice(s->prob->device));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return FEM_OK;
+}
+
+fem_status fem_get_step(const fem_solver* s, int32_t* t)
+{
+    if (!s || !t) return fail(FEM_E_INVAL, "NULL argument");
+    *t = s->t;
+    return FEM_OK;
+}
+
+fem_status fem_get_fields(fem_solver* s, float* h, int on_device)
+{
+    if (!s || !h) return fail(FEM_E_INVAL, "NULL argument");
+    HIPCHK(hipSetDevice(s->prob->device));
+    HIPCHK(hipMemcpyAsync(h, s->h, s->vals * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return FEM_OK;
+}
+
+fem_status fem_last_grad(fem_solver* s, float* g, int on_device)
+{
+    if (!s || !g) return fail(FEM_E_INVAL, "NULL argument");
+    if (!s->prm.keep_grad) return fail(FEM_E_STATE, "solver created without keep_grad");
+    if (s->t == 0) return fail(FEM_E_STATE, "no step has run");
+    HIPCHK(hipSetDevice(s->prob->device));
+    HIPCHK(hipMemcpyAsync(g, s->grad, s->vals * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return FEM_OK;
+}
+
+static fem_status copy_energies(fem_solver* s, const double* src, double* U, double* S, double* F)
+{
+    const size_t IR = (size_t)s->n_inst * s->R;
+    std::vector<double> buf(IR * 3);
+    HIPCHK(hipMemcpyAsync(buf.data(), src, buf.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    bool finite = true;
+    for (size_t b = 0; b < (size_t)s->n_inst; ++b)
+        for (size_t r = 0; r < (size_t)s->R; ++r) {
+            const double* x = buf.data() + b * 3 * s->R;
+            if (U) U[b * s->R + r] = x[r];
+            if (S) S[b * s->R + r] = x[s->R + r];
+            if (F) F[b * s->R + r] = x[2 * s->R + r];
+            finite = finite && std::isfinite(x[r]) && std::isfinite(x[s->R + r]) && std::isfinite(x[2 * s->R + r]);
+        }
+    if (!finite) return fail(FEM_E_NUMERIC, "non-finite energy");
+    return FEM_OK;
+}
+
+fem_status fem_energies(fem_solver* s, double* U, double* S, double* F)
+{
+    if (!s) return fail(FEM_E_INVAL, "solver is NULL");
+    if (s->last_energy_step < 0) return fail(FEM_E_STATE, "no step has evaluated energies");
+    HIPCHK(hipSetDevice(s->prob->device));
+    return copy_energies(s, energy_slot(s, s->last_energy_step), U, S, F);
+}
+
+fem_status fem_energy_history(fem_solver* s, int32_t first, int32_t count, double* U, double* S, double* F)
+{
+    if (!s) return fail(FEM_E_INVAL, "solver is NULL");
+    if (!s->ehist) return fail(FEM_E_STATE, "solver created without record_energies");
+    if (first < 0 || count < 0 || first + count > s->n_records) return fail(FEM_E_INVAL, "record range out of bounds");
+    HIPCHK(hipSetDevice(s->prob->device));
+    const size_t IR = (size_t)s->n_inst * s->R;
+    for (int32_t k = 0; k < count; ++k)
+        STCHK(copy_energies(s, s->ehist + (size_t)(first + k) * IR * 3, U ? U + k * IR : nullptr,
+                            S ? S + k * IR : nullptr, F ? F + k * IR : nullptr));
+    return FEM_OK;
+}
+
+fem_status fem_round(fem_solver* s, int32_t* sigma)
+{
+    if (!s || !sigma) return fail(FEM_E_INVAL, "NULL argument");
+    if (!s->fields_set) return fail(FEM_E_STATE, "no fields set");
+    HIPCHK(hipSetDevice(s->prob->device));
+    HIPCHK(launch_round(s->kind, s->n, s->R, s->q, s->h, s->sigma, s->stream));
+    std::vector<uint8_t> buf((size_t)s->n * s->R);
+    HIPCHK(hipMemcpyAsync(buf.data(), s->sigma, buf.size(), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (size_t i = 0; i < (size_t)s->n; ++i)
+        for (size_t r = 0; r < (size_t)s->R; ++r) sigma[r * s->n + i] = buf[i * s->R + r];
+    return FEM_OK;
+}
+
+// integer outputs from the device evaluation buffers
+static fem_status fetch_eval(fem_solver* s, std::vector<double>& v, std::vector<long long>& sz)
+{
+    const size_t IR = (size_t)s->n_inst * s->R;
+    v.resize(IR);
+    HIPCHK(hipMemcpyAsync(v.data(), s->vout, IR * 8, hipMemcpyDeviceToHost, s->stream));
+    if (s->kind == KIND_BMINCUT) {
+        sz.resize(IR * s->q);
+        HIPCHK(hipMemcpyAsync(sz.data(), s->sout, sz.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return FEM_OK;
+}
+
+static int64_t value_of(const fem_solver* s, double v)
+{
+    // graphs: the evaluation summed ordered pairs
+    return s->kind == KIND_MAXSAT ? (int64_t)v : (int64_t)std::llround(0.5 * v);
+}
+
+fem_status fem_eval_int(const fem_problem* fp, int32_t R, const int32_t* sigma, int64_t* value, int64_t* sizes)
+{
+    if (!fp || !sigma || !value) return fail(FEM_E_INVAL, "NULL argument");
+    if (R < 1) return fail(FEM_E_INVAL, "R must be >= 1");
+    const Problem& p = fp->p;
+    for (size_t k = 0; k < (size_t)p.n * R; ++k)
+        if (sigma[k] < 0 || sigma[k] >= p.q) return fail(FEM_E_INVAL, "sigma value %d out of range [0, %d)", sigma[k], p.q);
+    fem_params prm;
+    fem_params_default(&prm);
+    prm.replicas = R;
+    prm.steps = 1;
+    prm.energy_every = 0;
+    fem_solver* s = nullptr;
+    STCHK(fem_solver_create(fp, &prm, nullptr, &s));
+    auto done = [&](fem_status st) {
+        std::string keep = g_err;
+        destroy_solver(s);
+        g_err = keep;
+        return st;
+    };
+    int32_t* d_sig = nullptr;
+    hipError_t e = dalloc(&d_sig, (size_t)p.n * R);
+    if (e != hipSuccess) return done(fail(FEM_E_NOMEM, "device allocation: %s", hipGetErrorString(e)));
+    e = hipMemcpy(d_sig, sigma, (size_t)p.n * R * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_transpose_sigma(p.n, R, d_sig, s->sigma, nullptr);
+    if (e != hipSuccess) {
+        dfree(d_sig);
+        return done(fail(FEM_E_HIP, "sigma upload: %s", hipGetErrorString(e)));
+    }
+    fem_status st = readout_eval(s, s->sigma, false);
+    std::vector<double> v;
+    std::vector<long long> sz;
+    if (st == FEM_OK) st = fetch_eval(s, v, sz);
+    dfree(d_sig);
+    if (st != FEM_OK) return done(st);
+    for (size_t k = 0; k < v.size(); ++k) value[k] = value_of(s, v[k]);
+    if (sizes && p.kind == KIND_BMINCUT)
+        for (size_t k = 0; k < sz.size(); ++k) sizes[k] = sz[k];
+    return done(FEM_OK);
+}
+
+fem_status fem_best(fem_solver* s, int32_t* replica, int64_t* value, int32_t* sigma)
+{
+    if (!s || !replica || !value) return fail(FEM_E_INVAL, "NULL argument");
+    if (!s->fields_set) return fail(FEM_E_STATE, "no fields set");
+    HIPCHK(hipSetDevice(s->prob->device));
+    STCHK(readout_eval(s, nullptr, false));
+    std::vector<double> v;
+    std::vector<long long> sz;
+    STCHK(fetch_eval(s, v, sz));
+    std::vector<uint8_t> sg;
+    if (sigma) {
+        sg.resize((size_t)s->n * s->R);
+        HIPCHK(hipMemcpy(sg.data(), s->sigma, sg.size(), hipMemcpyDeviceToHost));
+    }
+    const double lamf = s->prm.lambda;
+    for (int b = 0; b < s->n_inst; ++b) {
+        int br = 0;
+        double bs = std::numeric_limits<double>::infinity();
+        for (int r = 0; r < s->R; ++r) {
+            const size_t k = (size_t)b * s->R + r;
+            double score;
+            if (s->kind == KIND_MAXCUT) score = -v[k];
+            else if (s->kind == KIND_MAXSAT) score = v[k];
+            else {
+                double pen = 0.0;
+                for (int c = 0; c < s->q; ++c) {
+                    const double x = (double)sz[k * s->q + c];
+                    pen += x * (x - 1.0);
+                }
+                score = v[k] + lamf * pen;
+            }
+            if (score < bs) {
+                bs = score;
+                br = r;
+            }
+        }
+        replica[b] = br;
+        value[b] = value_of(s, v[(size_t)b * s->R + br]);
+        if (sigma) {
+            const int32_t i0 = s->prob->inst_off[(size_t)b], i1 = s->prob->inst_off[(size_t)b + 1];
+            for (int32_t i = i0; i < i1; ++i) sigma[i] = sg[(size_t)i * s->R + br];
+        }
+    }
+    return FEM_OK;
+}
+
+fem_status fem_anytime_best(fem_solver* s, double* value)
+{
+    if (!s || !value) return fail(FEM_E_INVAL, "NULL argument");
+    HIPCHK(hipSetDevice(s->prob->device));
+    const size_t IR = (size_t)s->n_inst * s->R;
+    std::vector<double> b(IR);
+    HIPCHK(hipMemcpyAsync(b.data(), s->best, IR * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (size_t k = 0; k < IR; ++k) {
+        // stored as "lower is better" scores
+        value[k] = (s->kind == KIND_MAXCUT) ? -b[k] : b[k];
+    }
+    return FEM_OK;
+}
+
+// ------------------------------------------------------------- checkpoints --
+struct StateHeader {
+    char magic[8];
+    int32_t version, kind, n, R, Q, dtype, t, n_inst;
+    int64_t bytes;
+};
+
+fem_status fem_state_size(const fem_solver* s, size_t* bytes)
+{
+    if (!s || !bytes) return fail(FEM_E_INVAL, "NULL argument");
+    *bytes = sizeof(StateHeader) + 3 * s->vals * 4 + (size_t)s->n_inst * s->R * 8;
+    return FEM_OK;
+}
+
+fem_status fem_get_state(fem_solver* s, void* buf, size_t bytes)
+{
+    size_t need = 0;
+    STCHK(fem_state_size(s, &need));
+    if (!buf || bytes < need) return fail(FEM_E_INVAL, "state buffer too small (%zu < %zu)", bytes, need);
+    if (!s->fields_set) return fail(FEM_E_STATE, "no fields set");
+    HIPCHK(hipSetDevice(s->prob->device));
+    StateHeader hd{};
+    std::memcpy(hd.magic, "FEMSTAT1", 8);
+    hd.version = 1;
+    hd.kind = s->kind;
+    hd.n = s->n;
+    hd.R = s->R;
+    hd.Q = s->Q;
+    hd.dtype = s->dtype;
+    hd.t = s->t;
+    hd.n_inst = s->n_inst;
+    hd.bytes = (int64_t)need;
+    char* out = static_cast<char*>(buf);
+    std::memcpy(out, &hd, sizeof hd);
+    char* p = out + sizeof hd;
+    HIPCHK(hipMemcpyAsync(p, s->h, s->vals * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(p + s->vals * 4, s->m1, s->vals * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(p + 2 * s->vals * 4, s->m2, s->vals * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(p + 3 * s->vals * 4, s->best, (size_t)s->n_inst * s->R * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return FEM_OK;
+}
+
+fem_status fem_set_state(fem_solver* s, const void* buf, size_t bytes)
+{
+    size_t need = 0;
+    STCHK(fem_state_size(s, &need));
+    if (!buf || bytes < need) return fail(FEM_E_INVAL, "state buffer too small (%zu < %zu)", bytes, need);
+    StateHeader hd;
+    std::memcpy(&hd, buf, sizeof hd);
+    if (std::memcmp(hd.magic, "FEMSTAT1", 8) != 0 || hd.version != 1)
+        return fail(FEM_E_INVAL, "not a FEM state buffer");
+    if (hd.kind != s->kind || hd.n != s->n || hd.R != s->R || hd.Q != s->Q || hd.n_inst != s->n_inst)
+        return fail(FEM_E_INVAL, "state belongs to a different problem or replica count");
+    if (hd.t < 0 || hd.t > s->prm.steps) return fail(FEM_E_INVAL, "state step %d outside the schedule", hd.t);
+    HIPCHK(hipSetDevice(s->prob->device));
+    const char* p = static_cast<const char*>(buf) + sizeof hd;
+    HIPCHK(hipMemcpyAsync(s->h, p, s->vals * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->m1, p + s->vals * 4, s->vals * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->m2, p + 2 * s->vals * 4, s->vals * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->best, p + 3 * s->vals * 4, (size_t)s->n_inst * s->R * 8, hipMemcpyHostToDevice, s->stream));
+    s->t = hd.t;
+    s->last_energy_step = -1;
+    STCHK(init_marginals(s));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->fields_set = true;
+    return FEM_OK;
+}
+
+// ------------------------------------------------------------------ tiling --
+fem_status fem_get_tile(const fem_solver* s, fem_tile* t)
+{
+    if (!s || !t) return fail(FEM_E_INVAL, "NULL argument");
+    t->vec = s->kind == KIND_BMINCUT ? s->q : s->shape.vec;
+    t->waves = s->shape.waves;
+    t->rows = s->shape.rows;
+    return FEM_OK;
+}
+
+fem_status fem_set_tile(fem_solver* s, const fem_tile* t)
+{
+    if (!s || !t) return fail(FEM_E_INVAL, "NULL argument");
+    TileShape sh;
+    sh.vec = s->kind == KIND_BMINCUT ? 1 : t->vec;
+    sh.waves = t->waves;
+    sh.rows = t->rows;
+    if (!valid_shape(s, sh)) return fail(FEM_E_INVAL, "invalid tile shape (vec %d, waves %d, rows %d) for R = %d", t->vec, t->waves, t->rows, s->R);
+    HIPCHK(hipSetDevice(s->prob->device));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    STCHK(setup_tiling(s, sh));
+    // column-sum partials are laid out per tile: rebuild them
+    if (s->fields_set && s->kind == KIND_BMINCUT) STCHK(init_marginals(s));
+    return FEM_OK;
+}
+
+static std::string tune_cache_path()
+{
+    const char* env = std::getenv("FEM_TUNE_CACHE");
+    if (env && *env) return env;
+    const char* home = std::getenv("HOME");
+    std::string dir = std::string(home ? home : "/tmp") + "/.cache";
+    (void)mkdir(dir.c_str(), 0755);
+    dir += "/femx";
+    (void)mkdir(dir.c_str(), 0755);
+    return dir + "/tune.txt";
+}
+
+static std::string tune_key(const fem_solver* s)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "k%d_n%d_nnz%lld_R%d_q%d_dt%d_inst%d_en%d", s->kind, s->n, (long long)s->prob->nnz, s->R,
+             s->q, s->dtype, s->n_inst, s->prm.energy_every > 0 ? 1 : 0);
+    return buf;
+}
+
+fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_tile* chosen)
+{
+    if (!s) return fail(FEM_E_INVAL, "solver is NULL");
+    if (!s->fields_set) return fail(FEM_E_STATE, "fem_set_fields must come first");
+    if (trial_steps < 1) return fail(FEM_E_INVAL, "trial_steps must be >= 1");
+    HIPCHK(hipSetDevice(s->prob->device));
+    const std::string path = tune_cache_path(), key = tune_key(s);
+    if (use_cache) {
+        FILE* f = std::fopen(path.c_str(), "r");
+        if (f) {
+            char k[256];
+            int v, w, r;
+            bool found = false;
+            TileShape sh;
+            while (std::fscanf(f, "%255s %d %d %d", k, &v, &w, &r) == 4)
+                if (key == k) {
+                    sh.vec = v;
+                    sh.waves = w;
+                    sh.rows = r;
+                    found = true;
+                }
+            std::fclose(f);
+            if (found && valid_shape(s, sh)) {
+                fem_tile t{sh.vec, sh.waves, sh.rows};
+                STCHK(fem_set_tile(s, &t));
+                if (chosen) STCHK(fem_get_tile(s, chosen));
+                return FEM_OK;
+            }
+        }
+    }
+    // save the state, try every shape from the same state, restore
+    size_t bytes = 0;
+    STCHK(fem_state_size(s, &bytes));
+    std::vector<char> saved(bytes);
+    STCHK(fem_get_state(s, saved.data(), bytes));
+    const int t_save = s->t;
+    const int steps_avail = s->prm.steps - t_save;
+    const int trial = std::min(trial_steps, std::max(1, steps_avail));
+    if (steps_avail < 1) return fail(FEM_E_STATE, "no steps left to tune with");
+    std::vector<TileShape> cands;
+    const int vecs[4] = {1, 2, 4, 8};
+    const int wavess[3] = {2, 4, 8};
+    const int rowss[4] = {1, 2, 4, 8};
+    for (int vi = 0; vi < (s->kind == KIND_BMINCUT ? 1 : 4); ++vi)
+        for (int wv : wavess)
+            for (int rw : rowss) {
+                TileShape sh;
+                sh.vec = vecs[vi];
+                sh.waves = wv;
+                sh.rows = rw;
+                if (valid_shape(s, sh)) cands.push_back(sh);
+            }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    TileShape best_sh = s->shape;
+    float best_ms = std::numeric_limits<float>::infinity();
+    const bool prof = s->profile;
+    s->profile = false;
+    fem_status st = FEM_OK;
+    for (const TileShape& sh : cands) {
+        fem_tile t{sh.vec, sh.waves, sh.rows};
+        st = fem_set_tile(s, &t);
+        if (st != FEM_OK) break;
+        st = fem_set_state(s, saved.data(), bytes);
+        if (st != FEM_OK) break;
+        st = fem_step(s, 1);   // warm-up
+        if (st != FEM_OK) break;
+        st = fem_set_state(s, saved.data(), bytes);
+        if (st != FEM_OK) break;
+        (void)hipEventRecord(e0, s->stream);
+        st = fem_step(s, trial);
+        (void)hipEventRecord(e1, s->stream);
+        if (st != FEM_OK) break;
+        (void)hipEventSynchronize(e1);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_sh = sh;
+        }
+    }
+    s->profile = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    fem_tile bt{best_sh.vec, best_sh.waves, best_sh.rows};
+    fem_status st2 = fem_set_tile(s, &bt);
+    if (st2 == FEM_OK) st2 = fem_set_state(s, saved.data(), bytes);
+    if (st != FEM_OK) return st;
+    if (st2 != FEM_OK) return st2;
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (f) {
+        std::fprintf(f, "%s %d %d %d\n", key.c_str(), best_sh.vec, best_sh.waves, best_sh.rows);
+        std::fclose(f);
+    }
+    if (chosen) STCHK(fem_get_tile(s, chosen));
+    return FEM_OK;
+}
+
+fem_status fem_profile(fem_solver* s, int32_t on)
+{
+    if (!s) return fail(FEM_E_INVAL, "solver is NULL");
+    s->profile = on != 0;
+    s->prof_used = 0;
+    return FEM_OK;
+}
+
+fem_status fem_profile_result(fem_solver* s, double* step_kernel_ms, int32_t* n_kernels)
+{
+    if (!s || !step_kernel_ms) return fail(FEM_E_INVAL, "NULL argument");
+    HIPCHK(hipSetDevice(s->prob->device));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    double tot = 0.0;
+    for (size_t k = 0; k < s->prof_used; ++k) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, s->prof_events[k].first, s->prof_events[k].second));
+        tot += ms;
+    }
+    *step_kernel_ms = s->prof_used ? tot / (double)s->prof_used : 0.0;
+    if (n_kernels) *n_kernels = (int32_t)s->prof_used;
+    s->prof_used = 0;
+    return FEM_OK;
+}
+
+}  // extern "C"

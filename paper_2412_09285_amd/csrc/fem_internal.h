@@ -1,0 +1,128 @@
+// Internal declarations of the FEM library (host structures, kernel launch
+// parameters).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace fem {
+
+enum Kind { KIND_MAXCUT = 0, KIND_BMINCUT = 1, KIND_MAXSAT = 2 };
+
+// One tile = a contiguous row range of a single instance; one workgroup per
+// tile (times the replica segments along grid.y).
+struct Tile {
+    int32_t inst, row_begin, row_end, slot;   // slot: index of the tile's partial sums
+};
+
+// Device-resident problem.
+struct Problem {
+    int device = 0;
+    int kind = KIND_MAXCUT;
+    int32_t n = 0;         // total rows (nodes / variables) over all instances
+    int32_t q = 2;         // states (2 for one-logit kinds)
+    int64_t nnz = 0;       // adjacency entries or literal incidences
+    int32_t n_inst = 1;
+    int32_t sat_width = 2; // Max-k-SAT: other literals stored per incidence (2 or 3)
+    int64_t n_clauses = 0;
+    bool integral = true;  // all weights integral (exact integer cut values)
+    std::vector<int32_t> inst_off;   // host [n_inst+1] node offsets
+    std::vector<double> inst_wtot;   // host [n_inst] sum of undirected weights
+    // device arrays
+    int64_t* row_off = nullptr;      // [n+1]
+    int2* adj = nullptr;             // graphs: {col, float bits of w}
+    int2* inc2 = nullptr;            // Max-k-SAT, <= 2 other literals per incidence
+    int4* inc4 = nullptr;            // Max-k-SAT, <= 3 other literals per incidence
+    float* wdeg = nullptr;           // bMinCut: sum_j W_ij per node
+    // host copies kept for batching and validation
+    std::vector<int64_t> h_row_off;
+    std::vector<int2> h_adj;
+    std::vector<int2> h_inc2;
+    std::vector<int4> h_inc4;
+    std::vector<float> h_wdeg;
+};
+
+// Marginal-copy literal packing for Max-k-SAT incidence records:
+//   bit 31: literal is positive; bits 0..29: variable; the value
+//   SAT_NONE in bits 0..29 marks an unused slot (treated as a false literal
+//   with probability 1, i.e. a neutral factor).
+constexpr uint32_t SAT_VAR_MASK = 0x3FFFFFFFu;
+constexpr uint32_t SAT_NONE = 0x3FFFFFFFu;
+constexpr uint32_t SAT_POS = 0x80000000u;
+// flag bits carried in bit 30 of the first / second slot
+constexpr uint32_t SAT_FLAG = 0x40000000u;   // slot0: own literal positive; slot1: owner incidence
+
+struct TileShape {
+    int vec = 1, waves = 4, rows = 4;
+};
+
+// Per-step scalars, computed on the host in double and passed as float.
+struct StepScalars {
+    float inv_beta;
+    float lam;
+    float step_size;   // lr / (1 - b1^n)
+    float bc2_sqrt;    // sqrt(1 - b2^n)
+    float b1, one_m_b1, b2, one_m_b2, eps, wd;
+};
+
+struct LaunchGeom {
+    int lanes;        // lanes per team (power of two, <= 64)
+    int nseg;         // replica segments (grid.y)
+    int teams_per_block;
+    int n_tiles;
+};
+
+// Arguments shared by the step kernels.
+struct StepArgs {
+    const int64_t* row_off;
+    const int2* adj;
+    const int2* inc2;
+    const int4* inc4;
+    const float* wdeg;
+    const Tile* tiles;
+    const void* marg_cur;
+    void* marg_nxt;
+    float* h;
+    float* m1;
+    float* m2;
+    float* grad;                  // may be null
+    double* epart;                // [n_tiles][NE][R] or null (no energies this step)
+    const float* ctil;            // bMinCut: centred column sums C~ [inst][R][q] (float)
+    long long* cpart;             // bMinCut: column-sum partials of the new P [n_tiles][R][q]
+    int32_t R;
+    int32_t q;
+    int32_t lanes_log2;
+    StepScalars sc;
+};
+
+// host-side kernel launchers (fem_kernels.hip)
+hipError_t launch_step(int kind, int dtype, int vec, const LaunchGeom& g, int waves,
+                       const StepArgs& a, hipStream_t st);
+// marginal copy of a.h into a.marg_nxt (count = n*R values for one-logit kinds);
+// for bMinCut also the column-sum partials a.cpart
+hipError_t launch_init_marginals(int kind, int dtype, const LaunchGeom& g, int waves,
+                                 const StepArgs& a, size_t count, hipStream_t st);
+// out[inst][c] = sum over the instance's tiles of part[tile][c] (two fixed-order stages)
+template <typename T>
+hipError_t launch_seg_reduce(const T* part, int cols, const int32_t* chunk_off, int n_chunks,
+                             const int32_t* inst_chunk_off, int n_inst, T* tmp, T* out,
+                             hipStream_t st);
+hipError_t launch_energy_combine(int kind, int R, int q, int n_inst, const double* raw,
+                                 const double* wtot, const double* csum, double lam, double beta,
+                                 double* eout, hipStream_t st);
+hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, double* csum,
+                                 float* ctil, hipStream_t st);
+hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h,
+                        uint8_t* sigma, hipStream_t st);
+hipError_t launch_transpose_sigma(int32_t n, int32_t R, const int32_t* sig_rn, uint8_t* sig_nr,
+                                  hipStream_t st);
+hipError_t launch_eval(const Problem& p, const LaunchGeom& g, int waves, const Tile* tiles,
+                       int32_t R, const uint8_t* sigma, double* vpart, int* spart,
+                       hipStream_t st);
+hipError_t launch_sizes_widen(size_t count, const int* in, long long* out, hipStream_t st);
+hipError_t launch_best_update(int kind, int R, int n_inst, int q, double lam, const double* vout,
+                              const long long* sout, double* best, hipStream_t st);
+
+}  // namespace fem

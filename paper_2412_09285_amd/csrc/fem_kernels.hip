@@ -1,0 +1,1059 @@
+// HIP kernels of the FEM hot path for gfx950 (CDNA4, wave64).
+//
+// One step kernel per problem kind fuses, for a tile of rows (nodes or
+// variables) and all replicas:
+//   gather of neighbour marginals (sparse product W . m, W . P, or the
+//   clause cavity products) -> gradient dF/dh -> Adam -> new marginal copy,
+// plus optional per-replica energy partials.  The gradient formulas are the
+// paper's explicit gradients (supplementary "The explicit gradients and
+// manipulated gradients ...", with the discretisation and normalisers of the
+// manipulated variant left out, i.e. c_i = 1, e_j -> P_j, gamma_grad = 1)
+// pushed through the softmax chain rule ("The explicit gradient formulations"),
+// and for q = 2 the one-logit reduction ("Simplification of FEM for solving the
+// MaxCut problem").
+//
+// Layout: rows are node-major with the replica index fastest (then the Potts
+// state), so one neighbour gather reads R*q contiguous values.  A "team" of L
+// lanes (L a power of two <= 64) owns one row at a time; lane l holds V
+// consecutive replicas (one-logit kinds) or one replica's q states (Potts).
+// Several teams share a wave when L < 64.  A workgroup owns one tile, a row
+// range of a single instance, so per-instance reductions never mix instances.
+//
+// Determinism: every sum has a fixed order (CSR order for gathers, butterfly
+// then wave order inside a workgroup, tile order across workgroups).  The
+// Potts column sums, which feed back into the gradient, are accumulated in
+// 2^-40 fixed point (int64), so they do not depend on the tile shape at all.
+#include "fem_internal.h"
+
+namespace fem {
+
+// ---------------------------------------------------------------- helpers --
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+// round-to-nearest-even float -> bfloat16 (NaN kept quiet)
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// V consecutive float32 values
+template <int V>
+__device__ __forceinline__ void ld_f32(const float* __restrict__ p, float (&x)[V])
+{
+    if constexpr (V == 1) {
+        x[0] = p[0];
+    } else if constexpr (V == 2) {
+        f32x2 t = *reinterpret_cast<const f32x2*>(p);
+        x[0] = t.x; x[1] = t.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k) {
+            f32x4 t = reinterpret_cast<const f32x4*>(p)[k];
+            x[4 * k] = t.x; x[4 * k + 1] = t.y; x[4 * k + 2] = t.z; x[4 * k + 3] = t.w;
+        }
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void st_f32(float* __restrict__ p, const float (&x)[V])
+{
+    if constexpr (V == 1) {
+        p[0] = x[0];
+    } else if constexpr (V == 2) {
+        f32x2 t; t.x = x[0]; t.y = x[1];
+        *reinterpret_cast<f32x2*>(p) = t;
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k) {
+            f32x4 t; t.x = x[4 * k]; t.y = x[4 * k + 1]; t.z = x[4 * k + 2]; t.w = x[4 * k + 3];
+            reinterpret_cast<f32x4*>(p)[k] = t;
+        }
+    }
+}
+
+// V consecutive bfloat16 values, widened
+template <int V>
+__device__ __forceinline__ void ld_bf16(const uint16_t* __restrict__ p, float (&x)[V])
+{
+    if constexpr (V == 1) {
+        x[0] = bf16_to_f32(p[0]);
+    } else if constexpr (V == 2) {
+        uint32_t t = *reinterpret_cast<const uint32_t*>(p);
+        x[0] = __uint_as_float(t << 16); x[1] = __uint_as_float(t & 0xffff0000u);
+    } else if constexpr (V == 4) {
+        u32x2 t = *reinterpret_cast<const u32x2*>(p);
+        x[0] = __uint_as_float(t.x << 16); x[1] = __uint_as_float(t.x & 0xffff0000u);
+        x[2] = __uint_as_float(t.y << 16); x[3] = __uint_as_float(t.y & 0xffff0000u);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 8; ++k) {
+            u32x4 t = reinterpret_cast<const u32x4*>(p)[k];
+            x[8 * k + 0] = __uint_as_float(t.x << 16); x[8 * k + 1] = __uint_as_float(t.x & 0xffff0000u);
+            x[8 * k + 2] = __uint_as_float(t.y << 16); x[8 * k + 3] = __uint_as_float(t.y & 0xffff0000u);
+            x[8 * k + 4] = __uint_as_float(t.z << 16); x[8 * k + 5] = __uint_as_float(t.z & 0xffff0000u);
+            x[8 * k + 6] = __uint_as_float(t.w << 16); x[8 * k + 7] = __uint_as_float(t.w & 0xffff0000u);
+        }
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void st_bf16(uint16_t* __restrict__ p, const float (&x)[V])
+{
+    if constexpr (V == 1) {
+        p[0] = f32_to_bf16(x[0]);
+    } else if constexpr (V == 2) {
+        *reinterpret_cast<uint32_t*>(p) = (uint32_t)f32_to_bf16(x[0]) | ((uint32_t)f32_to_bf16(x[1]) << 16);
+    } else if constexpr (V == 4) {
+        u32x2 t;
+        t.x = (uint32_t)f32_to_bf16(x[0]) | ((uint32_t)f32_to_bf16(x[1]) << 16);
+        t.y = (uint32_t)f32_to_bf16(x[2]) | ((uint32_t)f32_to_bf16(x[3]) << 16);
+        *reinterpret_cast<u32x2*>(p) = t;
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 8; ++k) {
+            u32x4 t;
+            t.x = (uint32_t)f32_to_bf16(x[8 * k + 0]) | ((uint32_t)f32_to_bf16(x[8 * k + 1]) << 16);
+            t.y = (uint32_t)f32_to_bf16(x[8 * k + 2]) | ((uint32_t)f32_to_bf16(x[8 * k + 3]) << 16);
+            t.z = (uint32_t)f32_to_bf16(x[8 * k + 4]) | ((uint32_t)f32_to_bf16(x[8 * k + 5]) << 16);
+            t.w = (uint32_t)f32_to_bf16(x[8 * k + 6]) | ((uint32_t)f32_to_bf16(x[8 * k + 7]) << 16);
+            reinterpret_cast<u32x4*>(p)[k] = t;
+        }
+    }
+}
+
+template <typename MT, int V>
+__device__ __forceinline__ void ld_marg(const MT* p, float (&x)[V])
+{
+    if constexpr (sizeof(MT) == 4) ld_f32<V>(reinterpret_cast<const float*>(p), x);
+    else ld_bf16<V>(reinterpret_cast<const uint16_t*>(p), x);
+}
+
+template <typename MT, int V>
+__device__ __forceinline__ void st_marg(MT* p, const float (&x)[V])
+{
+    if constexpr (sizeof(MT) == 4) st_f32<V>(reinterpret_cast<float*>(p), x);
+    else st_bf16<V>(reinterpret_cast<uint16_t*>(p), x);
+}
+
+// Adam, torch.optim.Adam semantics: g += wd*h; m1 = b1 m1 + (1-b1) g;
+// m2 = b2 m2 + (1-b2) g^2; h -= step_size * m1 / (sqrt(m2)/sqrt(1-b2^n) + eps)
+__device__ __forceinline__ float adam_update(float x, float g, float& m1, float& m2, const StepScalars& s)
+{
+    g = g + s.wd * x;
+    m1 = s.b1 * m1 + s.one_m_b1 * g;
+    m2 = s.b2 * m2 + s.one_m_b2 * (g * g);
+    float denom = sqrtf(m2) / s.bc2_sqrt + s.eps;
+    return x - s.step_size * (m1 / denom);
+}
+
+// 2^-40 fixed point of a probability in [0, 1]
+__device__ __forceinline__ long long to_fixed(float p) { return (long long)rintf(p * 1099511627776.0f); }
+
+// Max-k-SAT stored marginal: the smaller of P(x=1) and P(x=0), negative (sign
+// bit set) when P(x=1) > 1/2.  Both tails keep full relative precision.
+__device__ __forceinline__ float sat_encode(float h)
+{
+    float e = expf(-fabsf(h));
+    float small = e / (1.0f + e);
+    return h > 0.0f ? -small : small;
+}
+// probability that a literal of polarity pos is false, from the stored value
+__device__ __forceinline__ float sat_u(float s, bool pos)
+{
+    bool hi = signbit(s);
+    float a = fabsf(s);
+    return (pos == hi) ? a : 1.0f - a;
+}
+
+// Butterfly over the teams of one wave (lanes that hold the same replicas),
+// then a fixed-order sum over the waves of the workgroup.  vals[k] are per-lane
+// values, K per lane.  Results land in out[k * L * Vl + lane * Vl + v]-style
+// layout chosen by the caller through 'store'.
+template <typename T, int K>
+__device__ __forceinline__ void team_butterfly(T (&v)[K], int lanes_log2)
+{
+    for (int off = 1 << lanes_log2; off < 64; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    }
+}
+
+// ------------------------------------------------------- geometry helpers --
+struct TeamIdx {
+    int lane, wave, nwaves, L, tl, team, teams;
+};
+__device__ __forceinline__ TeamIdx team_idx(int lanes_log2)
+{
+    TeamIdx t;
+    t.lane = threadIdx.x & 63;
+    t.wave = threadIdx.x >> 6;
+    t.nwaves = blockDim.x >> 6;
+    t.L = 1 << lanes_log2;
+    t.tl = t.lane & (t.L - 1);
+    t.team = t.wave * (64 >> lanes_log2) + (t.lane >> lanes_log2);
+    t.teams = t.nwaves * (64 >> lanes_log2);
+    return t;
+}
+
+// Sum K per-lane values over the workgroup's teams in a fixed order (butterfly
+// within the wave, then waves in order) and hand each total to store(k, l, s),
+// where l is the lane-in-team index.  lds must hold nwaves * L * K values.
+template <typename T, int K, typename Store>
+__device__ __forceinline__ void block_reduce_store(T (&v)[K], const TeamIdx& ti, int lanes_log2, T* lds,
+                                                   Store store)
+{
+    team_butterfly<T, K>(v, lanes_log2);
+    if (ti.lane < ti.L) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[(ti.wave * K + k) * ti.L + ti.lane] = v[k];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ti.L * K; t += blockDim.x) {
+        const int k = t / ti.L, l = t % ti.L;
+        T s = lds[k * ti.L + l];
+        for (int w = 1; w < ti.nwaves; ++w) s += lds[(w * K + k) * ti.L + l];
+        store(k, l, s);
+    }
+    __syncthreads();
+}
+
+// ========================================================= MaxCut step ====
+// phi_i = sum_j W_ij m_j with m = tanh(h/2) = 2P - 1 (the stored copy);
+// g_i = P_i (1 - P_i) [2 phi_i + h_i / beta]: the explicit gradient of the
+// ordered-pair F through the one-logit reduction.  Energies: U = -W_tot +
+// (1/2) sum_i m_i phi_i and S = sum_i H2(P_i), accumulated here as
+// [sum m phi, sum H2] per replica.
+template <int V, typename MT, bool EN>
+__global__ void __launch_bounds__(1024) maxcut_step_kernel(StepArgs a)
+{
+    const Tile tile = a.tiles[blockIdx.x];
+    const TeamIdx ti = team_idx(a.lanes_log2);
+    const int R = a.R;
+    const int rb = (blockIdx.y * ti.L + ti.tl) * V;
+    const bool act = rb < R;
+    const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
+    MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
+    const StepScalars sc = a.sc;
+    double eacc[2 * V];
+#pragma unroll
+    for (int k = 0; k < 2 * V; ++k) eacc[k] = 0.0;
+
+    if (act) {
+        for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
+            float acc[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] = 0.0f;
+            int64_t k = a.row_off[i];
+            const int64_t kend = a.row_off[i + 1];
+            for (; k + 4 <= kend; k += 4) {
+                const int2 e0 = a.adj[k], e1 = a.adj[k + 1], e2 = a.adj[k + 2], e3 = a.adj[k + 3];
+                float x0[V], x1[V], x2[V], x3[V];
+                ld_marg<MT, V>(mc + (size_t)e0.x * R + rb, x0);
+                ld_marg<MT, V>(mc + (size_t)e1.x * R + rb, x1);
+                ld_marg<MT, V>(mc + (size_t)e2.x * R + rb, x2);
+                ld_marg<MT, V>(mc + (size_t)e3.x * R + rb, x3);
+                const float w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
+                const float w2 = __int_as_float(e2.y), w3 = __int_as_float(e3.y);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    acc[v] = fmaf(w0, x0[v], acc[v]);
+                    acc[v] = fmaf(w1, x1[v], acc[v]);
+                    acc[v] = fmaf(w2, x2[v], acc[v]);
+                    acc[v] = fmaf(w3, x3[v], acc[v]);
+                }
+            }
+            for (; k < kend; ++k) {
+                const int2 e0 = a.adj[k];
+                float x0[V];
+                ld_marg<MT, V>(mc + (size_t)e0.x * R + rb, x0);
+                const float w0 = __int_as_float(e0.y);
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] = fmaf(w0, x0[v], acc[v]);
+            }
+            const size_t base = (size_t)i * R + rb;
+            float hv[V], m1v[V], m2v[V], mnew[V], gv[V];
+            ld_f32<V>(a.h + base, hv);
+            ld_f32<V>(a.m1 + base, m1v);
+            ld_f32<V>(a.m2 + base, m2v);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float x = hv[v];
+                const float ax = fabsf(x);
+                const float e = expf(-ax);
+                const float ope = 1.0f + e;
+                const float pq = e / (ope * ope);   // P(1-P) without cancellation
+                const float g = pq * (2.0f * acc[v] + x * sc.inv_beta);
+                gv[v] = g;
+                if constexpr (EN) {
+                    eacc[v] += (double)(tanhf(0.5f * x) * acc[v]);
+                    eacc[V + v] += (double)(log1pf(e) + ax * (e / ope));
+                }
+                const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
+                hv[v] = nh;
+                mnew[v] = tanhf(0.5f * nh);
+            }
+            st_f32<V>(a.h + base, hv);
+            st_f32<V>(a.m1 + base, m1v);
+            st_f32<V>(a.m2 + base, m2v);
+            st_marg<MT, V>(mn + base, mnew);
+            if (a.grad) st_f32<V>(a.grad + base, gv);
+        }
+    }
+    if constexpr (EN) {
+        extern __shared__ double lds_d[];
+        block_reduce_store<double, 2 * V>(eacc, ti, a.lanes_log2, lds_d, [&](int k, int l, double s) {
+            const int term = k / V, v = k % V;
+            const int r = (blockIdx.y * ti.L + l) * V + v;
+            if (r < R) a.epart[((size_t)tile.slot * 2 + term) * R + r] = s;
+        });
+    }
+}
+
+// ======================================================= bMinCut step =====
+// Potts, q states per node, softmax marginals.  With Phi_i(s) = sum_j W_ij
+// P_j(s) and C~(s) the centred column sum of the current marginals:
+//   A(s) = -2 Phi_i(s) + 2 lam [C~(s) - P_i(s)] + h_i(s) / beta
+//   g_i(s) = P_i(s) [A(s) - sum_s' P_i(s') A(s')]
+// This equals the chain rule applied to the explicit bMinCut gradient: the
+// terms (ln P + 1)/beta and the column-sum centring differ from h/beta and
+// C~ by per-(node, replica) constants, which the chain rule removes exactly.
+// Energies per replica: [sum_i (sum_j W_ij - P_i.Phi_i), sum_i |P_i|^2,
+// -sum_i P_i.ln P_i].  Column sums of the new marginals go out as 2^-40
+// fixed point.
+template <int Q, typename MT, bool EN>
+__global__ void __launch_bounds__(1024) potts_step_kernel(StepArgs a)
+{
+    const Tile tile = a.tiles[blockIdx.x];
+    const TeamIdx ti = team_idx(a.lanes_log2);
+    const int R = a.R;
+    const int r = blockIdx.y * ti.L + ti.tl;   // replica of this lane
+    const bool act = r < R;
+    const int RQ = R * Q;
+    const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
+    MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
+    const StepScalars sc = a.sc;
+    float ct[Q];
+    double eacc[3] = {0.0, 0.0, 0.0};
+    long long cs[Q];
+#pragma unroll
+    for (int s = 0; s < Q; ++s) cs[s] = 0;
+    if (act) {
+        ld_f32<Q>(a.ctil + ((size_t)tile.inst * R + r) * Q, ct);
+        for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
+            float phi[Q];
+#pragma unroll
+            for (int s = 0; s < Q; ++s) phi[s] = 0.0f;
+            int64_t k = a.row_off[i];
+            const int64_t kend = a.row_off[i + 1];
+            for (; k + 2 <= kend; k += 2) {
+                const int2 e0 = a.adj[k], e1 = a.adj[k + 1];
+                float x0[Q], x1[Q];
+                ld_marg<MT, Q>(mc + (size_t)e0.x * RQ + (size_t)r * Q, x0);
+                ld_marg<MT, Q>(mc + (size_t)e1.x * RQ + (size_t)r * Q, x1);
+                const float w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
+#pragma unroll
+                for (int s = 0; s < Q; ++s) {
+                    phi[s] = fmaf(w0, x0[s], phi[s]);
+                    phi[s] = fmaf(w1, x1[s], phi[s]);
+                }
+            }
+            for (; k < kend; ++k) {
+                const int2 e0 = a.adj[k];
+                float x0[Q];
+                ld_marg<MT, Q>(mc + (size_t)e0.x * RQ + (size_t)r * Q, x0);
+                const float w0 = __int_as_float(e0.y);
+#pragma unroll
+                for (int s = 0; s < Q; ++s) phi[s] = fmaf(w0, x0[s], phi[s]);
+            }
+            const size_t base = ((size_t)i * R + r) * Q;
+            float hv[Q], m1v[Q], m2v[Q];
+            ld_f32<Q>(a.h + base, hv);
+            ld_f32<Q>(a.m1 + base, m1v);
+            ld_f32<Q>(a.m2 + base, m2v);
+            // softmax of the current fields
+            float mx = hv[0];
+#pragma unroll
+            for (int s = 1; s < Q; ++s) mx = fmaxf(mx, hv[s]);
+            float P[Q], Z = 0.0f;
+#pragma unroll
+            for (int s = 0; s < Q; ++s) { P[s] = expf(hv[s] - mx); Z += P[s]; }
+            const float invZ = 1.0f / Z;
+#pragma unroll
+            for (int s = 0; s < Q; ++s) P[s] *= invZ;
+            float A[Q], avg = 0.0f;
+#pragma unroll
+            for (int s = 0; s < Q; ++s) {
+                A[s] = -2.0f * phi[s] + 2.0f * sc.lam * (ct[s] - P[s]) + (hv[s] - mx) * sc.inv_beta;
+                avg = fmaf(P[s], A[s], avg);
+            }
+            float gv[Q];
+#pragma unroll
+            for (int s = 0; s < Q; ++s) gv[s] = (A[s] - avg) * P[s];
+            if constexpr (EN) {
+                const float lz = logf(Z);
+                float dot = 0.0f, sq = 0.0f, ent = 0.0f;
+#pragma unroll
+                for (int s = 0; s < Q; ++s) {
+                    dot = fmaf(P[s], phi[s], dot);
+                    sq = fmaf(P[s], P[s], sq);
+                    ent = fmaf(-P[s], hv[s] - mx - lz, ent);
+                }
+                eacc[0] += (double)(a.wdeg[i] - dot);
+                eacc[1] += (double)sq;
+                eacc[2] += (double)ent;
+            }
+            // Adam, then the softmax of the new fields
+#pragma unroll
+            for (int s = 0; s < Q; ++s) hv[s] = adam_update(hv[s], gv[s], m1v[s], m2v[s], sc);
+            float mx2 = hv[0];
+#pragma unroll
+            for (int s = 1; s < Q; ++s) mx2 = fmaxf(mx2, hv[s]);
+            float Pn[Q], Z2 = 0.0f;
+#pragma unroll
+            for (int s = 0; s < Q; ++s) { Pn[s] = expf(hv[s] - mx2); Z2 += Pn[s]; }
+            const float invZ2 = 1.0f / Z2;
+#pragma unroll
+            for (int s = 0; s < Q; ++s) {
+                Pn[s] *= invZ2;
+                cs[s] += to_fixed(Pn[s]);
+            }
+            st_f32<Q>(a.h + base, hv);
+            st_f32<Q>(a.m1 + base, m1v);
+            st_f32<Q>(a.m2 + base, m2v);
+            st_marg<MT, Q>(mn + base, Pn);
+            if (a.grad) st_f32<Q>(a.grad + base, gv);
+        }
+    }
+    extern __shared__ double lds_d[];
+    block_reduce_store<long long, Q>(cs, ti, a.lanes_log2, reinterpret_cast<long long*>(lds_d),
+                                     [&](int s, int l, long long v) {
+                                         const int rr = blockIdx.y * ti.L + l;
+                                         if (rr < R) a.cpart[((size_t)tile.slot * R + rr) * Q + s] = v;
+                                     });
+    if constexpr (EN) {
+        block_reduce_store<double, 3>(eacc, ti, a.lanes_log2, lds_d, [&](int k, int l, double s) {
+            const int rr = blockIdx.y * ti.L + l;
+            if (rr < R) a.epart[((size_t)tile.slot * 3 + k) * R + rr] = s;
+        });
+    }
+}
+
+// ======================================================= Max-k-SAT step ===
+// Variable-centric: every incidence (m, i) of variable i stores the clause's
+// other literals.  With u = probability that a literal is false and
+// c_mi = prod_{k in m, k != i} u_mk (the cavity product, formed from the
+// others, never by division):
+//   d_i = sum_{m ∋ i} (literal positive ? -1 : +1) c_mi
+//   g_i = P_i (1 - P_i) [d_i + h_i / beta]
+// Energies per replica: [sum over owner incidences of prod_{k in m} u_mk,
+// sum_i H2(P_i)]; each clause has exactly one owner incidence.
+template <int W>
+struct SatRec;
+template <>
+struct SatRec<2> {
+    using T = int2;
+};
+template <>
+struct SatRec<3> {
+    using T = int4;
+};
+
+template <int V, typename MT, int W, bool EN>
+__global__ void __launch_bounds__(1024) sat_step_kernel(StepArgs a)
+{
+    const Tile tile = a.tiles[blockIdx.x];
+    const TeamIdx ti = team_idx(a.lanes_log2);
+    const int R = a.R;
+    const int rb = (blockIdx.y * ti.L + ti.tl) * V;
+    const bool act = rb < R;
+    const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
+    MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
+    const StepScalars sc = a.sc;
+    double eacc[2 * V];
+#pragma unroll
+    for (int k = 0; k < 2 * V; ++k) eacc[k] = 0.0;
+    using Rec = typename SatRec<W>::T;
+    const Rec* __restrict__ inc = reinterpret_cast<const Rec*>(W == 2 ? (const void*)a.inc2 : (const void*)a.inc4);
+
+    if (act) {
+        for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
+            const size_t base = (size_t)i * R + rb;
+            float hv[V], m1v[V], m2v[V];
+            ld_f32<V>(a.h + base, hv);
+            float own_small[V];
+            bool own_hi[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float e = expf(-fabsf(hv[v]));
+                own_small[v] = e / (1.0f + e);
+                own_hi[v] = hv[v] > 0.0f;
+            }
+            float d[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) d[v] = 0.0f;
+            const int64_t kend = a.row_off[i + 1];
+            for (int64_t k = a.row_off[i]; k < kend; ++k) {
+                const Rec rec = inc[k];
+                uint32_t lit[W];
+                bool own_pos, owner;
+                if constexpr (W == 2) {
+                    lit[0] = (uint32_t)rec.x; lit[1] = (uint32_t)rec.y;
+                    own_pos = (lit[0] & SAT_FLAG) != 0;
+                    owner = (lit[1] & SAT_FLAG) != 0;
+                } else {
+                    lit[0] = (uint32_t)rec.x; lit[1] = (uint32_t)rec.y; lit[2] = (uint32_t)rec.z;
+                    own_pos = (rec.w & 1) != 0;
+                    owner = (rec.w & 2) != 0;
+                }
+                float c[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) c[v] = 1.0f;
+#pragma unroll
+                for (int s = 0; s < W; ++s) {
+                    const uint32_t var = lit[s] & SAT_VAR_MASK;
+                    if (var != SAT_NONE) {
+                        float x[V];
+                        ld_marg<MT, V>(mc + (size_t)var * R + rb, x);
+                        const bool pos = (lit[s] & SAT_POS) != 0;
+#pragma unroll
+                        for (int v = 0; v < V; ++v) c[v] *= sat_u(x[v], pos);
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    d[v] += own_pos ? -c[v] : c[v];
+                    if constexpr (EN) {
+                        if (owner) {
+                            const float uo = (own_pos == own_hi[v]) ? own_small[v] : 1.0f - own_small[v];
+                            eacc[v] += (double)(uo * c[v]);
+                        }
+                    }
+                }
+            }
+            ld_f32<V>(a.m1 + base, m1v);
+            ld_f32<V>(a.m2 + base, m2v);
+            float gv[V], snew[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float x = hv[v];
+                const float ax = fabsf(x);
+                const float e = expf(-ax);
+                const float ope = 1.0f + e;
+                const float pq = e / (ope * ope);
+                const float g = pq * (d[v] + x * sc.inv_beta);
+                gv[v] = g;
+                if constexpr (EN) eacc[V + v] += (double)(log1pf(e) + ax * (e / ope));
+                const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
+                hv[v] = nh;
+                snew[v] = sat_encode(nh);
+            }
+            st_f32<V>(a.h + base, hv);
+            st_f32<V>(a.m1 + base, m1v);
+            st_f32<V>(a.m2 + base, m2v);
+            st_marg<MT, V>(mn + base, snew);
+            if (a.grad) st_f32<V>(a.grad + base, gv);
+        }
+    }
+    if constexpr (EN) {
+        extern __shared__ double lds_d[];
+        block_reduce_store<double, 2 * V>(eacc, ti, a.lanes_log2, lds_d, [&](int k, int l, double s) {
+            const int term = k / V, v = k % V;
+            const int r = (blockIdx.y * ti.L + l) * V + v;
+            if (r < R) a.epart[((size_t)tile.slot * 2 + term) * R + r] = s;
+        });
+    }
+}
+
+// ================================================== marginal initialisation
+// Writes the marginal copy of the current fields (m = tanh(h/2), the SAT
+// encoding, or the softmax) into marg_nxt; for Potts also the column-sum
+// partials of those marginals.
+template <typename MT>
+__global__ void init_q1_kernel(int kind, const float* __restrict__ h, MT* __restrict__ out, size_t count)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
+        float x[1] = {kind == KIND_MAXSAT ? sat_encode(h[k]) : tanhf(0.5f * h[k])};
+        st_marg<MT, 1>(out + k, x);
+    }
+}
+
+template <int Q, typename MT>
+__global__ void __launch_bounds__(1024) potts_init_kernel(StepArgs a)
+{
+    const Tile tile = a.tiles[blockIdx.x];
+    const TeamIdx ti = team_idx(a.lanes_log2);
+    const int R = a.R;
+    const int r = blockIdx.y * ti.L + ti.tl;
+    const bool act = r < R;
+    MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
+    long long cs[Q];
+#pragma unroll
+    for (int s = 0; s < Q; ++s) cs[s] = 0;
+    if (act) {
+        for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
+            const size_t base = ((size_t)i * R + r) * Q;
+            float hv[Q];
+            ld_f32<Q>(a.h + base, hv);
+            float mx = hv[0];
+#pragma unroll
+            for (int s = 1; s < Q; ++s) mx = fmaxf(mx, hv[s]);
+            float P[Q], Z = 0.0f;
+#pragma unroll
+            for (int s = 0; s < Q; ++s) { P[s] = expf(hv[s] - mx); Z += P[s]; }
+            const float invZ = 1.0f / Z;
+#pragma unroll
+            for (int s = 0; s < Q; ++s) { P[s] *= invZ; cs[s] += to_fixed(P[s]); }
+            st_marg<MT, Q>(mn + base, P);
+        }
+    }
+    extern __shared__ double lds_d[];
+    block_reduce_store<long long, Q>(cs, ti, a.lanes_log2, reinterpret_cast<long long*>(lds_d),
+                                     [&](int s, int l, long long v) {
+                                         const int rr = blockIdx.y * ti.L + l;
+                                         if (rr < R) a.cpart[((size_t)tile.slot * R + rr) * Q + s] = v;
+                                     });
+}
+
+// ============================================== segmented tile reductions ==
+// out[seg][c] = sum_{t in [seg_off[seg], seg_off[seg+1])} part[t][c], in a
+// fixed order: eight sub-sums over t = t0+sub, t0+sub+8, ..., then sub 0..7.
+template <typename T>
+__global__ void __launch_bounds__(256) seg_reduce_kernel(const T* __restrict__ part, int cols,
+                                                         const int32_t* __restrict__ seg_off,
+                                                         T* __restrict__ out)
+{
+    __shared__ T lds[256];
+    const int seg = blockIdx.x;
+    const int c = blockIdx.y * 32 + (threadIdx.x & 31);
+    const int sub = threadIdx.x >> 5;
+    const int t0 = seg_off[seg], t1 = seg_off[seg + 1];
+    T acc = 0;
+    if (c < cols)
+        for (int t = t0 + sub; t < t1; t += 8) acc += part[(size_t)t * cols + c];
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    if (sub == 0 && c < cols) {
+        T v = lds[threadIdx.x];
+#pragma unroll
+        for (int s = 1; s < 8; ++s) v += lds[s * 32 + threadIdx.x];
+        out[(size_t)seg * cols + c] = v;
+    }
+}
+
+template <typename T>
+static hipError_t seg_reduce2(const T* part, int cols, const int32_t* chunk_off, int n_chunks,
+                              const int32_t* inst_chunk_off, int n_inst, T* tmp, T* out, hipStream_t st)
+{
+    dim3 g1(n_chunks, (cols + 31) / 32);
+    seg_reduce_kernel<T><<<g1, 256, 0, st>>>(part, cols, chunk_off, tmp);
+    dim3 g2(n_inst, (cols + 31) / 32);
+    seg_reduce_kernel<T><<<g2, 256, 0, st>>>(tmp, cols, inst_chunk_off, out);
+    return hipGetLastError();
+}
+
+// energies: raw[inst][NE][R] -> eout[inst][3][R] = U, S, F
+__global__ void energy_combine_kernel(int kind, int R, int q, int n_inst, const double* __restrict__ raw,
+                                      const double* __restrict__ wtot, const double* __restrict__ csum,
+                                      double lam, double beta, double* __restrict__ eout)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_inst * R) return;
+    const int inst = idx / R, r = idx % R;
+    double U, S;
+    if (kind == KIND_MAXCUT) {
+        const double* x = raw + (size_t)inst * 2 * R;
+        U = -wtot[inst] + 0.5 * x[r];
+        S = x[R + r];
+    } else if (kind == KIND_MAXSAT) {
+        const double* x = raw + (size_t)inst * 2 * R;
+        U = x[r];
+        S = x[R + r];
+    } else {
+        const double* x = raw + (size_t)inst * 3 * R;
+        const double* C = csum + ((size_t)inst * R + r) * q;
+        double c2 = 0.0;
+        for (int s = 0; s < q; ++s) c2 += C[s] * C[s];
+        U = x[r] + lam * (c2 - x[R + r]);
+        S = x[2 * R + r];
+    }
+    double* o = eout + (size_t)inst * 3 * R;
+    o[r] = U;
+    o[R + r] = S;
+    o[2 * R + r] = U - S / beta;
+}
+
+// column sums: fixed point -> C (double) and centred C~ (float)
+__global__ void colsum_combine_kernel(int R, int q, int n_inst, const long long* __restrict__ fx,
+                                      double* __restrict__ csum, float* __restrict__ ctil)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_inst * R) return;
+    const long long* x = fx + (size_t)idx * q;
+    double mean = 0.0;
+    for (int s = 0; s < q; ++s) {
+        const double c = (double)x[s] * 0x1p-40;
+        csum[(size_t)idx * q + s] = c;
+        mean += c;
+    }
+    mean /= q;
+    for (int s = 0; s < q; ++s) ctil[(size_t)idx * q + s] = (float)(csum[(size_t)idx * q + s] - mean);
+}
+
+// ================================================ read-out & evaluation ===
+// sigma[i][r] = argmax_s h_i^r(s), ties to the lowest state; one logit: h > 0.
+__global__ void round_kernel(int kind, int32_t n, int32_t R, int32_t q, const float* __restrict__ h,
+                             uint8_t* __restrict__ sigma)
+{
+    const size_t count = (size_t)n * R;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
+        if (kind != KIND_BMINCUT) {
+            sigma[k] = h[k] > 0.0f ? 1 : 0;
+        } else {
+            const float* x = h + k * q;
+            int best = 0;
+            float bv = x[0];
+            for (int s = 1; s < q; ++s)
+                if (x[s] > bv) { bv = x[s]; best = s; }
+            sigma[k] = (uint8_t)best;
+        }
+    }
+}
+
+// host [R][n] int32 -> device [n][R] uint8
+__global__ void transpose_sigma_kernel(int32_t n, int32_t R, const int32_t* __restrict__ in, uint8_t* __restrict__ out)
+{
+    const size_t count = (size_t)n * R;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = k / R, r = k % R;
+        out[k] = (uint8_t)in[r * (size_t)n + i];
+    }
+}
+
+// Ordered cut sum_{j in N(i)} W_ij [sigma_i != sigma_j] per replica (graphs),
+// group sizes (bMinCut), or unsatisfied clauses counted at owner incidences
+// (Max-k-SAT).  One lane per replica.
+template <int Q>
+__global__ void __launch_bounds__(1024) eval_graph_kernel(const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
+                                                         const Tile* __restrict__ tiles, int32_t R, int lanes_log2,
+                                                         const uint8_t* __restrict__ sigma, double* __restrict__ vpart,
+                                                         int* __restrict__ spart)
+{
+    const Tile tile = tiles[blockIdx.x];
+    const TeamIdx ti = team_idx(lanes_log2);
+    const int r = blockIdx.y * ti.L + ti.tl;
+    const bool act = r < R;
+    double acc[1] = {0.0};
+    int cnt[Q];
+#pragma unroll
+    for (int s = 0; s < Q; ++s) cnt[s] = 0;
+    if (act) {
+        for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
+            const uint8_t si = sigma[(size_t)i * R + r];
+            if constexpr (Q > 1) {
+#pragma unroll
+                for (int s = 0; s < Q; ++s) cnt[s] += (si == s) ? 1 : 0;
+            }
+            for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
+                const int2 e = adj[k];
+                if (sigma[(size_t)e.x * R + r] != si) acc[0] += (double)__int_as_float(e.y);
+            }
+        }
+    }
+    extern __shared__ double lds_d[];
+    block_reduce_store<double, 1>(acc, ti, lanes_log2, lds_d, [&](int, int l, double s) {
+        const int rr = blockIdx.y * ti.L + l;
+        if (rr < R) vpart[(size_t)tile.slot * R + rr] = s;
+    });
+    if constexpr (Q > 1) {
+        block_reduce_store<int, Q>(cnt, ti, lanes_log2, reinterpret_cast<int*>(lds_d), [&](int s, int l, int v) {
+            const int rr = blockIdx.y * ti.L + l;
+            if (rr < R) spart[((size_t)tile.slot * R + rr) * Q + s] = v;
+        });
+    }
+}
+
+template <int W>
+__global__ void __launch_bounds__(1024) eval_sat_kernel(const int64_t* __restrict__ row_off, const void* __restrict__ incv,
+                                                       const Tile* __restrict__ tiles, int32_t R, int lanes_log2,
+                                                       const uint8_t* __restrict__ sigma, double* __restrict__ vpart)
+{
+    using Rec = typename SatRec<W>::T;
+    const Rec* inc = reinterpret_cast<const Rec*>(incv);
+    const Tile tile = tiles[blockIdx.x];
+    const TeamIdx ti = team_idx(lanes_log2);
+    const int r = blockIdx.y * ti.L + ti.tl;
+    const bool act = r < R;
+    double acc[1] = {0.0};
+    if (act) {
+        for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
+            const uint8_t si = sigma[(size_t)i * R + r];
+            for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
+                const Rec rec = inc[k];
+                uint32_t lit[W];
+                bool own_pos, owner;
+                if constexpr (W == 2) {
+                    lit[0] = (uint32_t)rec.x; lit[1] = (uint32_t)rec.y;
+                    own_pos = (lit[0] & SAT_FLAG) != 0;
+                    owner = (lit[1] & SAT_FLAG) != 0;
+                } else {
+                    lit[0] = (uint32_t)rec.x; lit[1] = (uint32_t)rec.y; lit[2] = (uint32_t)rec.z;
+                    own_pos = (rec.w & 1) != 0;
+                    owner = (rec.w & 2) != 0;
+                }
+                if (!owner) continue;
+                bool all_false = own_pos ? (si == 0) : (si == 1);
+#pragma unroll
+                for (int s = 0; s < W; ++s) {
+                    const uint32_t var = lit[s] & SAT_VAR_MASK;
+                    if (var != SAT_NONE) {
+                        const uint8_t sv = sigma[(size_t)var * R + r];
+                        const bool pos = (lit[s] & SAT_POS) != 0;
+                        all_false = all_false && (pos ? (sv == 0) : (sv == 1));
+                    }
+                }
+                acc[0] += all_false ? 1.0 : 0.0;
+            }
+        }
+    }
+    extern __shared__ double lds_d[];
+    block_reduce_store<double, 1>(acc, ti, lanes_log2, lds_d, [&](int, int l, double s) {
+        const int rr = blockIdx.y * ti.L + l;
+        if (rr < R) vpart[(size_t)tile.slot * R + rr] = s;
+    });
+}
+
+// values[inst][R] (double) and sizes[inst][R][q] (int64 from int) finished
+__global__ void sizes_widen_kernel(size_t count, const int* __restrict__ in, long long* __restrict__ out)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x)
+        out[k] = in[k];
+}
+
+// anytime best: best[inst][r] <- better of best and the value just evaluated.
+// MaxCut: cut = ordered / 2, larger is better; Max-k-SAT: fewer unsat;
+// bMinCut: integer energy 2 cut + lam sum_s |Pi_s| (|Pi_s| - 1), lower.
+__global__ void best_update_kernel(int kind, int R, int n_inst, int q, double lam, const double* __restrict__ v,
+                                   const long long* __restrict__ sz, double* __restrict__ best)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_inst * R) return;
+    double score;
+    if (kind == KIND_MAXCUT) {
+        score = -0.5 * v[idx];
+    } else if (kind == KIND_MAXSAT) {
+        score = v[idx];
+    } else {
+        double pen = 0.0;
+        for (int s = 0; s < q; ++s) {
+            const double c = (double)sz[(size_t)idx * q + s];
+            pen += c * (c - 1.0);
+        }
+        score = v[idx] + lam * pen;   // ordered cut = 2 cut
+    }
+    if (score < best[idx]) best[idx] = score;
+}
+
+// ============================================================ launchers ===
+// LDS for block_reduce_store: waves * L * K values of 8 bytes.
+static inline size_t lds_bytes(int waves, int L, int K) { return (size_t)waves * L * K * 8; }
+
+template <int V, typename MT>
+static void launch_maxcut(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStream_t st)
+{
+    if (en) maxcut_step_kernel<V, MT, true><<<g, b, lds_bytes(b.x / 64, L, 2 * V), st>>>(a);
+    else maxcut_step_kernel<V, MT, false><<<g, b, 0, st>>>(a);
+}
+template <int V, typename MT, int W>
+static void launch_sat(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStream_t st)
+{
+    if (en) sat_step_kernel<V, MT, W, true><<<g, b, lds_bytes(b.x / 64, L, 2 * V), st>>>(a);
+    else sat_step_kernel<V, MT, W, false><<<g, b, 0, st>>>(a);
+}
+template <int Q, typename MT>
+static void launch_potts(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStream_t st)
+{
+    const size_t lds = lds_bytes(b.x / 64, L, Q > 3 ? Q : 3);
+    if (en) potts_step_kernel<Q, MT, true><<<g, b, lds, st>>>(a);
+    else potts_step_kernel<Q, MT, false><<<g, b, lds, st>>>(a);
+}
+
+template <typename MT>
+static hipError_t launch_step_t(int kind, int vec, const LaunchGeom& geo, int waves, const StepArgs& a,
+                                hipStream_t st)
+{
+    dim3 g(geo.n_tiles, geo.nseg), b(64 * waves);
+    const int L = geo.lanes;
+    const bool en = a.epart != nullptr;
+    if (kind == KIND_MAXCUT) {
+        switch (vec) {
+        case 1: launch_maxcut<1, MT>(en, g, b, L, a, st); break;
+        case 2: launch_maxcut<2, MT>(en, g, b, L, a, st); break;
+        case 4: launch_maxcut<4, MT>(en, g, b, L, a, st); break;
+        case 8: launch_maxcut<8, MT>(en, g, b, L, a, st); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else if (kind == KIND_MAXSAT) {
+        const bool w2 = a.inc2 != nullptr;
+        switch (vec) {
+        case 1: w2 ? launch_sat<1, MT, 2>(en, g, b, L, a, st) : launch_sat<1, MT, 3>(en, g, b, L, a, st); break;
+        case 2: w2 ? launch_sat<2, MT, 2>(en, g, b, L, a, st) : launch_sat<2, MT, 3>(en, g, b, L, a, st); break;
+        case 4: w2 ? launch_sat<4, MT, 2>(en, g, b, L, a, st) : launch_sat<4, MT, 3>(en, g, b, L, a, st); break;
+        case 8: w2 ? launch_sat<8, MT, 2>(en, g, b, L, a, st) : launch_sat<8, MT, 3>(en, g, b, L, a, st); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (a.q) {
+        case 2: launch_potts<2, MT>(en, g, b, L, a, st); break;
+        case 4: launch_potts<4, MT>(en, g, b, L, a, st); break;
+        case 8: launch_potts<8, MT>(en, g, b, L, a, st); break;
+        case 16: launch_potts<16, MT>(en, g, b, L, a, st); break;
+        case 32: launch_potts<32, MT>(en, g, b, L, a, st); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int kind, int dtype, int vec, const LaunchGeom& g, int waves, const StepArgs& a,
+                       hipStream_t st)
+{
+    if (dtype == 1) return launch_step_t<uint16_t>(kind, vec, g, waves, a, st);
+    return launch_step_t<float>(kind, vec, g, waves, a, st);
+}
+
+template <typename MT>
+static hipError_t launch_potts_init_t(const LaunchGeom& geo, int waves, const StepArgs& a, hipStream_t st)
+{
+    dim3 g(geo.n_tiles, geo.nseg), b(64 * waves);
+    const size_t lds = lds_bytes(waves, geo.lanes, a.q);
+    switch (a.q) {
+    case 2: potts_init_kernel<2, MT><<<g, b, lds, st>>>(a); break;
+    case 4: potts_init_kernel<4, MT><<<g, b, lds, st>>>(a); break;
+    case 8: potts_init_kernel<8, MT><<<g, b, lds, st>>>(a); break;
+    case 16: potts_init_kernel<16, MT><<<g, b, lds, st>>>(a); break;
+    case 32: potts_init_kernel<32, MT><<<g, b, lds, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static inline int grid_for(size_t count)
+{
+    const size_t b = (count + 255) / 256;
+    return (int)(b < 65536 ? (b ? b : 1) : 65536);
+}
+
+hipError_t launch_init_marginals(int kind, int dtype, const LaunchGeom& g, int waves, const StepArgs& a,
+                                 size_t count, hipStream_t st)
+{
+    if (kind == KIND_BMINCUT) {
+        if (dtype == 1) return launch_potts_init_t<uint16_t>(g, waves, a, st);
+        return launch_potts_init_t<float>(g, waves, a, st);
+    }
+    if (count == 0) return hipSuccess;
+    if (dtype == 1)
+        init_q1_kernel<uint16_t><<<grid_for(count), 256, 0, st>>>(kind, a.h, static_cast<uint16_t*>(a.marg_nxt), count);
+    else
+        init_q1_kernel<float><<<grid_for(count), 256, 0, st>>>(kind, a.h, static_cast<float*>(a.marg_nxt), count);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_seg_reduce(const T* part, int cols, const int32_t* chunk_off, int n_chunks,
+                             const int32_t* inst_chunk_off, int n_inst, T* tmp, T* out, hipStream_t st)
+{
+    return seg_reduce2<T>(part, cols, chunk_off, n_chunks, inst_chunk_off, n_inst, tmp, out, st);
+}
+template hipError_t launch_seg_reduce<double>(const double*, int, const int32_t*, int, const int32_t*, int,
+                                              double*, double*, hipStream_t);
+template hipError_t launch_seg_reduce<long long>(const long long*, int, const int32_t*, int, const int32_t*, int,
+                                                 long long*, long long*, hipStream_t);
+template hipError_t launch_seg_reduce<int>(const int*, int, const int32_t*, int, const int32_t*, int, int*, int*,
+                                           hipStream_t);
+
+hipError_t launch_energy_combine(int kind, int R, int q, int n_inst, const double* raw, const double* wtot,
+                                 const double* csum, double lam, double beta, double* eout, hipStream_t st)
+{
+    const int n = n_inst * R;
+    energy_combine_kernel<<<(n + 255) / 256, 256, 0, st>>>(kind, R, q, n_inst, raw, wtot, csum, lam, beta, eout);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, double* csum, float* ctil,
+                                 hipStream_t st)
+{
+    const int n = n_inst * R;
+    colsum_combine_kernel<<<(n + 255) / 256, 256, 0, st>>>(R, q, n_inst, fx, csum, ctil);
+    return hipGetLastError();
+}
+
+hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h, uint8_t* sigma, hipStream_t st)
+{
+    const size_t count = (size_t)n * R;
+    if (count == 0) return hipSuccess;
+    round_kernel<<<grid_for(count), 256, 0, st>>>(kind, n, R, q, h, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_sigma(int32_t n, int32_t R, const int32_t* sig_rn, uint8_t* sig_nr, hipStream_t st)
+{
+    const size_t count = (size_t)n * R;
+    if (count == 0) return hipSuccess;
+    transpose_sigma_kernel<<<grid_for(count), 256, 0, st>>>(n, R, sig_rn, sig_nr);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const Problem& p, const LaunchGeom& geo, int waves, const Tile* tiles, int32_t R,
+                       const uint8_t* sigma, double* vpart, int* spart, hipStream_t st)
+{
+    dim3 g(geo.n_tiles, geo.nseg), b(64 * waves);
+    int lanes_log2 = 0;
+    while ((1 << lanes_log2) < geo.lanes) ++lanes_log2;
+    const int L = geo.lanes;
+    if (p.kind == KIND_MAXSAT) {
+        const size_t lds = lds_bytes(waves, L, 1);
+        if (p.sat_width == 2)
+            eval_sat_kernel<2><<<g, b, lds, st>>>(p.row_off, (const void*)p.inc2, tiles, R, lanes_log2, sigma, vpart);
+        else
+            eval_sat_kernel<3><<<g, b, lds, st>>>(p.row_off, (const void*)p.inc4, tiles, R, lanes_log2, sigma, vpart);
+    } else if (p.kind == KIND_MAXCUT) {
+        eval_graph_kernel<1><<<g, b, lds_bytes(waves, L, 1), st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma,
+                                                                    vpart, spart);
+    } else {
+        const size_t lds = lds_bytes(waves, L, p.q);
+        switch (p.q) {
+        case 2: eval_graph_kernel<2><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        case 4: eval_graph_kernel<4><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        case 8: eval_graph_kernel<8><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        case 16: eval_graph_kernel<16><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        case 32: eval_graph_kernel<32><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sizes_widen(size_t count, const int* in, long long* out, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    sizes_widen_kernel<<<grid_for(count), 256, 0, st>>>(count, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_best_update(int kind, int R, int n_inst, int q, double lam, const double* vout,
+                              const long long* sout, double* best, hipStream_t st)
+{
+    const int n = n_inst * R;
+    best_update_kernel<<<(n + 255) / 256, 256, 0, st>>>(kind, R, n_inst, q, lam, vout, sout, best);
+    return hipGetLastError();
+}
+
+}  // namespace fem

@@ -1,0 +1,167 @@
+"""GPU parity of the MaxCut hot path against the FP64 oracle (through the C ABI).
+
+Every input comes from the seeded generators; both sides start from the same
+h0 and run independently (free-running); nothing from the GPU is fed to the
+oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2412_09285_amd import fem
+from paper_2412_09285_amd import workloads as W
+from _parity import assert_energy_close, assert_grad_close, grad_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def free_run(graph, R, T, n_steps, seed, dtype=fem.F32, tile=None, lr=0.1):
+    h0 = W.initial_fields(graph.n, R, seed)
+    prob = fem.Problem.maxcut(graph.n, graph.u, graph.v, graph.w)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1, record_energies=1,
+                                            marginal_dtype=dtype, lr=lr))
+    if tile is not None:
+        s.set_tile(*tile)
+    s.set_fields(h0)
+    grads = []
+    for _ in range(n_steps):
+        s.step(1)
+        grads.append(s.last_grad())
+    U, S, F = s.energy_history(0, n_steps)
+    h = s.fields()
+    run = O.maxcut_run(graph, O.Params(R=R, T=T, lr=lr), h0)
+    gh, Uh, Sh = run.step(n_steps, record=True)
+    betas = np.array([O.beta(0, 0.01, 5.0, T, t) for t in range(n_steps)])
+    return dict(grads=np.array(grads), U=U[:, 0], S=S[:, 0], F=F[:, 0], h=h, gref=gh, Uref=Uh, Sref=Sh,
+                href=run.h, betas=betas, solver=s, prob=prob)
+
+
+def check_run(res, R, tag):
+    worst = [0.0, 0.0, 0.0]
+    for t in range(res["grads"].shape[0]):
+        a, b = assert_grad_close(res["grads"][t], res["gref"][t], R, what=f"{tag} g step {t}")
+        worst[0] = max(worst[0], a, b)
+        e = assert_energy_close(res["U"][t], res["S"][t], res["F"][t], res["Uref"][t], res["Sref"][t],
+                                res["betas"][t], what=f"{tag} energies step {t}")
+        worst[1] = max(worst[1], *e)
+    rel, mx = grad_errors(res["h"], res["href"], R)
+    worst[2] = max(rel.max(), mx.max())
+    assert worst[2] <= 1e-5, f"{tag}: h rel {rel.max():.3e} max {mx.max():.3e}"
+    print(f"[{tag}] worst rel error: grad {worst[0]:.2e}, energies {worst[1]:.2e}, h {worst[2]:.2e}", flush=True)
+
+
+def test_config1_first_100_steps():
+    """ER N=800, 19,176 edges, W=+1, R=16, T=500: the first 100 steps."""
+    g = W.config_graph(1)
+    res = free_run(g, R=16, T=500, n_steps=100, seed=101)
+    check_run(res, 16, "C1")
+
+
+@pytest.mark.parametrize("R,n", [(1, 97), (3, 333), (64, 517), (256, 211), (1024, 70)])
+def test_ragged_shapes(R, n):
+    """Several tiles with a ragged tail, odd replica counts and more than one
+    replica segment per row (R = 1024)."""
+    g = W.random_sparse_graph(n, 4 * n, seed=n, weights="pm1")
+    res = free_run(g, R=R, T=200, n_steps=25, seed=7 + R)
+    check_run(res, R, f"n{n}_R{R}")
+
+
+def test_isolated_nodes_and_tiny_graphs():
+    # node 5 and 6 isolated, a single edge elsewhere
+    g = W.Graph(7, np.array([0, 1, 2], np.int32), np.array([1, 2, 3], np.int32), np.array([1, -2, 3], np.float32))
+    res = free_run(g, R=8, T=50, n_steps=10, seed=3)
+    check_run(res, 8, "isolated")
+    g1 = W.Graph(1, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    res = free_run(g1, R=4, T=10, n_steps=5, seed=4)
+    check_run(res, 4, "single node")
+
+
+@pytest.mark.parametrize("vec,waves,rows", [(1, 1, 1), (2, 8, 3), (4, 2, 16), (8, 4, 4)])
+def test_every_tile_shape_matches_oracle(vec, waves, rows):
+    g = W.random_sparse_graph(900, 2700, seed=5, weights="pm1")
+    res = free_run(g, R=64, T=100, n_steps=15, seed=9, tile=(vec, waves, rows))
+    check_run(res, 64, f"tile{vec}x{waves}x{rows}")
+
+
+def test_integer_eval_bitexact():
+    rng = np.random.default_rng(0)
+    g = W.random_sparse_graph(1500, 6000, seed=11, weights="pm1")
+    g.w = rng.integers(-5, 6, size=g.n_edges).astype(np.float32)
+    g.w[g.w == 0] = 7
+    prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
+    sigma = rng.integers(0, 2, size=(37, g.n)).astype(np.int32)
+    vals, _ = prob.eval_int(sigma)
+    ref = O.cut(g.n, g.u, g.v, g.w, sigma)
+    assert np.array_equal(vals[0], ref.astype(np.int64))
+
+
+def test_round_and_best_on_seeded_fields_with_ties():
+    """Fields with exact zeros: sigma = 1 iff h > 0 on both sides; the best
+    replica (ties to the lowest index) and its cut agree exactly."""
+    g = W.config_graph(1)
+    R = 16
+    h = W.initial_fields(g.n, R, seed=77)
+    h[::7] = 0.0
+    prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=10))
+    s.set_fields(h)
+    sig = s.round()
+    sig_ref = O.round_(h.astype(np.float64), 1)
+    assert np.array_equal(sig, sig_ref)
+    rep, val, best_sig = s.best()
+    cuts = O.cut(g.n, g.u, g.v, g.w, sig_ref)
+    assert rep[0] == int(np.argmax(cuts)) and val[0] == int(cuts.max())
+    assert np.array_equal(best_sig, sig_ref[rep[0]])
+
+
+def test_config2_full_size_one_step_sampled():
+    """N=100,000, 300,000 edges (+/-1), R=256 in the tuned launch shape: one
+    step; the oracle recomputes four sampled replicas at full size."""
+    g = W.config_graph(2)
+    R, T = 256, 2000
+    h0 = W.initial_fields(g.n, R, seed=102)
+    prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1))
+    s.set_fields(h0)
+    s.tune(trial_steps=3, use_cache=True)
+    s.set_fields(h0)
+    for step in range(2):
+        s.step(1)
+        gg = s.last_grad()
+        U, S, F = s.energies()
+        cols = [0, 1, 128, 255]
+        hs = h0[:, cols] if step == 0 else hs_next
+        run = O.maxcut_run(g, O.Params(R=len(cols), T=T), hs)
+        run.t = step
+        if step == 1:
+            run.m1, run.m2 = m1s, m2s
+        gh, Uh, Sh = run.step(1, record=True)
+        assert_grad_close(gg[:, cols], gh[0], len(cols), what=f"C2 step {step}")
+        assert_energy_close(U[0, cols], S[0, cols], F[0, cols], Uh[0], Sh[0], O.beta(0, 0.01, 5.0, T, step))
+        hs_next, m1s, m2s = run.h.copy(), run.m1.copy(), run.m2.copy()
+    print(f"[C2 full] tile {s.tile()}", flush=True)
+
+
+def test_bf16_marginals_gradient_bound():
+    """BF16 storage of m = tanh(h/2) changes each gathered value by at most
+    2^-9 |m_j| (round to nearest, 8 significant bits), so
+    |g_bf16 - g| <= P(1-P) * 2 * sum_j |W_ij| |m_j| 2^-9 on top of the float32
+    rounding.  Checked on the first steps of C1 against the FP64 oracle; the
+    free-running error over 100 steps is printed, not asserted."""
+    g = W.config_graph(1)
+    R, T = 16, 500
+    res = free_run(g, R=R, T=T, n_steps=100, seed=101, dtype=fem.BF16)
+    h0 = W.initial_fields(g.n, R, seed=101).astype(np.float64)
+    # bound at step 0, where both sides evaluate the same h0
+    m = np.tanh(h0 / 2)
+    absW = np.zeros(g.n)
+    phi_abs = np.zeros((g.n, R))
+    np.add.at(phi_abs, g.u, np.abs(g.w)[:, None] * np.abs(m[g.v]))
+    np.add.at(phi_abs, g.v, np.abs(g.w)[:, None] * np.abs(m[g.u]))
+    p = 1 / (1 + np.exp(-h0))
+    bound = p * (1 - p) * 2 * phi_abs * 2.0 ** -9 + 1e-5 * np.abs(res["gref"][0]).max()
+    err = np.abs(res["grads"][0] - res["gref"][0])
+    assert np.all(err <= bound), float((err - bound).max())
+    rel, mx = grad_errors(res["grads"][-1], res["gref"][-1], R)
+    hrel, _ = grad_errors(res["h"], res["href"], R)
+    print(f"[C1 bf16] step-99 grad rel err {rel.max():.2e}, h(100) rel err {hrel.max():.2e}", flush=True)
