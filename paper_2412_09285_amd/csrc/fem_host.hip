@@ -395,6 +395,7 @@ static bool valid_shape(const fem_solver* s, const TileShape& t)
         if (t.vec != 1 && t.vec != 2 && t.vec != 4 && t.vec != 8) return false;
         if (s->R % t.vec != 0) return false;
     }
+    if (64 * t.waves > step_max_threads(s->kind, s->kind == KIND_BMINCUT ? s->q : t.vec)) return false;
     const LaunchGeom g = make_geom(per_lane, s->R, t.waves);
     const LaunchGeom ge = make_geom(1, s->R, t.waves);
     const int k_step = (s->kind == KIND_BMINCUT) ? std::max(s->q, 3) : 2 * t.vec;
@@ -906,6 +907,15 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     if (e != hipSuccess) return bail(fail(FEM_E_HIP, "hipSetDevice: %s", hipGetErrorString(e)));
     const size_t msz = s->dtype == FEM_BF16 ? 2 : 4;
     const size_t IR = (size_t)s->n_inst * s->R;
+    {
+        size_t free_b = 0, total_b = 0;
+        e = hipMemGetInfo(&free_b, &total_b);
+        if (e != hipSuccess) return bail(fail(FEM_E_HIP, "hipMemGetInfo: %s", hipGetErrorString(e)));
+        const double need = (double)s->vals * (12.0 + 2.0 * msz + (P.keep_grad ? 4.0 : 0.0));
+        if (need > (double)free_b)
+            return bail(fail(FEM_E_NOMEM, "solver state needs %.3g GB, %.3g GB free on device %d", need * 1e-9,
+                             free_b * 1e-9, p.device));
+    }
 #define ALLOC(ptr, cnt)                                                                                    \
     do {                                                                                                   \
         hipError_t ee = dalloc(&(ptr), (cnt));                                                             \
@@ -1418,7 +1428,7 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     if (steps_avail < 1) return fail(FEM_E_STATE, "no steps left to tune with");
     std::vector<TileShape> cands;
     const int vecs[4] = {1, 2, 4, 8};
-    const int wavess[3] = {2, 4, 8};
+    const int wavess[4] = {2, 4, 8, 16};
     const int rowss[4] = {1, 2, 4, 8};
     for (int vi = 0; vi < (s->kind == KIND_BMINCUT ? 1 : 4); ++vi)
         for (int wv : wavess)

@@ -54,6 +54,15 @@ constexpr uint32_t SAT_POS = 0x80000000u;
 // flag bits carried in bit 30 of the first / second slot
 constexpr uint32_t SAT_FLAG = 0x40000000u;   // slot0: own literal positive; slot1: owner incidence
 
+// Largest workgroup of a step kernel: register-heavy instantiations (8 values
+// per lane; Potts with q >= 8) get a smaller bound so that the compiler may use
+// up to 256 (512 threads) or 512 (256 threads) VGPRs without spilling.
+__host__ __device__ constexpr int step_max_threads(int kind, int per_lane)
+{
+    return kind == KIND_BMINCUT ? (per_lane >= 16 ? 256 : (per_lane >= 8 ? 512 : 1024))
+                                : (per_lane >= 8 ? 512 : 1024);
+}
+
 struct TileShape {
     int vec = 1, waves = 4, rows = 4;
 };

@@ -232,7 +232,7 @@ __device__ __forceinline__ void block_reduce_store(T (&v)[K], const TeamIdx& ti,
 // (1/2) sum_i m_i phi_i and S = sum_i H2(P_i), accumulated here as
 // [sum m phi, sum H2] per replica.
 template <int V, typename MT, bool EN>
-__global__ void __launch_bounds__(1024) maxcut_step_kernel(StepArgs a)
+__global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blockIdx.x];
     const TeamIdx ti = team_idx(a.lanes_log2);
@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(1024) maxcut_step_kernel(StepArgs a)
 // -sum_i P_i.ln P_i].  Column sums of the new marginals go out as 2^-40
 // fixed point.
 template <int Q, typename MT, bool EN>
-__global__ void __launch_bounds__(1024) potts_step_kernel(StepArgs a)
+__global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blockIdx.x];
     const TeamIdx ti = team_idx(a.lanes_log2);
@@ -467,7 +467,7 @@ struct SatRec<3> {
 };
 
 template <int V, typename MT, int W, bool EN>
-__global__ void __launch_bounds__(1024) sat_step_kernel(StepArgs a)
+__global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blockIdx.x];
     const TeamIdx ti = team_idx(a.lanes_log2);

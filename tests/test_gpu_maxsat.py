@@ -1,0 +1,141 @@
+"""GPU parity of the Max-k-SAT (clause-product gradient) hot path against the
+FP64 oracle, through the C ABI.  Seeded inputs only; free-running."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2412_09285_amd import fem
+from paper_2412_09285_amd import workloads as W
+from _parity import assert_energy_close, assert_grad_close, grad_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_cnf(n, M, seed):
+    """Clauses of 1..4 literals, with repeated literals and tautologies."""
+    rng = np.random.default_rng(seed)
+    clauses = []
+    for m in range(M):
+        k = int(rng.integers(1, 5))
+        vs = rng.choice(n, size=k, replace=False)
+        c = [int(x + 1) if rng.random() < 0.5 else -int(x + 1) for x in vs]
+        if m % 17 == 0:
+            c.append(c[0])           # repeated literal
+        if m % 29 == 0:
+            c.append(-c[0])          # tautology
+        clauses.append(c)
+    off = np.cumsum([0] + [len(c) for c in clauses]).astype(np.int64)
+    lits = np.array([x for c in clauses for x in c], dtype=np.int32)
+    return W.CNF(n, off, lits)
+
+
+def free_run(cnf, R, T, n_steps, seed, dtype=fem.F32, tile=None):
+    h0 = W.initial_fields(cnf.n_vars, R, seed)
+    prob = fem.Problem.maxsat(cnf.n_vars, cnf.clause_off, cnf.lits)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1, record_energies=1,
+                                            marginal_dtype=dtype))
+    if tile is not None:
+        s.set_tile(*tile)
+    s.set_fields(h0)
+    grads = []
+    for _ in range(n_steps):
+        s.step(1)
+        grads.append(s.last_grad())
+    U, S, F = s.energy_history(0, n_steps)
+    run = O.maxsat_run(cnf, O.Params(R=R, T=T), h0)
+    gh, Uh, Sh = run.step(n_steps, record=True)
+    betas = np.array([O.beta(0, 0.01, 5.0, T, t) for t in range(n_steps)])
+    return dict(grads=np.array(grads), U=U[:, 0], S=S[:, 0], F=F[:, 0], h=s.fields(), gref=gh, Uref=Uh,
+                Sref=Sh, href=run.h, betas=betas)
+
+
+def check_run(res, R, tag):
+    worst = [0.0, 0.0]
+    for t in range(res["grads"].shape[0]):
+        a, b = assert_grad_close(res["grads"][t], res["gref"][t], R, what=f"{tag} g step {t}")
+        e = assert_energy_close(res["U"][t], res["S"][t], res["F"][t], res["Uref"][t], res["Sref"][t],
+                                res["betas"][t], what=f"{tag} energies step {t}")
+        worst = [max(worst[0], a, b), max(worst[1], *e)]
+    rel, mx = grad_errors(res["h"], res["href"], R)
+    assert max(rel.max(), mx.max()) <= 1e-5, f"{tag}: h rel {rel.max():.3e} max {mx.max():.3e}"
+    print(f"[{tag}] worst rel error: grad {worst[0]:.2e}, energies {worst[1]:.2e}, h {max(rel.max(), mx.max()):.2e}",
+          flush=True)
+
+
+def test_random_3sat_first_100_steps():
+    """The Max-3-SAT recipe (ratio 8, distinct variables, fair signs) at
+    N = 2,000, R = 64."""
+    cnf = W.random_ksat(2000, 16000, 3, seed=4)
+    res = free_run(cnf, R=64, T=2000, n_steps=100, seed=104)
+    check_run(res, 64, "3sat2000")
+
+
+@pytest.mark.parametrize("R", [1, 16, 24])
+def test_mixed_lengths_repeats_tautologies(R):
+    cnf = mixed_cnf(300, 1500, seed=R)
+    res = free_run(cnf, R=R, T=300, n_steps=40, seed=R + 1)
+    check_run(res, R, f"mixed_R{R}")
+
+
+@pytest.mark.parametrize("vec,waves,rows", [(1, 2, 1), (2, 4, 5), (4, 8, 2)])
+def test_tile_shapes(vec, waves, rows):
+    cnf = W.random_ksat(1000, 8000, 3, seed=8)
+    res = free_run(cnf, R=64, T=100, n_steps=10, seed=5, tile=(vec, waves, rows))
+    check_run(res, 64, f"tile{vec}x{waves}x{rows}")
+
+
+def test_unsat_count_bitexact():
+    rng = np.random.default_rng(2)
+    for cnf in (W.random_ksat(3000, 24000, 3, seed=9), mixed_cnf(400, 3000, seed=3)):
+        prob = fem.Problem.maxsat(cnf.n_vars, cnf.clause_off, cnf.lits)
+        sigma = rng.integers(0, 2, size=(33, cnf.n_vars)).astype(np.int32)
+        vals, _ = prob.eval_int(sigma)
+        ref = O.unsat(cnf.n_vars, cnf.clause_off, cnf.lits, sigma)
+        assert np.array_equal(vals[0], ref)
+
+
+def test_paper_example_cnf():
+    """The worked CNF of the Max-k-SAT section: every assignment is counted as
+    the definition says, and the optimum is 0."""
+    clauses = [[1, -2, -2], [-1, 4], [2, -3, -4]]
+    off = np.cumsum([0] + [len(c) for c in clauses]).astype(np.int64)
+    lits = np.array([x for c in clauses for x in c], dtype=np.int32)
+    prob = fem.Problem.maxsat(4, off, lits)
+    import itertools
+
+    allsig = np.array(list(itertools.product((0, 1), repeat=4)), dtype=np.int32)
+    vals, _ = prob.eval_int(allsig)
+    assert np.array_equal(vals[0], O.unsat(4, off, lits, allsig))
+    assert vals.min() == 0
+
+
+def test_bf16_close():
+    cnf = W.random_ksat(2000, 16000, 3, seed=4)
+    res = free_run(cnf, R=64, T=2000, n_steps=30, seed=104, dtype=fem.BF16)
+    rel, _ = grad_errors(res["grads"][0], res["gref"][0], 64)
+    # stored min(P, 1-P) keeps 8 significant bits: each factor of a cavity
+    # product is off by <= 2^-9 relative
+    assert rel.max() < 4 * 2.0 ** -9, rel.max()
+    rel2, _ = grad_errors(res["grads"][-1], res["gref"][-1], 64)
+    print(f"[3sat bf16] step-0 grad rel {rel.max():.2e}, step-29 grad rel {rel2.max():.2e}", flush=True)
+
+
+def test_config4_full_size_one_step_sampled():
+    """N = 100,000 variables, M = 800,000 3-clauses, R = 64: one step in the
+    tuned launch shape; two replicas recomputed by the oracle at full size."""
+    cnf = W.config_cnf(4)
+    R, T = 64, 2000
+    h0 = W.initial_fields(cnf.n_vars, R, seed=104)
+    prob = fem.Problem.maxsat(cnf.n_vars, cnf.clause_off, cnf.lits)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1))
+    s.set_fields(h0)
+    s.tune(trial_steps=3, use_cache=True)
+    s.set_fields(h0)
+    s.step(1)
+    gg = s.last_grad()
+    U, S, F = s.energies()
+    cols = [0, 63]
+    gref, Uref, Sref = O.maxsat_grad(cnf.n_vars, cnf.clause_off, cnf.lits, h0[:, cols].astype(np.float64), 0.01)
+    assert_grad_close(gg[:, cols], gref, 2, what="C4")
+    assert_energy_close(U[0, cols], S[0, cols], F[0, cols], Uref, Sref, 0.01)
+    print(f"[C4 full] tile {s.tile()}", flush=True)
