@@ -132,7 +132,7 @@ def main():
     s.step(n_prof)
     kern_ms, n_k = s.profile_result()
     s.profile(False)
-    vec, waves, rows = tile
+    vec, waves, rows = tile[:3]
     lanes = min(64, 1 << (max(1, -(-R // vec)) - 1).bit_length())
     n_tiles = -(-g.n // (waves * (64 // lanes) * rows))
     mbytes = 2 if dtype == fem.BF16 else 4

@@ -135,7 +135,9 @@ typedef struct {
  * R = 16, T = 500, F32 marginals, energies every step, no recording. */
 void fem_params_default(fem_params* p);
 
-/* hip_stream: a hipStream_t on the problem's device (NULL = the null stream). */
+/* hip_stream: a hipStream_t on the problem's device (NULL = the null stream).
+ * The solver keeps a reference to the problem: fem_problem_destroy may be
+ * called while solvers still use it (the memory is released with the last). */
 fem_status fem_solver_create(const fem_problem* p, const fem_params* prm, void* hip_stream,
                              fem_solver** out);
 void fem_solver_destroy(fem_solver* s);
@@ -144,6 +146,12 @@ void fem_solver_destroy(fem_solver* s);
  * Adam moments to zero, the step counter t to 0, the anytime bests, and
  * recomputes the marginal copy. */
 fem_status fem_set_fields(fem_solver* s, const float* h, int on_device);
+
+/* Full optimiser state: fields h, Adam moments m1, m2 (all in the layout of
+ * h, float32, host or device) and the step counter t (0 <= t <= T); the
+ * marginal copy is recomputed.  Resumes an anneal from any state. */
+fem_status fem_set_adam_state(fem_solver* s, const float* h, const float* m1, const float* m2,
+                              int32_t t, int on_device);
 
 /* Enqueue n_steps annealing steps t -> t+1 (t + n_steps <= T).  Step t uses
  * beta(t), lambda(t) and Adam step count t+1; its gradient and energies are
@@ -201,10 +209,12 @@ fem_status fem_set_state(fem_solver* s, const void* buf, size_t bytes);
 
 /* --------------------------------------------------------------- tiling */
 /* Launch shape of the step kernels.  vec: values per lane along the replica
- * axis (1, 2, 4, 8; Potts uses q); waves: wavefronts per workgroup (1..16);
- * rows: rows per team per tile (1..64).  All shapes give bit-identical fields. */
+ * axis (1, 2, 4, 8; Potts uses q); waves: wavefronts per workgroup (1..16,
+ * fewer for register-heavy kernels); rows: rows per team per tile (1..64);
+ * nt: 1 = non-temporal loads and stores of h and the Adam moments.  All shapes
+ * give bit-identical fields. */
 typedef struct {
-    int32_t vec, waves, rows;
+    int32_t vec, waves, rows, nt;
 } fem_tile;
 fem_status fem_get_tile(const fem_solver* s, fem_tile* t);
 fem_status fem_set_tile(fem_solver* s, const fem_tile* t);

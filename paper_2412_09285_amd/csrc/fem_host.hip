@@ -70,9 +70,24 @@ static void dfree(T*& p)
 }
 
 // ---------------------------------------------------------------- problems --
+// Problems are reference counted: every solver holds one reference, so a
+// problem released by its owner stays alive until its last solver is gone.
 struct fem_problem {
     Problem p;
+    int refs = 0;
+    bool released = false;
 };
+
+static void free_problem_device(Problem& p);
+static void problem_unref(fem_problem* fp)
+{
+    if (!fp) return;
+    if (--fp->refs <= 0 && fp->released) {
+        (void)hipSetDevice(fp->p.device);
+        free_problem_device(fp->p);
+        delete fp;
+    }
+}
 
 static void free_problem_device(Problem& p)
 {
@@ -307,6 +322,7 @@ static fem_status build_sat(int device, int32_t n_vars, int64_t n_clauses, const
 
 // ------------------------------------------------------------------ solver --
 struct fem_solver {
+    fem_problem* owner = nullptr;   // holds one reference
     const Problem* prob = nullptr;
     fem_params prm{};
     hipStream_t stream = nullptr;
@@ -615,7 +631,7 @@ static fem_status do_step(fem_solver* s)
         ++s->prof_used;
         HIPCHK(hipEventRecord(e0, s->stream));
     }
-    HIPCHK(launch_step(s->kind, s->dtype, s->shape.vec, s->geo, s->shape.waves, a, s->stream));
+    HIPCHK(launch_step(s->kind, s->dtype, s->shape.vec, s->shape.nt != 0, s->geo, s->shape.waves, a, s->stream));
     if (e1) HIPCHK(hipEventRecord(e1, s->stream));
     if (en) {
         double* slot = energy_slot(s, t);
@@ -679,7 +695,9 @@ static void destroy_solver(fem_solver* s)
     dfree(s->sint);
     dfree(s->sout);
     dfree(s->best);
+    fem_problem* owner = s->owner;
     delete s;
+    problem_unref(owner);
 }
 
 static TileShape default_shape(int kind, int R)
@@ -829,9 +847,12 @@ fem_status fem_problem_instance_offsets(const fem_problem* fp, int32_t* offsets)
 void fem_problem_destroy(fem_problem* fp)
 {
     if (!fp) return;
-    (void)hipSetDevice(fp->p.device);
-    free_problem_device(fp->p);
-    delete fp;
+    fp->released = true;
+    if (fp->refs <= 0) {
+        (void)hipSetDevice(fp->p.device);
+        free_problem_device(fp->p);
+        delete fp;
+    }
 }
 
 void fem_params_default(fem_params* p)
@@ -879,6 +900,8 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
         return fail(FEM_E_NOMEM, "state of %lld values does not fit", (long long)p.n * P.replicas);
     auto* s = new (std::nothrow) fem_solver;
     if (!s) return fail(FEM_E_NOMEM, "host allocation failed");
+    s->owner = const_cast<fem_problem*>(fp);
+    s->owner->refs++;
     s->prob = &p;
     s->prm = P;
     s->stream = static_cast<hipStream_t>(hip_stream);
@@ -976,6 +999,24 @@ fem_status fem_set_fields(fem_solver* s, const float* h, int on_device)
     s->last_energy_step = -1;
     STCHK(init_marginals(s));
     STCHK(reset_best(s));
+    s->fields_set = true;
+    return FEM_OK;
+}
+
+fem_status fem_set_adam_state(fem_solver* s, const float* h, const float* m1, const float* m2, int32_t t,
+                              int on_device)
+{
+    if (!s || !h || !m1 || !m2) return fail(FEM_E_INVAL, "NULL argument");
+    if (t < 0 || t > s->prm.steps) return fail(FEM_E_INVAL, "step %d outside [0, %d]", t, s->prm.steps);
+    HIPCHK(hipSetDevice(s->prob->device));
+    const hipMemcpyKind kd = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(s->h, h, s->vals * 4, kd, s->stream));
+    HIPCHK(hipMemcpyAsync(s->m1, m1, s->vals * 4, kd, s->stream));
+    HIPCHK(hipMemcpyAsync(s->m2, m2, s->vals * 4, kd, s->stream));
+    s->t = t;
+    s->last_energy_step = -1;
+    STCHK(init_marginals(s));
+    HIPCHK(hipStreamSynchronize(s->stream));
     s->fields_set = true;
     return FEM_OK;
 }
@@ -1348,6 +1389,7 @@ fem_status fem_get_tile(const fem_solver* s, fem_tile* t)
     t->vec = s->kind == KIND_BMINCUT ? s->q : s->shape.vec;
     t->waves = s->shape.waves;
     t->rows = s->shape.rows;
+    t->nt = s->shape.nt;
     return FEM_OK;
 }
 
@@ -1358,6 +1400,8 @@ fem_status fem_set_tile(fem_solver* s, const fem_tile* t)
     sh.vec = s->kind == KIND_BMINCUT ? 1 : t->vec;
     sh.waves = t->waves;
     sh.rows = t->rows;
+    sh.nt = t->nt ? 1 : 0;
+    if (t->nt != 0 && t->nt != 1) return fail(FEM_E_INVAL, "nt must be 0 or 1");
     if (!valid_shape(s, sh)) return fail(FEM_E_INVAL, "invalid tile shape (vec %d, waves %d, rows %d) for R = %d", t->vec, t->waves, t->rows, s->R);
     HIPCHK(hipSetDevice(s->prob->device));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -1398,47 +1442,70 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
         FILE* f = std::fopen(path.c_str(), "r");
         if (f) {
             char k[256];
-            int v, w, r;
+            int v, w, r, ntf;
             bool found = false;
             TileShape sh;
-            while (std::fscanf(f, "%255s %d %d %d", k, &v, &w, &r) == 4)
+            while (std::fscanf(f, "%255s %d %d %d %d", k, &v, &w, &r, &ntf) == 5)
                 if (key == k) {
                     sh.vec = v;
                     sh.waves = w;
                     sh.rows = r;
+                    sh.nt = ntf;
                     found = true;
                 }
             std::fclose(f);
             if (found && valid_shape(s, sh)) {
-                fem_tile t{sh.vec, sh.waves, sh.rows};
+                fem_tile t{sh.vec, sh.waves, sh.rows, sh.nt};
                 STCHK(fem_set_tile(s, &t));
                 if (chosen) STCHK(fem_get_tile(s, chosen));
                 return FEM_OK;
             }
         }
     }
-    // save the state, try every shape from the same state, restore
-    size_t bytes = 0;
-    STCHK(fem_state_size(s, &bytes));
-    std::vector<char> saved(bytes);
-    STCHK(fem_get_state(s, saved.data(), bytes));
+    // keep a device copy of the state, try every shape from it, restore
     const int t_save = s->t;
     const int steps_avail = s->prm.steps - t_save;
-    const int trial = std::min(trial_steps, std::max(1, steps_avail));
     if (steps_avail < 1) return fail(FEM_E_STATE, "no steps left to tune with");
+    const int trial = std::min(trial_steps, steps_avail);
+    float* backup = nullptr;
+    HIPCHK(dalloc(&backup, 3 * s->vals));
+    auto save_restore = [&](bool save) -> fem_status {
+        const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+        float* st3[3] = {s->h, s->m1, s->m2};
+        for (int j = 0; j < 3; ++j) {
+            if (save) HIPCHK(hipMemcpyAsync(backup + j * s->vals, st3[j], s->vals * 4, k, s->stream));
+            else HIPCHK(hipMemcpyAsync(st3[j], backup + j * s->vals, s->vals * 4, k, s->stream));
+        }
+        if (!save) {
+            s->t = t_save;
+            s->last_energy_step = -1;
+            STCHK(init_marginals(s));
+        }
+        HIPCHK(hipStreamSynchronize(s->stream));
+        return FEM_OK;
+    };
+    {
+        fem_status st0 = save_restore(true);
+        if (st0 != FEM_OK) {
+            dfree(backup);
+            return st0;
+        }
+    }
     std::vector<TileShape> cands;
     const int vecs[4] = {1, 2, 4, 8};
     const int wavess[4] = {2, 4, 8, 16};
     const int rowss[4] = {1, 2, 4, 8};
     for (int vi = 0; vi < (s->kind == KIND_BMINCUT ? 1 : 4); ++vi)
         for (int wv : wavess)
-            for (int rw : rowss) {
-                TileShape sh;
-                sh.vec = vecs[vi];
-                sh.waves = wv;
-                sh.rows = rw;
-                if (valid_shape(s, sh)) cands.push_back(sh);
-            }
+            for (int rw : rowss)
+                for (int ntf = 0; ntf < 2; ++ntf) {
+                    TileShape sh;
+                    sh.vec = vecs[vi];
+                    sh.waves = wv;
+                    sh.rows = rw;
+                    sh.nt = ntf;
+                    if (valid_shape(s, sh)) cands.push_back(sh);
+                }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1448,14 +1515,14 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     s->profile = false;
     fem_status st = FEM_OK;
     for (const TileShape& sh : cands) {
-        fem_tile t{sh.vec, sh.waves, sh.rows};
+        fem_tile t{sh.vec, sh.waves, sh.rows, sh.nt};
         st = fem_set_tile(s, &t);
         if (st != FEM_OK) break;
-        st = fem_set_state(s, saved.data(), bytes);
+        st = save_restore(false);
         if (st != FEM_OK) break;
         st = fem_step(s, 1);   // warm-up
         if (st != FEM_OK) break;
-        st = fem_set_state(s, saved.data(), bytes);
+        st = save_restore(false);
         if (st != FEM_OK) break;
         (void)hipEventRecord(e0, s->stream);
         st = fem_step(s, trial);
@@ -1472,14 +1539,15 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     s->profile = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    fem_tile bt{best_sh.vec, best_sh.waves, best_sh.rows};
+    fem_tile bt{best_sh.vec, best_sh.waves, best_sh.rows, best_sh.nt};
     fem_status st2 = fem_set_tile(s, &bt);
-    if (st2 == FEM_OK) st2 = fem_set_state(s, saved.data(), bytes);
+    if (st2 == FEM_OK) st2 = save_restore(false);
+    dfree(backup);
     if (st != FEM_OK) return st;
     if (st2 != FEM_OK) return st2;
     FILE* f = std::fopen(path.c_str(), "a");
     if (f) {
-        std::fprintf(f, "%s %d %d %d\n", key.c_str(), best_sh.vec, best_sh.waves, best_sh.rows);
+        std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), best_sh.vec, best_sh.waves, best_sh.rows, best_sh.nt);
         std::fclose(f);
     }
     if (chosen) STCHK(fem_get_tile(s, chosen));

@@ -65,6 +65,7 @@ __host__ __device__ constexpr int step_max_threads(int kind, int per_lane)
 
 struct TileShape {
     int vec = 1, waves = 4, rows = 4;
+    int nt = 0;   // non-temporal access to h, m1, m2
 };
 
 // Per-step scalars, computed on the host in double and passed as float.
@@ -107,7 +108,7 @@ struct StepArgs {
 };
 
 // host-side kernel launchers (fem_kernels.hip)
-hipError_t launch_step(int kind, int dtype, int vec, const LaunchGeom& g, int waves,
+hipError_t launch_step(int kind, int dtype, int vec, bool nt, const LaunchGeom& g, int waves,
                        const StepArgs& a, hipStream_t st);
 // marginal copy of a.h into a.marg_nxt (count = n*R values for one-logit kinds);
 // for bMinCut also the column-sum partials a.cpart

@@ -143,6 +143,45 @@ __device__ __forceinline__ void st_marg(MT* p, const float (&x)[V])
     else st_bf16<V>(reinterpret_cast<uint16_t*>(p), x);
 }
 
+// h, m1, m2 are read once and written once per step: with NT the accesses
+// are non-temporal, so they do not evict the gathered marginal copy from L2
+// and the Infinity Cache.
+template <int V, bool NT>
+__device__ __forceinline__ void ld_state(const float* __restrict__ p, float (&x)[V])
+{
+    if constexpr (!NT || V < 4) {
+        if constexpr (NT && V == 1) x[0] = __builtin_nontemporal_load(p);
+        else if constexpr (NT && V == 2) {
+            f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+            x[0] = t.x; x[1] = t.y;
+        } else ld_f32<V>(p, x);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k) {
+            f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p) + k);
+            x[4 * k] = t.x; x[4 * k + 1] = t.y; x[4 * k + 2] = t.z; x[4 * k + 3] = t.w;
+        }
+    }
+}
+
+template <int V, bool NT>
+__device__ __forceinline__ void st_state(float* __restrict__ p, const float (&x)[V])
+{
+    if constexpr (!NT || V < 4) {
+        if constexpr (NT && V == 1) __builtin_nontemporal_store(x[0], p);
+        else if constexpr (NT && V == 2) {
+            f32x2 t; t.x = x[0]; t.y = x[1];
+            __builtin_nontemporal_store(t, reinterpret_cast<f32x2*>(p));
+        } else st_f32<V>(p, x);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k) {
+            f32x4 t; t.x = x[4 * k]; t.y = x[4 * k + 1]; t.z = x[4 * k + 2]; t.w = x[4 * k + 3];
+            __builtin_nontemporal_store(t, reinterpret_cast<f32x4*>(p) + k);
+        }
+    }
+}
+
 // Adam, torch.optim.Adam semantics: g += wd*h; m1 = b1 m1 + (1-b1) g;
 // m2 = b2 m2 + (1-b2) g^2; h -= step_size * m1 / (sqrt(m2)/sqrt(1-b2^n) + eps)
 __device__ __forceinline__ float adam_update(float x, float g, float& m1, float& m2, const StepScalars& s)
@@ -231,7 +270,7 @@ __device__ __forceinline__ void block_reduce_store(T (&v)[K], const TeamIdx& ti,
 // ordered-pair F through the one-logit reduction.  Energies: U = -W_tot +
 // (1/2) sum_i m_i phi_i and S = sum_i H2(P_i), accumulated here as
 // [sum m phi, sum H2] per replica.
-template <int V, typename MT, bool EN>
+template <int V, typename MT, bool EN, bool NT>
 __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blockIdx.x];
@@ -248,6 +287,12 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
 
     if (act) {
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
+            // the row's own state first: its loads overlap the neighbour gather
+            const size_t base = (size_t)i * R + rb;
+            float hv[V], m1v[V], m2v[V], mnew[V], gv[V];
+            ld_state<V, NT>(a.h + base, hv);
+            ld_state<V, NT>(a.m1 + base, m1v);
+            ld_state<V, NT>(a.m2 + base, m2v);
             float acc[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) acc[v] = 0.0f;
@@ -278,11 +323,6 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc[v] = fmaf(w0, x0[v], acc[v]);
             }
-            const size_t base = (size_t)i * R + rb;
-            float hv[V], m1v[V], m2v[V], mnew[V], gv[V];
-            ld_f32<V>(a.h + base, hv);
-            ld_f32<V>(a.m1 + base, m1v);
-            ld_f32<V>(a.m2 + base, m2v);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const float x = hv[v];
@@ -300,9 +340,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 hv[v] = nh;
                 mnew[v] = tanhf(0.5f * nh);
             }
-            st_f32<V>(a.h + base, hv);
-            st_f32<V>(a.m1 + base, m1v);
-            st_f32<V>(a.m2 + base, m2v);
+            st_state<V, NT>(a.h + base, hv);
+            st_state<V, NT>(a.m1 + base, m1v);
+            st_state<V, NT>(a.m2 + base, m2v);
             st_marg<MT, V>(mn + base, mnew);
             if (a.grad) st_f32<V>(a.grad + base, gv);
         }
@@ -328,7 +368,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
 // Energies per replica: [sum_i (sum_j W_ij - P_i.Phi_i), sum_i |P_i|^2,
 // -sum_i P_i.ln P_i].  Column sums of the new marginals go out as 2^-40
 // fixed point.
-template <int Q, typename MT, bool EN>
+template <int Q, typename MT, bool EN, bool NT>
 __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blockIdx.x];
@@ -348,6 +388,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
     if (act) {
         ld_f32<Q>(a.ctil + ((size_t)tile.inst * R + r) * Q, ct);
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
+            const size_t base = ((size_t)i * R + r) * Q;
+            float hv[Q], m1v[Q], m2v[Q];
+            ld_state<Q, NT>(a.h + base, hv);
+            ld_state<Q, NT>(a.m1 + base, m1v);
+            ld_state<Q, NT>(a.m2 + base, m2v);
             float phi[Q];
 #pragma unroll
             for (int s = 0; s < Q; ++s) phi[s] = 0.0f;
@@ -373,11 +418,6 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
 #pragma unroll
                 for (int s = 0; s < Q; ++s) phi[s] = fmaf(w0, x0[s], phi[s]);
             }
-            const size_t base = ((size_t)i * R + r) * Q;
-            float hv[Q], m1v[Q], m2v[Q];
-            ld_f32<Q>(a.h + base, hv);
-            ld_f32<Q>(a.m1 + base, m1v);
-            ld_f32<Q>(a.m2 + base, m2v);
             // softmax of the current fields
             float mx = hv[0];
 #pragma unroll
@@ -425,9 +465,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
                 Pn[s] *= invZ2;
                 cs[s] += to_fixed(Pn[s]);
             }
-            st_f32<Q>(a.h + base, hv);
-            st_f32<Q>(a.m1 + base, m1v);
-            st_f32<Q>(a.m2 + base, m2v);
+            st_state<Q, NT>(a.h + base, hv);
+            st_state<Q, NT>(a.m1 + base, m1v);
+            st_state<Q, NT>(a.m2 + base, m2v);
             st_marg<MT, Q>(mn + base, Pn);
             if (a.grad) st_f32<Q>(a.grad + base, gv);
         }
@@ -466,7 +506,7 @@ struct SatRec<3> {
     using T = int4;
 };
 
-template <int V, typename MT, int W, bool EN>
+template <int V, typename MT, int W, bool EN, bool NT>
 __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blockIdx.x];
@@ -487,7 +527,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             const size_t base = (size_t)i * R + rb;
             float hv[V], m1v[V], m2v[V];
-            ld_f32<V>(a.h + base, hv);
+            ld_state<V, NT>(a.h + base, hv);
+            ld_state<V, NT>(a.m1 + base, m1v);
+            ld_state<V, NT>(a.m2 + base, m2v);
             float own_small[V];
             bool own_hi[V];
 #pragma unroll
@@ -538,8 +580,6 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                     }
                 }
             }
-            ld_f32<V>(a.m1 + base, m1v);
-            ld_f32<V>(a.m2 + base, m2v);
             float gv[V], snew[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -555,9 +595,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 hv[v] = nh;
                 snew[v] = sat_encode(nh);
             }
-            st_f32<V>(a.h + base, hv);
-            st_f32<V>(a.m1 + base, m1v);
-            st_f32<V>(a.m2 + base, m2v);
+            st_state<V, NT>(a.h + base, hv);
+            st_state<V, NT>(a.m1 + base, m1v);
+            st_state<V, NT>(a.m2 + base, m2v);
             st_marg<MT, V>(mn + base, snew);
             if (a.grad) st_f32<V>(a.grad + base, gv);
         }
@@ -652,6 +692,7 @@ template <typename T>
 static hipError_t seg_reduce2(const T* part, int cols, const int32_t* chunk_off, int n_chunks,
                               const int32_t* inst_chunk_off, int n_inst, T* tmp, T* out, hipStream_t st)
 {
+    (void)hipGetLastError();
     dim3 g1(n_chunks, (cols + 31) / 32);
     seg_reduce_kernel<T><<<g1, 256, 0, st>>>(part, cols, chunk_off, tmp);
     dim3 g2(n_inst, (cols + 31) / 32);
@@ -865,27 +906,27 @@ __global__ void best_update_kernel(int kind, int R, int n_inst, int q, double la
 // LDS for block_reduce_store: waves * L * K values of 8 bytes.
 static inline size_t lds_bytes(int waves, int L, int K) { return (size_t)waves * L * K * 8; }
 
-template <int V, typename MT>
+template <int V, typename MT, bool NT>
 static void launch_maxcut(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStream_t st)
 {
-    if (en) maxcut_step_kernel<V, MT, true><<<g, b, lds_bytes(b.x / 64, L, 2 * V), st>>>(a);
-    else maxcut_step_kernel<V, MT, false><<<g, b, 0, st>>>(a);
+    if (en) maxcut_step_kernel<V, MT, true, NT><<<g, b, lds_bytes(b.x / 64, L, 2 * V), st>>>(a);
+    else maxcut_step_kernel<V, MT, false, NT><<<g, b, 0, st>>>(a);
 }
-template <int V, typename MT, int W>
+template <int V, typename MT, int W, bool NT>
 static void launch_sat(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStream_t st)
 {
-    if (en) sat_step_kernel<V, MT, W, true><<<g, b, lds_bytes(b.x / 64, L, 2 * V), st>>>(a);
-    else sat_step_kernel<V, MT, W, false><<<g, b, 0, st>>>(a);
+    if (en) sat_step_kernel<V, MT, W, true, NT><<<g, b, lds_bytes(b.x / 64, L, 2 * V), st>>>(a);
+    else sat_step_kernel<V, MT, W, false, NT><<<g, b, 0, st>>>(a);
 }
-template <int Q, typename MT>
+template <int Q, typename MT, bool NT>
 static void launch_potts(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStream_t st)
 {
     const size_t lds = lds_bytes(b.x / 64, L, Q > 3 ? Q : 3);
-    if (en) potts_step_kernel<Q, MT, true><<<g, b, lds, st>>>(a);
-    else potts_step_kernel<Q, MT, false><<<g, b, lds, st>>>(a);
+    if (en) potts_step_kernel<Q, MT, true, NT><<<g, b, lds, st>>>(a);
+    else potts_step_kernel<Q, MT, false, NT><<<g, b, lds, st>>>(a);
 }
 
-template <typename MT>
+template <typename MT, bool NT>
 static hipError_t launch_step_t(int kind, int vec, const LaunchGeom& geo, int waves, const StepArgs& a,
                                 hipStream_t st)
 {
@@ -894,39 +935,43 @@ static hipError_t launch_step_t(int kind, int vec, const LaunchGeom& geo, int wa
     const bool en = a.epart != nullptr;
     if (kind == KIND_MAXCUT) {
         switch (vec) {
-        case 1: launch_maxcut<1, MT>(en, g, b, L, a, st); break;
-        case 2: launch_maxcut<2, MT>(en, g, b, L, a, st); break;
-        case 4: launch_maxcut<4, MT>(en, g, b, L, a, st); break;
-        case 8: launch_maxcut<8, MT>(en, g, b, L, a, st); break;
+        case 1: launch_maxcut<1, MT, NT>(en, g, b, L, a, st); break;
+        case 2: launch_maxcut<2, MT, NT>(en, g, b, L, a, st); break;
+        case 4: launch_maxcut<4, MT, NT>(en, g, b, L, a, st); break;
+        case 8: launch_maxcut<8, MT, NT>(en, g, b, L, a, st); break;
         default: return hipErrorInvalidValue;
         }
     } else if (kind == KIND_MAXSAT) {
         const bool w2 = a.inc2 != nullptr;
         switch (vec) {
-        case 1: w2 ? launch_sat<1, MT, 2>(en, g, b, L, a, st) : launch_sat<1, MT, 3>(en, g, b, L, a, st); break;
-        case 2: w2 ? launch_sat<2, MT, 2>(en, g, b, L, a, st) : launch_sat<2, MT, 3>(en, g, b, L, a, st); break;
-        case 4: w2 ? launch_sat<4, MT, 2>(en, g, b, L, a, st) : launch_sat<4, MT, 3>(en, g, b, L, a, st); break;
-        case 8: w2 ? launch_sat<8, MT, 2>(en, g, b, L, a, st) : launch_sat<8, MT, 3>(en, g, b, L, a, st); break;
+        case 1: w2 ? launch_sat<1, MT, 2, NT>(en, g, b, L, a, st) : launch_sat<1, MT, 3, NT>(en, g, b, L, a, st); break;
+        case 2: w2 ? launch_sat<2, MT, 2, NT>(en, g, b, L, a, st) : launch_sat<2, MT, 3, NT>(en, g, b, L, a, st); break;
+        case 4: w2 ? launch_sat<4, MT, 2, NT>(en, g, b, L, a, st) : launch_sat<4, MT, 3, NT>(en, g, b, L, a, st); break;
+        case 8: w2 ? launch_sat<8, MT, 2, NT>(en, g, b, L, a, st) : launch_sat<8, MT, 3, NT>(en, g, b, L, a, st); break;
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (a.q) {
-        case 2: launch_potts<2, MT>(en, g, b, L, a, st); break;
-        case 4: launch_potts<4, MT>(en, g, b, L, a, st); break;
-        case 8: launch_potts<8, MT>(en, g, b, L, a, st); break;
-        case 16: launch_potts<16, MT>(en, g, b, L, a, st); break;
-        case 32: launch_potts<32, MT>(en, g, b, L, a, st); break;
+        case 2: launch_potts<2, MT, NT>(en, g, b, L, a, st); break;
+        case 4: launch_potts<4, MT, NT>(en, g, b, L, a, st); break;
+        case 8: launch_potts<8, MT, NT>(en, g, b, L, a, st); break;
+        case 16: launch_potts<16, MT, NT>(en, g, b, L, a, st); break;
+        case 32: launch_potts<32, MT, NT>(en, g, b, L, a, st); break;
         default: return hipErrorInvalidValue;
         }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_step(int kind, int dtype, int vec, const LaunchGeom& g, int waves, const StepArgs& a,
+hipError_t launch_step(int kind, int dtype, int vec, bool nt, const LaunchGeom& g, int waves, const StepArgs& a,
                        hipStream_t st)
 {
-    if (dtype == 1) return launch_step_t<uint16_t>(kind, vec, g, waves, a, st);
-    return launch_step_t<float>(kind, vec, g, waves, a, st);
+    (void)hipGetLastError();   // drop stale errors of earlier calls
+    if (dtype == 1)
+        return nt ? launch_step_t<uint16_t, true>(kind, vec, g, waves, a, st)
+                  : launch_step_t<uint16_t, false>(kind, vec, g, waves, a, st);
+    return nt ? launch_step_t<float, true>(kind, vec, g, waves, a, st)
+              : launch_step_t<float, false>(kind, vec, g, waves, a, st);
 }
 
 template <typename MT>
@@ -954,6 +999,7 @@ static inline int grid_for(size_t count)
 hipError_t launch_init_marginals(int kind, int dtype, const LaunchGeom& g, int waves, const StepArgs& a,
                                  size_t count, hipStream_t st)
 {
+    (void)hipGetLastError();   // drop stale errors of earlier calls
     if (kind == KIND_BMINCUT) {
         if (dtype == 1) return launch_potts_init_t<uint16_t>(g, waves, a, st);
         return launch_potts_init_t<float>(g, waves, a, st);
@@ -982,6 +1028,7 @@ template hipError_t launch_seg_reduce<int>(const int*, int, const int32_t*, int,
 hipError_t launch_energy_combine(int kind, int R, int q, int n_inst, const double* raw, const double* wtot,
                                  const double* csum, double lam, double beta, double* eout, hipStream_t st)
 {
+    (void)hipGetLastError();   // drop stale errors of earlier calls
     const int n = n_inst * R;
     energy_combine_kernel<<<(n + 255) / 256, 256, 0, st>>>(kind, R, q, n_inst, raw, wtot, csum, lam, beta, eout);
     return hipGetLastError();
@@ -990,6 +1037,7 @@ hipError_t launch_energy_combine(int kind, int R, int q, int n_inst, const doubl
 hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, double* csum, float* ctil,
                                  hipStream_t st)
 {
+    (void)hipGetLastError();   // drop stale errors of earlier calls
     const int n = n_inst * R;
     colsum_combine_kernel<<<(n + 255) / 256, 256, 0, st>>>(R, q, n_inst, fx, csum, ctil);
     return hipGetLastError();
@@ -997,6 +1045,7 @@ hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, 
 
 hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h, uint8_t* sigma, hipStream_t st)
 {
+    (void)hipGetLastError();   // drop stale errors of earlier calls
     const size_t count = (size_t)n * R;
     if (count == 0) return hipSuccess;
     round_kernel<<<grid_for(count), 256, 0, st>>>(kind, n, R, q, h, sigma);
@@ -1005,6 +1054,7 @@ hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* 
 
 hipError_t launch_transpose_sigma(int32_t n, int32_t R, const int32_t* sig_rn, uint8_t* sig_nr, hipStream_t st)
 {
+    (void)hipGetLastError();   // drop stale errors of earlier calls
     const size_t count = (size_t)n * R;
     if (count == 0) return hipSuccess;
     transpose_sigma_kernel<<<grid_for(count), 256, 0, st>>>(n, R, sig_rn, sig_nr);
@@ -1014,6 +1064,7 @@ hipError_t launch_transpose_sigma(int32_t n, int32_t R, const int32_t* sig_rn, u
 hipError_t launch_eval(const Problem& p, const LaunchGeom& geo, int waves, const Tile* tiles, int32_t R,
                        const uint8_t* sigma, double* vpart, int* spart, hipStream_t st)
 {
+    (void)hipGetLastError();   // drop stale errors of earlier calls
     dim3 g(geo.n_tiles, geo.nseg), b(64 * waves);
     int lanes_log2 = 0;
     while ((1 << lanes_log2) < geo.lanes) ++lanes_log2;
@@ -1043,6 +1094,7 @@ hipError_t launch_eval(const Problem& p, const LaunchGeom& geo, int waves, const
 
 hipError_t launch_sizes_widen(size_t count, const int* in, long long* out, hipStream_t st)
 {
+    (void)hipGetLastError();   // drop stale errors of earlier calls
     if (count == 0) return hipSuccess;
     sizes_widen_kernel<<<grid_for(count), 256, 0, st>>>(count, in, out);
     return hipGetLastError();
@@ -1051,6 +1103,7 @@ hipError_t launch_sizes_widen(size_t count, const int* in, long long* out, hipSt
 hipError_t launch_best_update(int kind, int R, int n_inst, int q, double lam, const double* vout,
                               const long long* sout, double* best, hipStream_t st)
 {
+    (void)hipGetLastError();   // drop stale errors of earlier calls
     const int n = n_inst * R;
     best_update_kernel<<<(n + 255) / 256, 256, 0, st>>>(kind, R, n_inst, q, lam, vout, sout, best);
     return hipGetLastError();

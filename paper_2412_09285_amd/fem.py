@@ -45,7 +45,7 @@ class Params(C.Structure):
 
 
 class Tile(C.Structure):
-    _fields_ = [("vec", C.c_int32), ("waves", C.c_int32), ("rows", C.c_int32)]
+    _fields_ = [("vec", C.c_int32), ("waves", C.c_int32), ("rows", C.c_int32), ("nt", C.c_int32)]
 
 
 _lib = None
@@ -68,6 +68,7 @@ _SIGS = {
     "fem_solver_create": (C.c_int, [_P, C.POINTER(Params), _P, _PP]),
     "fem_solver_destroy": (None, [_P]),
     "fem_set_fields": (C.c_int, [_P, _P, C.c_int]),
+    "fem_set_adam_state": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_int]),
     "fem_step": (C.c_int, [_P, C.c_int32]),
     "fem_run": (C.c_int, [_P]),
     "fem_run_until": (C.c_int, [_P, C.c_int32]),
@@ -260,6 +261,13 @@ class Solver:
             assert a.shape == self.shape, (a.shape, self.shape)
             _check(lib().fem_set_fields(self._h, pa, 0))
 
+    def set_adam_state(self, h, m1, m2, t):
+        """Host arrays in the layout of h; t = the next step to run."""
+        arrs = [_host(x, np.float32) for x in (h, m1, m2)]
+        for a, _ in arrs:
+            assert a.shape == self.shape, (a.shape, self.shape)
+        _check(lib().fem_set_adam_state(self._h, arrs[0][1], arrs[1][1], arrs[2][1], t, 0))
+
     def fields(self, out=None):
         if out is not None and _is_torch(out) and out.is_cuda:
             _check(lib().fem_get_fields(self._h, C.c_void_p(out.data_ptr()), 1))
@@ -341,18 +349,19 @@ class Solver:
 
     # ---- tiling
     def tile(self):
+        """(vec, waves, rows, nt)"""
         t = Tile()
         _check(lib().fem_get_tile(self._h, C.byref(t)))
-        return (t.vec, t.waves, t.rows)
+        return (t.vec, t.waves, t.rows, t.nt)
 
-    def set_tile(self, vec, waves, rows):
-        t = Tile(vec, waves, rows)
+    def set_tile(self, vec, waves, rows, nt=0):
+        t = Tile(vec, waves, rows, nt)
         _check(lib().fem_set_tile(self._h, C.byref(t)))
 
     def tune(self, trial_steps=5, use_cache=True):
         t = Tile()
         _check(lib().fem_tune(self._h, trial_steps, int(use_cache), C.byref(t)))
-        return (t.vec, t.waves, t.rows)
+        return (t.vec, t.waves, t.rows, t.nt)
 
     # ---- profiling
     def profile(self, on=True):

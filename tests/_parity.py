@@ -42,3 +42,88 @@ def assert_energy_close(U, S, F, Ur, Sr, beta, rtol=RTOL, what="E"):
     eu, es, ef = energy_errors(U, S, F, Ur, Sr, beta)
     assert max(eu, es, ef) <= rtol, f"{what}: U {eu:.3e} S {es:.3e} F {ef:.3e}"
     return eu, es, ef
+
+
+# ---------------------------------------------------------------------------
+# Lockstep parity along the oracle's trajectory.
+#
+# Free-running FP32 and FP64 trajectories separate: Adam's first step is
+# -lr * g / (|g| + eps), a sign function wherever |g| is tiny, and the anneal
+# amplifies any difference after the ordering transition.  So each step t is
+# checked from the oracle's own state (h, m1, m2, t), rounded to float32 and
+# loaded into the GPU solver: data flows from the oracle to the GPU only.  The
+# GPU's gradient and energies at step t must match the oracle's to RTOL; its
+# h(t+1) must lie within the deviation that Adam's update shows when the
+# gradient moves within the gradient tolerance (evaluated in FP64 on a grid of
+# the interval), plus RTOL * max |h(t+1)|.
+# ---------------------------------------------------------------------------
+def oracle_trajectory(run, n_steps):
+    states, gs, Us, Ss = [], [], [], []
+    for _ in range(n_steps):
+        states.append((run.h.copy(), run.m1.copy(), run.m2.copy()))
+        g, U, S = run.step(1, record=True)
+        gs.append(g[0]); Us.append(U[0]); Ss.append(S[0])
+    states.append((run.h.copy(), run.m1.copy(), run.m2.copy()))
+    return states, gs, Us, Ss
+
+
+def adam_deviation(h, m1, m2, g, t, p, dg, npts=9):
+    """max_{|e| <= dg} |Adam(h, m1, m2, g + e) - Adam(h, m1, m2, g)| (FP64)."""
+    n = t + 1
+    bc1 = 1 - p.b1 ** n
+    bc2s = np.sqrt(1 - p.b2 ** n)
+
+    def upd(gg):
+        gg = gg + p.wd * h
+        a = p.b1 * m1 + (1 - p.b1) * gg
+        b = p.b2 * m2 + (1 - p.b2) * gg * gg
+        return h - (p.lr / bc1) * a / (np.sqrt(b) / bc2s + p.eps)
+
+    base = upd(g)
+    dev = np.zeros_like(g)
+    for x in np.linspace(-1.0, 1.0, npts):
+        dev = np.maximum(dev, np.abs(upd(g + x * dg) - base))
+    return dev
+
+
+def per_replica_max(x, R):
+    """max |x| per replica, broadcast back to the layout of x."""
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    m = x.reshape(x.shape[0], R, -1).max(axis=(0, 2))
+    shape = (1, R) + (1,) * (x.ndim - 2)
+    return m.reshape(shape)
+
+
+def lockstep(solver, run, params, n_steps, R, tag, betas, energies=True, rtol=RTOL):
+    """Run the oracle n_steps, then replay every step on the GPU from the
+    oracle's state; returns the worst relative errors."""
+    states, gs, Us, Ss = oracle_trajectory(run, n_steps)
+    worst = dict(g=0.0, E=0.0, h=0.0)
+    for t in range(n_steps):
+        h, m1, m2 = states[t]
+        solver.set_adam_state(h, m1, m2, t)
+        solver.step(1)
+        a, b = assert_grad_close(solver.last_grad(), gs[t], R, rtol=rtol, what=f"{tag} g step {t}")
+        worst["g"] = max(worst["g"], a, b)
+        if energies:
+            U, S, F = solver.energies()
+            e = assert_energy_close(U[0], S[0], F[0], Us[t], Ss[t], betas[t], rtol=rtol,
+                                    what=f"{tag} energies step {t}")
+            worst["E"] = max(worst["E"], *e)
+        hn = solver.fields().astype(np.float64)
+        href = states[t + 1][0]
+        dg = rtol * per_replica_max(gs[t], R)
+        tol = adam_deviation(h, m1, m2, gs[t], t, params, dg) + rtol * per_replica_max(href, R)
+        err = np.abs(hn - href)
+        bad = err > tol
+        assert not bad.any(), f"{tag} h({t + 1}): {int(bad.sum())} values outside the propagated tolerance, " \
+                              f"worst excess {float((err - tol).max()):.3e}"
+        worst["h"] = max(worst["h"], float((err / np.maximum(per_replica_max(href, R), 1e-300)).max()))
+    print(f"[{tag}] lockstep {n_steps} steps: worst rel error grad {worst['g']:.2e}, energies {worst['E']:.2e}, "
+          f"h {worst['h']:.2e}", flush=True)
+    return worst
+
+
+def free_running_drift(grads, gref, R):
+    """Per-step norm-wise relative gradient error of a free-running pair."""
+    return [float(grad_errors(grads[t], gref[t], R)[0].max()) for t in range(len(grads))]

@@ -1,8 +1,9 @@
 """GPU parity of the MaxCut hot path against the FP64 oracle (through the C ABI).
 
-Every input comes from the seeded generators; both sides start from the same
-h0 and run independently (free-running); nothing from the GPU is fed to the
-oracle.
+Every input comes from the seeded generators.  Step parity is lockstep: each
+step is replayed on the GPU from the oracle's own state (oracle -> GPU only;
+nothing from the GPU is fed to the oracle).  Free-running runs are compared by
+value (drift, cut statistics).
 """
 import numpy as np
 import pytest
@@ -10,7 +11,7 @@ import pytest
 import oracle as O
 from paper_2412_09285_amd import fem
 from paper_2412_09285_amd import workloads as W
-from _parity import assert_energy_close, assert_grad_close, grad_errors
+from _parity import assert_energy_close, assert_grad_close, free_running_drift, grad_errors, lockstep
 
 pytestmark = pytest.mark.gpu
 
@@ -36,25 +37,41 @@ def free_run(graph, R, T, n_steps, seed, dtype=fem.F32, tile=None, lr=0.1):
                 href=run.h, betas=betas, solver=s, prob=prob)
 
 
-def check_run(res, R, tag):
-    worst = [0.0, 0.0, 0.0]
-    for t in range(res["grads"].shape[0]):
-        a, b = assert_grad_close(res["grads"][t], res["gref"][t], R, what=f"{tag} g step {t}")
-        worst[0] = max(worst[0], a, b)
-        e = assert_energy_close(res["U"][t], res["S"][t], res["F"][t], res["Uref"][t], res["Sref"][t],
-                                res["betas"][t], what=f"{tag} energies step {t}")
-        worst[1] = max(worst[1], *e)
-    rel, mx = grad_errors(res["h"], res["href"], R)
-    worst[2] = max(rel.max(), mx.max())
-    assert worst[2] <= 1e-5, f"{tag}: h rel {rel.max():.3e} max {mx.max():.3e}"
-    print(f"[{tag}] worst rel error: grad {worst[0]:.2e}, energies {worst[1]:.2e}, h {worst[2]:.2e}", flush=True)
+def lockstep_maxcut(g, R, T, n_steps, seed, dtype=fem.F32, tile=None, lr=0.1, tag=""):
+    h0 = W.initial_fields(g.n, R, seed)
+    prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1, marginal_dtype=dtype, lr=lr))
+    if tile is not None:
+        s.set_tile(*tile)
+    P = O.Params(R=R, T=T, lr=lr)
+    run = O.maxcut_run(g, P, h0)
+    betas = [O.beta(0, P.beta_min, P.beta_max, T, t) for t in range(n_steps)]
+    return lockstep(s, run, P, n_steps, R, tag, betas)
 
 
 def test_config1_first_100_steps():
-    """ER N=800, 19,176 edges, W=+1, R=16, T=500: the first 100 steps."""
+    """ER N=800, 19,176 edges, W=+1, R=16, T=500: every one of the first 100
+    steps, replayed from the oracle's trajectory."""
+    lockstep_maxcut(W.config_graph(1), R=16, T=500, n_steps=100, seed=101, tag="C1")
+
+
+def test_config1_free_running_drift_and_quality():
+    """Both sides anneal C1 independently for all 500 steps.  The per-step
+    gradient drift is printed (FP32 vs FP64 trajectories separate, see
+    lockstep); the first steps agree to 1e-5, and the final best and mean cuts
+    agree statistically (independent trajectories of the same method)."""
     g = W.config_graph(1)
-    res = free_run(g, R=16, T=500, n_steps=100, seed=101)
-    check_run(res, 16, "C1")
+    res = free_run(g, R=16, T=500, n_steps=500, seed=101)
+    drift = free_running_drift(res["grads"], res["gref"], 16)
+    assert max(drift[:10]) <= 1e-5, drift[:10]
+    cut_gpu = res["prob"].eval_int(res["solver"].round())[0][0].astype(np.float64)
+    cut_ref = O.cut(g.n, g.u, g.v, g.w, O.round_(res["href"], 1))
+    assert abs(cut_gpu.max() - cut_ref.max()) <= 0.01 * cut_ref.max()
+    assert abs(cut_gpu.mean() - cut_ref.mean()) <= 0.01 * cut_ref.mean()
+    print(f"[C1 free-running] grad drift at steps 0/10/50/100/200: "
+          f"{drift[0]:.1e} {drift[10]:.1e} {drift[50]:.1e} {drift[100]:.1e} {drift[200]:.1e}; "
+          f"best cut GPU {cut_gpu.max():.0f} oracle {cut_ref.max():.0f}; "
+          f"mean GPU {cut_gpu.mean():.1f} oracle {cut_ref.mean():.1f}", flush=True)
 
 
 @pytest.mark.parametrize("R,n", [(1, 97), (3, 333), (64, 517), (256, 211), (1024, 70)])
@@ -62,25 +79,22 @@ def test_ragged_shapes(R, n):
     """Several tiles with a ragged tail, odd replica counts and more than one
     replica segment per row (R = 1024)."""
     g = W.random_sparse_graph(n, 4 * n, seed=n, weights="pm1")
-    res = free_run(g, R=R, T=200, n_steps=25, seed=7 + R)
-    check_run(res, R, f"n{n}_R{R}")
+    lockstep_maxcut(g, R=R, T=200, n_steps=25, seed=7 + R, tag=f"n{n}_R{R}")
 
 
 def test_isolated_nodes_and_tiny_graphs():
-    # node 5 and 6 isolated, a single edge elsewhere
+    # nodes 4, 5, 6 isolated, weighted path elsewhere
     g = W.Graph(7, np.array([0, 1, 2], np.int32), np.array([1, 2, 3], np.int32), np.array([1, -2, 3], np.float32))
-    res = free_run(g, R=8, T=50, n_steps=10, seed=3)
-    check_run(res, 8, "isolated")
+    lockstep_maxcut(g, R=8, T=50, n_steps=10, seed=3, tag="isolated")
     g1 = W.Graph(1, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
-    res = free_run(g1, R=4, T=10, n_steps=5, seed=4)
-    check_run(res, 4, "single node")
+    lockstep_maxcut(g1, R=4, T=10, n_steps=5, seed=4, tag="single node")
 
 
-@pytest.mark.parametrize("vec,waves,rows", [(1, 1, 1), (2, 8, 3), (4, 2, 16), (8, 4, 4)])
-def test_every_tile_shape_matches_oracle(vec, waves, rows):
+@pytest.mark.parametrize("vec,waves,rows,nt", [(1, 1, 1, 0), (2, 8, 3, 1), (4, 2, 16, 0), (8, 4, 4, 1)])
+def test_every_tile_shape_matches_oracle(vec, waves, rows, nt):
     g = W.random_sparse_graph(900, 2700, seed=5, weights="pm1")
-    res = free_run(g, R=64, T=100, n_steps=15, seed=9, tile=(vec, waves, rows))
-    check_run(res, 64, f"tile{vec}x{waves}x{rows}")
+    lockstep_maxcut(g, R=64, T=100, n_steps=15, seed=9, tile=(vec, waves, rows, nt),
+                    tag=f"tile{vec}x{waves}x{rows}nt{nt}")
 
 
 def test_integer_eval_bitexact():
@@ -114,32 +128,20 @@ def test_round_and_best_on_seeded_fields_with_ties():
     assert np.array_equal(best_sig, sig_ref[rep[0]])
 
 
-def test_config2_full_size_one_step_sampled():
-    """N=100,000, 300,000 edges (+/-1), R=256 in the tuned launch shape: one
-    step; the oracle recomputes four sampled replicas at full size."""
+def test_config2_full_size_two_steps():
+    """N=100,000, 300,000 edges (+/-1), R=256 in the tuned launch shape (the
+    one bench.py times): the first two steps, lockstep with the oracle run on
+    all 256 replicas at full size."""
     g = W.config_graph(2)
     R, T = 256, 2000
     h0 = W.initial_fields(g.n, R, seed=102)
     prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
     s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1))
     s.set_fields(h0)
-    s.tune(trial_steps=3, use_cache=True)
-    s.set_fields(h0)
-    for step in range(2):
-        s.step(1)
-        gg = s.last_grad()
-        U, S, F = s.energies()
-        cols = [0, 1, 128, 255]
-        hs = h0[:, cols] if step == 0 else hs_next
-        run = O.maxcut_run(g, O.Params(R=len(cols), T=T), hs)
-        run.t = step
-        if step == 1:
-            run.m1, run.m2 = m1s, m2s
-        gh, Uh, Sh = run.step(1, record=True)
-        assert_grad_close(gg[:, cols], gh[0], len(cols), what=f"C2 step {step}")
-        assert_energy_close(U[0, cols], S[0, cols], F[0, cols], Uh[0], Sh[0], O.beta(0, 0.01, 5.0, T, step))
-        hs_next, m1s, m2s = run.h.copy(), run.m1.copy(), run.m2.copy()
-    print(f"[C2 full] tile {s.tile()}", flush=True)
+    tile = s.tune(trial_steps=3, use_cache=True)
+    P = O.Params(R=R, T=T)
+    run = O.maxcut_run(g, P, h0)
+    lockstep(s, run, P, 2, R, f"C2 full, tile {tile}", [O.beta(0, 0.01, 5.0, T, t) for t in range(2)])
 
 
 def test_bf16_marginals_gradient_bound():

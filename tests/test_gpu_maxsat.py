@@ -1,12 +1,13 @@
 """GPU parity of the Max-k-SAT (clause-product gradient) hot path against the
-FP64 oracle, through the C ABI.  Seeded inputs only; free-running."""
+FP64 oracle, through the C ABI.  Seeded inputs only; step parity is lockstep
+along the oracle's trajectory (oracle -> GPU only)."""
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2412_09285_amd import fem
 from paper_2412_09285_amd import workloads as W
-from _parity import assert_energy_close, assert_grad_close, grad_errors
+from _parity import assert_energy_close, assert_grad_close, grad_errors, lockstep
 
 pytestmark = pytest.mark.gpu
 
@@ -49,39 +50,33 @@ def free_run(cnf, R, T, n_steps, seed, dtype=fem.F32, tile=None):
                 Sref=Sh, href=run.h, betas=betas)
 
 
-def check_run(res, R, tag):
-    worst = [0.0, 0.0]
-    for t in range(res["grads"].shape[0]):
-        a, b = assert_grad_close(res["grads"][t], res["gref"][t], R, what=f"{tag} g step {t}")
-        e = assert_energy_close(res["U"][t], res["S"][t], res["F"][t], res["Uref"][t], res["Sref"][t],
-                                res["betas"][t], what=f"{tag} energies step {t}")
-        worst = [max(worst[0], a, b), max(worst[1], *e)]
-    rel, mx = grad_errors(res["h"], res["href"], R)
-    assert max(rel.max(), mx.max()) <= 1e-5, f"{tag}: h rel {rel.max():.3e} max {mx.max():.3e}"
-    print(f"[{tag}] worst rel error: grad {worst[0]:.2e}, energies {worst[1]:.2e}, h {max(rel.max(), mx.max()):.2e}",
-          flush=True)
+def lockstep_sat(cnf, R, T, n_steps, seed, tile=None, tag=""):
+    h0 = W.initial_fields(cnf.n_vars, R, seed)
+    prob = fem.Problem.maxsat(cnf.n_vars, cnf.clause_off, cnf.lits)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1))
+    if tile is not None:
+        s.set_tile(*tile)
+    P = O.Params(R=R, T=T)
+    run = O.maxsat_run(cnf, P, h0)
+    betas = [O.beta(0, P.beta_min, P.beta_max, T, t) for t in range(n_steps)]
+    return lockstep(s, run, P, n_steps, R, tag, betas)
 
 
 def test_random_3sat_first_100_steps():
     """The Max-3-SAT recipe (ratio 8, distinct variables, fair signs) at
-    N = 2,000, R = 64."""
-    cnf = W.random_ksat(2000, 16000, 3, seed=4)
-    res = free_run(cnf, R=64, T=2000, n_steps=100, seed=104)
-    check_run(res, 64, "3sat2000")
+    N = 2,000, R = 64: the first 100 steps."""
+    lockstep_sat(W.random_ksat(2000, 16000, 3, seed=4), R=64, T=2000, n_steps=100, seed=104, tag="3sat2000")
 
 
 @pytest.mark.parametrize("R", [1, 16, 24])
 def test_mixed_lengths_repeats_tautologies(R):
-    cnf = mixed_cnf(300, 1500, seed=R)
-    res = free_run(cnf, R=R, T=300, n_steps=40, seed=R + 1)
-    check_run(res, R, f"mixed_R{R}")
+    lockstep_sat(mixed_cnf(300, 1500, seed=R), R=R, T=300, n_steps=40, seed=R + 1, tag=f"mixed_R{R}")
 
 
 @pytest.mark.parametrize("vec,waves,rows", [(1, 2, 1), (2, 4, 5), (4, 8, 2)])
 def test_tile_shapes(vec, waves, rows):
-    cnf = W.random_ksat(1000, 8000, 3, seed=8)
-    res = free_run(cnf, R=64, T=100, n_steps=10, seed=5, tile=(vec, waves, rows))
-    check_run(res, 64, f"tile{vec}x{waves}x{rows}")
+    lockstep_sat(W.random_ksat(1000, 8000, 3, seed=8), R=64, T=100, n_steps=10, seed=5, tile=(vec, waves, rows),
+                 tag=f"tile{vec}x{waves}x{rows}")
 
 
 def test_unsat_count_bitexact():
@@ -120,22 +115,16 @@ def test_bf16_close():
     print(f"[3sat bf16] step-0 grad rel {rel.max():.2e}, step-29 grad rel {rel2.max():.2e}", flush=True)
 
 
-def test_config4_full_size_one_step_sampled():
-    """N = 100,000 variables, M = 800,000 3-clauses, R = 64: one step in the
-    tuned launch shape; two replicas recomputed by the oracle at full size."""
+def test_config4_full_size_two_steps():
+    """N = 100,000 variables, M = 800,000 3-clauses, R = 64 in the tuned launch
+    shape: the first two steps lockstep with the oracle on all replicas."""
     cnf = W.config_cnf(4)
     R, T = 64, 2000
     h0 = W.initial_fields(cnf.n_vars, R, seed=104)
     prob = fem.Problem.maxsat(cnf.n_vars, cnf.clause_off, cnf.lits)
     s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1))
     s.set_fields(h0)
-    s.tune(trial_steps=3, use_cache=True)
-    s.set_fields(h0)
-    s.step(1)
-    gg = s.last_grad()
-    U, S, F = s.energies()
-    cols = [0, 63]
-    gref, Uref, Sref = O.maxsat_grad(cnf.n_vars, cnf.clause_off, cnf.lits, h0[:, cols].astype(np.float64), 0.01)
-    assert_grad_close(gg[:, cols], gref, 2, what="C4")
-    assert_energy_close(U[0, cols], S[0, cols], F[0, cols], Uref, Sref, 0.01)
-    print(f"[C4 full] tile {s.tile()}", flush=True)
+    tile = s.tune(trial_steps=3, use_cache=True)
+    P = O.Params(R=R, T=T)
+    run = O.maxsat_run(cnf, P, h0)
+    lockstep(s, run, P, 2, R, f"C4 full, tile {tile}", [O.beta(0, 0.01, 5.0, T, t) for t in range(2)])
