@@ -272,6 +272,27 @@ class Run:
     def sigma(self):
         return round_(self.h, 1 if self.kind != KIND_BMINCUT else self.q)
 
+    def eval_at(self, h, t):
+        """(g, U, S) of step t (beta(t), lambda(t)) at fields h, without
+        touching the run's own state."""
+        p = self.p
+        b = beta(p.sched, p.beta_min, p.beta_max, p.T, t)
+        if self.kind == KIND_MAXCUT:
+            u, v, w = self._keep
+            return maxcut_grad(self.n, u, v, w, h, b)
+        if self.kind == KIND_BMINCUT:
+            u, v, w = self._keep
+            return bmincut_grad(self.n, u, v, w, self.q, lam(p.lam_ramp, p.lam, p.T, t), h, b)
+        off, lits = self._keep
+        return maxsat_grad(self.n, off, lits, h, b)
+
+    def adam_from(self, h, m1, m2, g, t):
+        """Fields after the Adam step of step t from (h, m1, m2) with gradient g."""
+        p = self.p
+        hh, a, b = (np.array(x, dtype=np.float64, copy=True) for x in (h, m1, m2))
+        adam(g, hh, a, b, p.lr, p.b1, p.b2, p.eps, p.wd, t + 1)
+        return hh
+
 
 def maxcut_run(graph, params: Params, h0):
     return Run(KIND_MAXCUT, params, h0, n=graph.n, u=graph.u, v=graph.v, w=graph.w)

@@ -38,6 +38,12 @@ static fem_status fail(fem_status st, const char* fmt, ...)
     return st;
 }
 
+int fem::set_error(int st, const char* msg)
+{
+    g_err = msg;
+    return st;
+}
+
 #define HIPCHK(expr)                                                                      \
     do {                                                                                  \
         hipError_t e_ = (expr);                                                           \
@@ -70,13 +76,6 @@ static void dfree(T*& p)
 }
 
 // ---------------------------------------------------------------- problems --
-// Problems are reference counted: every solver holds one reference, so a
-// problem released by its owner stays alive until its last solver is gone.
-struct fem_problem {
-    Problem p;
-    int refs = 0;
-    bool released = false;
-};
 
 static void free_problem_device(Problem& p);
 static void problem_unref(fem_problem* fp)
@@ -361,7 +360,7 @@ struct fem_solver {
     long long* ctmp = nullptr;
     long long* cfix = nullptr;
     double* csum = nullptr;
-    float* ctil = nullptr;
+    double* ctil = nullptr;
     // evaluation
     uint8_t* sigma = nullptr;
     double* vpart = nullptr;
@@ -531,8 +530,10 @@ static StepScalars step_scalars(const fem_solver* s, int t)
     const fem_params& p = s->prm;
     const double nstep = (double)t + 1.0;
     StepScalars sc;
-    sc.inv_beta = (float)(1.0 / s->beta[(size_t)t]);
-    sc.lam = (float)s->lam[(size_t)t];
+    sc.inv_beta_d = 1.0 / s->beta[(size_t)t];
+    sc.lam_d = s->lam[(size_t)t];
+    sc.inv_beta = (float)sc.inv_beta_d;
+    sc.lam = (float)sc.lam_d;
     sc.step_size = (float)(p.lr / (1.0 - std::pow(p.adam_b1, nstep)));
     sc.bc2_sqrt = (float)std::sqrt(1.0 - std::pow(p.adam_b2, nstep));
     sc.b1 = (float)p.adam_b1;

@@ -70,6 +70,8 @@ struct TileShape {
 
 // Per-step scalars, computed on the host in double and passed as float.
 struct StepScalars {
+    double inv_beta_d;   // 1/beta and lambda in double for the gradient combination
+    double lam_d;
     float inv_beta;
     float lam;
     float step_size;   // lr / (1 - b1^n)
@@ -99,13 +101,16 @@ struct StepArgs {
     float* m2;
     float* grad;                  // may be null
     double* epart;                // [n_tiles][NE][R] or null (no energies this step)
-    const float* ctil;            // bMinCut: centred column sums C~ [inst][R][q] (float)
+    const double* ctil;           // bMinCut: centred column sums C~ [inst][R][q]
     long long* cpart;             // bMinCut: column-sum partials of the new P [n_tiles][R][q]
     int32_t R;
     int32_t q;
     int32_t lanes_log2;
     StepScalars sc;
 };
+
+// record the text of a failure for fem_last_error() (fem_host.hip); returns st
+int set_error(int st, const char* msg);
 
 // host-side kernel launchers (fem_kernels.hip)
 hipError_t launch_step(int kind, int dtype, int vec, bool nt, const LaunchGeom& g, int waves,
@@ -123,7 +128,7 @@ hipError_t launch_energy_combine(int kind, int R, int q, int n_inst, const doubl
                                  const double* wtot, const double* csum, double lam, double beta,
                                  double* eout, hipStream_t st);
 hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, double* csum,
-                                 float* ctil, hipStream_t st);
+                                 double* ctil, hipStream_t st);
 hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h,
                         uint8_t* sigma, hipStream_t st);
 hipError_t launch_transpose_sigma(int32_t n, int32_t R, const int32_t* sig_rn, uint8_t* sig_nr,
@@ -136,3 +141,11 @@ hipError_t launch_best_update(int kind, int R, int n_inst, int q, double lam, co
                               const long long* sout, double* best, hipStream_t st);
 
 }  // namespace fem
+
+// Problems are reference counted: every solver holds one reference, so a
+// problem released by its owner stays alive until its last solver is gone.
+struct fem_problem {
+    fem::Problem p;
+    int refs = 0;
+    bool released = false;
+};

@@ -25,6 +25,8 @@
 // 2^-40 fixed point (int64), so they do not depend on the tile shape at all.
 #include "fem_internal.h"
 
+#include <type_traits>
+
 namespace fem {
 
 // ---------------------------------------------------------------- helpers --
@@ -293,9 +295,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
             ld_state<V, NT>(a.h + base, hv);
             ld_state<V, NT>(a.m1 + base, m1v);
             ld_state<V, NT>(a.m2 + base, m2v);
-            float acc[V];
+            // phi accumulates in double: near equilibrium g is a small
+            // difference of 2 phi and h / beta
+            double acc[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc[v] = 0.0f;
+            for (int v = 0; v < V; ++v) acc[v] = 0.0;
             int64_t k = a.row_off[i];
             const int64_t kend = a.row_off[i + 1];
             for (; k + 4 <= kend; k += 4) {
@@ -305,23 +309,23 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 ld_marg<MT, V>(mc + (size_t)e1.x * R + rb, x1);
                 ld_marg<MT, V>(mc + (size_t)e2.x * R + rb, x2);
                 ld_marg<MT, V>(mc + (size_t)e3.x * R + rb, x3);
-                const float w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
-                const float w2 = __int_as_float(e2.y), w3 = __int_as_float(e3.y);
+                const double w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
+                const double w2 = __int_as_float(e2.y), w3 = __int_as_float(e3.y);
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    acc[v] = fmaf(w0, x0[v], acc[v]);
-                    acc[v] = fmaf(w1, x1[v], acc[v]);
-                    acc[v] = fmaf(w2, x2[v], acc[v]);
-                    acc[v] = fmaf(w3, x3[v], acc[v]);
+                    acc[v] = fma(w0, (double)x0[v], acc[v]);
+                    acc[v] = fma(w1, (double)x1[v], acc[v]);
+                    acc[v] = fma(w2, (double)x2[v], acc[v]);
+                    acc[v] = fma(w3, (double)x3[v], acc[v]);
                 }
             }
             for (; k < kend; ++k) {
                 const int2 e0 = a.adj[k];
                 float x0[V];
                 ld_marg<MT, V>(mc + (size_t)e0.x * R + rb, x0);
-                const float w0 = __int_as_float(e0.y);
+                const double w0 = __int_as_float(e0.y);
 #pragma unroll
-                for (int v = 0; v < V; ++v) acc[v] = fmaf(w0, x0[v], acc[v]);
+                for (int v = 0; v < V; ++v) acc[v] = fma(w0, (double)x0[v], acc[v]);
             }
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -330,10 +334,10 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 const float e = expf(-ax);
                 const float ope = 1.0f + e;
                 const float pq = e / (ope * ope);   // P(1-P) without cancellation
-                const float g = pq * (2.0f * acc[v] + x * sc.inv_beta);
+                const float g = (float)((double)pq * (2.0 * acc[v] + (double)x * sc.inv_beta_d));
                 gv[v] = g;
                 if constexpr (EN) {
-                    eacc[v] += (double)(tanhf(0.5f * x) * acc[v]);
+                    eacc[v] += (double)tanhf(0.5f * x) * acc[v];
                     eacc[V + v] += (double)(log1pf(e) + ax * (e / ope));
                 }
                 const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
@@ -380,22 +384,25 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
     const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
-    float ct[Q];
+    // Phi accumulates in double up to q = 8 (register budget above)
+    using AccT = typename std::conditional<(Q <= 8), double, float>::type;
+    AccT ct[Q];
     double eacc[3] = {0.0, 0.0, 0.0};
     long long cs[Q];
 #pragma unroll
     for (int s = 0; s < Q; ++s) cs[s] = 0;
     if (act) {
-        ld_f32<Q>(a.ctil + ((size_t)tile.inst * R + r) * Q, ct);
+#pragma unroll
+        for (int s = 0; s < Q; ++s) ct[s] = (AccT)a.ctil[((size_t)tile.inst * R + r) * Q + s];
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             const size_t base = ((size_t)i * R + r) * Q;
             float hv[Q], m1v[Q], m2v[Q];
             ld_state<Q, NT>(a.h + base, hv);
             ld_state<Q, NT>(a.m1 + base, m1v);
             ld_state<Q, NT>(a.m2 + base, m2v);
-            float phi[Q];
+            AccT phi[Q];
 #pragma unroll
-            for (int s = 0; s < Q; ++s) phi[s] = 0.0f;
+            for (int s = 0; s < Q; ++s) phi[s] = (AccT)0;
             int64_t k = a.row_off[i];
             const int64_t kend = a.row_off[i + 1];
             for (; k + 2 <= kend; k += 2) {
@@ -403,20 +410,20 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
                 float x0[Q], x1[Q];
                 ld_marg<MT, Q>(mc + (size_t)e0.x * RQ + (size_t)r * Q, x0);
                 ld_marg<MT, Q>(mc + (size_t)e1.x * RQ + (size_t)r * Q, x1);
-                const float w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
+                const AccT w0 = (AccT)__int_as_float(e0.y), w1 = (AccT)__int_as_float(e1.y);
 #pragma unroll
                 for (int s = 0; s < Q; ++s) {
-                    phi[s] = fmaf(w0, x0[s], phi[s]);
-                    phi[s] = fmaf(w1, x1[s], phi[s]);
+                    phi[s] = fma(w0, (AccT)x0[s], phi[s]);
+                    phi[s] = fma(w1, (AccT)x1[s], phi[s]);
                 }
             }
             for (; k < kend; ++k) {
                 const int2 e0 = a.adj[k];
                 float x0[Q];
                 ld_marg<MT, Q>(mc + (size_t)e0.x * RQ + (size_t)r * Q, x0);
-                const float w0 = __int_as_float(e0.y);
+                const AccT w0 = (AccT)__int_as_float(e0.y);
 #pragma unroll
-                for (int s = 0; s < Q; ++s) phi[s] = fmaf(w0, x0[s], phi[s]);
+                for (int s = 0; s < Q; ++s) phi[s] = fma(w0, (AccT)x0[s], phi[s]);
             }
             // softmax of the current fields
             float mx = hv[0];
@@ -428,25 +435,30 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             const float invZ = 1.0f / Z;
 #pragma unroll
             for (int s = 0; s < Q; ++s) P[s] *= invZ;
-            float A[Q], avg = 0.0f;
+            // gradient terms combined in double: A(s) - sum_s' P(s') A(s') is a
+            // small difference of large terms once the marginals settle
+            // (A is formed twice rather than stored: fewer registers at large q)
+            auto Aof = [&](int s) {
+                return -2.0 * (double)phi[s] + 2.0 * sc.lam_d * ((double)ct[s] - (double)P[s]) +
+                       (double)(hv[s] - mx) * sc.inv_beta_d;
+            };
+            double avg = 0.0;
 #pragma unroll
-            for (int s = 0; s < Q; ++s) {
-                A[s] = -2.0f * phi[s] + 2.0f * sc.lam * (ct[s] - P[s]) + (hv[s] - mx) * sc.inv_beta;
-                avg = fmaf(P[s], A[s], avg);
-            }
+            for (int s = 0; s < Q; ++s) avg = fma((double)P[s], Aof(s), avg);
             float gv[Q];
 #pragma unroll
-            for (int s = 0; s < Q; ++s) gv[s] = (A[s] - avg) * P[s];
+            for (int s = 0; s < Q; ++s) gv[s] = (float)((Aof(s) - avg) * (double)P[s]);
             if constexpr (EN) {
                 const float lz = logf(Z);
-                float dot = 0.0f, sq = 0.0f, ent = 0.0f;
+                double dot = 0.0;
+                float sq = 0.0f, ent = 0.0f;
 #pragma unroll
                 for (int s = 0; s < Q; ++s) {
-                    dot = fmaf(P[s], phi[s], dot);
+                    dot = fma((double)P[s], (double)phi[s], dot);
                     sq = fmaf(P[s], P[s], sq);
                     ent = fmaf(-P[s], hv[s] - mx - lz, ent);
                 }
-                eacc[0] += (double)(a.wdeg[i] - dot);
+                eacc[0] += (double)a.wdeg[i] - dot;
                 eacc[1] += (double)sq;
                 eacc[2] += (double)ent;
             }
@@ -538,9 +550,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 own_small[v] = e / (1.0f + e);
                 own_hi[v] = hv[v] > 0.0f;
             }
-            float d[V];
+            double d[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) d[v] = 0.0f;
+            for (int v = 0; v < V; ++v) d[v] = 0.0;
             const int64_t kend = a.row_off[i + 1];
             for (int64_t k = a.row_off[i]; k < kend; ++k) {
                 const Rec rec = inc[k];
@@ -571,7 +583,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 }
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    d[v] += own_pos ? -c[v] : c[v];
+                    d[v] += own_pos ? -(double)c[v] : (double)c[v];
                     if constexpr (EN) {
                         if (owner) {
                             const float uo = (own_pos == own_hi[v]) ? own_small[v] : 1.0f - own_small[v];
@@ -588,7 +600,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 const float e = expf(-ax);
                 const float ope = 1.0f + e;
                 const float pq = e / (ope * ope);
-                const float g = pq * (d[v] + x * sc.inv_beta);
+                const float g = (float)((double)pq * (d[v] + (double)x * sc.inv_beta_d));
                 gv[v] = g;
                 if constexpr (EN) eacc[V + v] += (double)(log1pf(e) + ax * (e / ope));
                 const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
@@ -733,7 +745,7 @@ __global__ void energy_combine_kernel(int kind, int R, int q, int n_inst, const 
 
 // column sums: fixed point -> C (double) and centred C~ (float)
 __global__ void colsum_combine_kernel(int R, int q, int n_inst, const long long* __restrict__ fx,
-                                      double* __restrict__ csum, float* __restrict__ ctil)
+                                      double* __restrict__ csum, double* __restrict__ ctil)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_inst * R) return;
@@ -745,7 +757,7 @@ __global__ void colsum_combine_kernel(int R, int q, int n_inst, const long long*
         mean += c;
     }
     mean /= q;
-    for (int s = 0; s < q; ++s) ctil[(size_t)idx * q + s] = (float)(csum[(size_t)idx * q + s] - mean);
+    for (int s = 0; s < q; ++s) ctil[(size_t)idx * q + s] = csum[(size_t)idx * q + s] - mean;
 }
 
 // ================================================ read-out & evaluation ===
@@ -1034,7 +1046,7 @@ hipError_t launch_energy_combine(int kind, int R, int q, int n_inst, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, double* csum, float* ctil,
+hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, double* csum, double* ctil,
                                  hipStream_t st)
 {
     (void)hipGetLastError();   // drop stale errors of earlier calls

@@ -1,0 +1,717 @@
+// Learned warm start for MaxCut FEM: a two-layer message-passing network of
+// width 64 that maps node features (bias, ln(1+deg), mean incident weight and
+// five uniform random features from a counter-based generator) to one logit
+// per node, h0 = alpha * z.  Training uses solutions that FEM itself produced,
+// a flip-invariant binary cross-entropy, the analytic backward pass and Adam;
+// every kernel here is hand-written HIP.  The paper has no such network: this
+// is an addition on top of the method, meant to let the anneal start colder.
+//
+// Network (per draw d, node i; a(v)_i = (1/max(deg_i,1)) sum_j W_ij v_j):
+//   pre1 = x A1 + a(x) B1 + b1,    H1 = relu(pre1)
+//   pre2 = H1 A2 + a(H1) B2 + b2,  H2 = relu(pre2)
+//   z    = H2 c + d
+// Weights are used as bfloat16 (round to nearest even) with float32
+// arithmetic; the float32 master copy and the Adam moments stay float32.
+//
+// Random features: Philox4x32-10 (Salmon et al., SC 2011) with counter
+// (i, draw, block, 0) and key (seed mod 2^32, seed div 2^32); a uniform in
+// [-1, 1) is the top 24 bits of a word times 2^-23, minus one (exact).
+//
+// Determinism: every sum runs in a fixed order (neighbour order of the CSR,
+// butterfly within a wave, rows in order within a workgroup, workgroups in
+// order in the final reduction).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fem.h"
+#include "fem_internal.h"
+
+using namespace fem;
+
+namespace {
+
+constexpr int D_IN = 8, HID = 64;
+constexpr int OFF_A1 = 0, OFF_B1 = 512, OFF_b1 = 1024, OFF_A2 = 1088, OFF_B2 = 5184, OFF_b2 = 9280, OFF_c = 9344,
+              OFF_d = 9408;
+constexpr int NP = 9409;
+constexpr int WG_BLOCKS = 512;   // workgroups of the weight-gradient reduction
+
+__device__ __forceinline__ float bf(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+// Philox4x32 with 10 rounds
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ float upm1(uint32_t w) { return (float)(w >> 8) * 0x1p-23f - 1.0f; }
+
+// value of x in lane k of the wave (k a compile-time constant after unrolling)
+__device__ __forceinline__ float lane_val(float x, int k)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ------------------------------------------------------------- forward ----
+__global__ void feat_kernel(int32_t n, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
+                            uint32_t k0, uint32_t k1, uint32_t draw, float* __restrict__ X, float* __restrict__ inv_deg)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int64_t b = row_off[i], e = row_off[i + 1];
+        float ws = 0.0f;
+        for (int64_t k = b; k < e; ++k) ws += __int_as_float(adj[k].y);
+        const float deg = (float)(e - b);
+        const U4 r0 = philox((uint32_t)i, draw, 0u, 0u, k0, k1);
+        const U4 r1 = philox((uint32_t)i, draw, 1u, 0u, k0, k1);
+        float* x = X + (size_t)i * D_IN;
+        x[0] = 1.0f;
+        x[1] = log1pf(deg);
+        x[2] = e > b ? ws / deg : 0.0f;
+        x[3] = upm1(r0.x);
+        x[4] = upm1(r0.y);
+        x[5] = upm1(r0.z);
+        x[6] = upm1(r0.w);
+        x[7] = upm1(r1.x);
+        inv_deg[i] = 1.0f / fmaxf(deg, 1.0f);
+    }
+}
+
+// one wave per node, lane = hidden unit
+__global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* __restrict__ row_off,
+                                                     const int2* __restrict__ adj, const float* __restrict__ X,
+                                                     const float* __restrict__ inv_deg, const uint16_t* __restrict__ w,
+                                                     float* __restrict__ A1agg, float* __restrict__ pre1)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    float colA[D_IN], colB[D_IN];
+#pragma unroll
+    for (int k = 0; k < D_IN; ++k) {
+        colA[k] = bf(w[OFF_A1 + k * HID + lane]);
+        colB[k] = bf(w[OFF_B1 + k * HID + lane]);
+    }
+    const float bias = bf(w[OFF_b1 + lane]);
+    for (int i = wave; i < n; i += nw) {
+        float a = 0.0f;   // lanes 0..7: component lane of the aggregate
+        if (lane < D_IN)
+            for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
+                const int2 e = adj[k];
+                a = fmaf(__int_as_float(e.y), X[(size_t)e.x * D_IN + lane], a);
+            }
+        a *= inv_deg[i];
+        const float xi = lane < D_IN ? X[(size_t)i * D_IN + lane] : 0.0f;
+        float acc = bias;
+#pragma unroll
+        for (int k = 0; k < D_IN; ++k) acc = fmaf(lane_val(xi, k), colA[k], acc);
+#pragma unroll
+        for (int k = 0; k < D_IN; ++k) acc = fmaf(lane_val(a, k), colB[k], acc);
+        pre1[(size_t)i * HID + lane] = acc;
+        if (lane < D_IN) A1agg[(size_t)i * D_IN + lane] = a;
+    }
+}
+
+// one wave per node; A2, B2 staged in LDS as float
+__global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* __restrict__ row_off,
+                                                     const int2* __restrict__ adj, const float* __restrict__ inv_deg,
+                                                     const uint16_t* __restrict__ w, const float* __restrict__ pre1,
+                                                     float* __restrict__ a2out, float* __restrict__ pre2out,
+                                                     float* __restrict__ z)
+{
+    __shared__ float sA[HID * HID], sB[HID * HID];
+    for (int t = threadIdx.x; t < HID * HID; t += blockDim.x) {
+        sA[t] = bf(w[OFF_A2 + t]);
+        sB[t] = bf(w[OFF_B2 + t]);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    const float bias = bf(w[OFF_b2 + lane]);
+    const float cl = bf(w[OFF_c + lane]);
+    const float dd = bf(w[OFF_d]);
+    for (int i = wave; i < n; i += nw) {
+        const float h = fmaxf(pre1[(size_t)i * HID + lane], 0.0f);
+        float a = 0.0f;
+        for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
+            const int2 e = adj[k];
+            a = fmaf(__int_as_float(e.y), fmaxf(pre1[(size_t)e.x * HID + lane], 0.0f), a);
+        }
+        a *= inv_deg[i];
+        float acc = bias;
+#pragma unroll
+        for (int k = 0; k < HID; ++k) acc = fmaf(lane_val(h, k), sA[k * HID + lane], acc);
+#pragma unroll
+        for (int k = 0; k < HID; ++k) acc = fmaf(lane_val(a, k), sB[k * HID + lane], acc);
+        const float zz = wave_sum(fmaxf(acc, 0.0f) * cl);
+        if (a2out) a2out[(size_t)i * HID + lane] = a;
+        if (pre2out) pre2out[(size_t)i * HID + lane] = acc;
+        if (lane == 0) z[i] = zz + dd;
+    }
+}
+
+// h0[i][r] = alpha * z_i for the replicas r with r mod n_draws == draw
+__global__ void write_h0_kernel(int32_t n, int32_t R, int32_t n_draws, int32_t draw, float alpha,
+                                const float* __restrict__ z, float* __restrict__ h0)
+{
+    const int per = (R - draw + n_draws - 1) / n_draws;   // replicas of this draw
+    const size_t count = (size_t)n * per;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = k / per;
+        const int r = draw + (int)(k % per) * n_draws;
+        h0[i * R + r] = alpha * z[i];
+    }
+}
+
+// ------------------------------------------------------------ training ----
+__device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+
+// per instance: L0 = mean softplus(z) - y z, L1 = mean softplus(z) - (1-y) z
+__global__ void __launch_bounds__(256) loss_kernel(const int32_t* __restrict__ inst_off, const float* __restrict__ z,
+                                                   const int32_t* __restrict__ y, double* __restrict__ L)
+{
+    __shared__ double s0[256], s1[256];
+    const int b = blockIdx.x;
+    const int i0 = inst_off[b], i1 = inst_off[b + 1];
+    double a0 = 0.0, a1 = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const float sp = softplusf(z[i]);
+        const float yy = (float)y[i];
+        a0 += (double)(sp - yy * z[i]);
+        a1 += (double)(sp - (1.0f - yy) * z[i]);
+    }
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            s0[threadIdx.x] += s0[threadIdx.x + s];
+            s1[threadIdx.x] += s1[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nb = (double)(i1 > i0 ? i1 - i0 : 1);
+        L[2 * b] = s0[0] / nb;
+        L[2 * b + 1] = s1[0] / nb;
+    }
+}
+
+// dz_i = (sigmoid(z_i) - y~_i) / (N_b * B), y~ the labelling with the lower loss
+__global__ void dz_kernel(int32_t n, const int32_t* __restrict__ inst_of, const int32_t* __restrict__ inst_off,
+                          int32_t B, const double* __restrict__ L, const float* __restrict__ z,
+                          const int32_t* __restrict__ y, float* __restrict__ dz)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int b = inst_of[i];
+        const bool flip = L[2 * b + 1] < L[2 * b];
+        const float yt = flip ? 1.0f - (float)y[i] : (float)y[i];
+        const float sg = 1.0f / (1.0f + expf(-z[i]));
+        const float nb = (float)(inst_off[b + 1] - inst_off[b]);
+        dz[i] = (sg - yt) / (nb * (float)B);
+    }
+}
+
+// dpre2 = dz c [pre2 > 0]; dH1 (own term) = dpre2 A2^T; da2s = (dpre2 B2^T) / max(deg, 1)
+__global__ void __launch_bounds__(256) back2_kernel(int32_t n, const float* __restrict__ inv_deg,
+                                                    const uint16_t* __restrict__ w, const float* __restrict__ dz,
+                                                    const float* __restrict__ pre2, float* __restrict__ dpre2,
+                                                    float* __restrict__ dh1s, float* __restrict__ da2s)
+{
+    __shared__ float sA[HID * (HID + 1)], sB[HID * (HID + 1)];   // padded rows: conflict-free row reads
+    for (int t = threadIdx.x; t < HID * HID; t += blockDim.x) {
+        const int k = t / HID, j = t % HID;
+        sA[k * (HID + 1) + j] = bf(w[OFF_A2 + t]);
+        sB[k * (HID + 1) + j] = bf(w[OFF_B2 + t]);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    const float cl = bf(w[OFF_c + lane]);
+    for (int i = wave; i < n; i += nw) {
+        const float p2 = pre2[(size_t)i * HID + lane];
+        const float dp = p2 > 0.0f ? dz[i] * cl : 0.0f;
+        float ha = 0.0f, hb = 0.0f;
+#pragma unroll
+        for (int j = 0; j < HID; ++j) {
+            const float v = lane_val(dp, j);
+            ha = fmaf(sA[lane * (HID + 1) + j], v, ha);
+            hb = fmaf(sB[lane * (HID + 1) + j], v, hb);
+        }
+        dpre2[(size_t)i * HID + lane] = dp;
+        dh1s[(size_t)i * HID + lane] = ha;
+        da2s[(size_t)i * HID + lane] = hb * inv_deg[i];
+    }
+}
+
+// dpre1_j = [pre1_j > 0] (dH1s_j + sum_{i in N(j)} W_ij da2s_i)
+__global__ void __launch_bounds__(256) back1_kernel(int32_t n, const int64_t* __restrict__ row_off,
+                                                    const int2* __restrict__ adj, const float* __restrict__ pre1,
+                                                    const float* __restrict__ dh1s, const float* __restrict__ da2s,
+                                                    float* __restrict__ dpre1)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    for (int j = wave; j < n; j += nw) {
+        float g = dh1s[(size_t)j * HID + lane];
+        for (int64_t k = row_off[j]; k < row_off[j + 1]; ++k) {
+            const int2 e = adj[k];
+            g = fmaf(__int_as_float(e.y), da2s[(size_t)e.x * HID + lane], g);
+        }
+        dpre1[(size_t)j * HID + lane] = pre1[(size_t)j * HID + lane] > 0.0f ? g : 0.0f;
+    }
+}
+
+// Weight gradients as sums of outer products over the rows; workgroup b owns
+// the contiguous row range [b*n/G, (b+1)*n/G) and writes one partial vector.
+struct WgradArgs {
+    int32_t n;
+    const float *X, *A1agg, *pre1, *a2, *pre2, *dz, *dpre2, *dpre1;
+    float* part;   // [G][NP]
+};
+
+__global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a)
+{
+    constexpr int RB = 16;   // rows staged per round
+    __shared__ float sH1[RB][HID], sA2[RB][HID], sD2[RB][HID], sD1[RB][HID], sH2[RB][HID];
+    __shared__ float sX[RB][D_IN], sA1[RB][D_IN], sdz[RB];
+    const int t = threadIdx.x;
+    const int G = gridDim.x;
+    const int64_t r0 = (int64_t)a.n * blockIdx.x / G, r1 = (int64_t)a.n * (blockIdx.x + 1) / G;
+    float gA2[16], gB2[16], gA1[2], gB1[2];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) gA2[k] = gB2[k] = 0.0f;
+    gA1[0] = gA1[1] = gB1[0] = gB1[1] = 0.0f;
+    float gb2 = 0.0f, gc = 0.0f, gb1 = 0.0f, gd = 0.0f;
+    for (int64_t base = r0; base < r1; base += RB) {
+        const int nr = (int)((r1 - base) < RB ? (r1 - base) : RB);
+        for (int e = t; e < RB * HID; e += blockDim.x) {
+            const int rr = e / HID, c = e % HID;
+            if (rr < nr) {
+                const size_t k = (size_t)(base + rr) * HID + c;
+                sH1[rr][c] = fmaxf(a.pre1[k], 0.0f);
+                sA2[rr][c] = a.a2[k];
+                sD2[rr][c] = a.dpre2[k];
+                sD1[rr][c] = a.dpre1[k];
+                sH2[rr][c] = fmaxf(a.pre2[k], 0.0f);
+            }
+        }
+        for (int e = t; e < RB * D_IN; e += blockDim.x) {
+            const int rr = e / D_IN, c = e % D_IN;
+            if (rr < nr) {
+                sX[rr][c] = a.X[(size_t)(base + rr) * D_IN + c];
+                sA1[rr][c] = a.A1agg[(size_t)(base + rr) * D_IN + c];
+            }
+        }
+        if (t < RB && t < nr) sdz[t] = a.dz[base + t];
+        __syncthreads();
+        for (int rr = 0; rr < nr; ++rr) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = t * 16 + q, k = e / HID, j = e % HID;
+                gA2[q] = fmaf(sH1[rr][k], sD2[rr][j], gA2[q]);
+                gB2[q] = fmaf(sA2[rr][k], sD2[rr][j], gB2[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int e = t * 2 + q, k = e / HID, j = e % HID;
+                gA1[q] = fmaf(sX[rr][k], sD1[rr][j], gA1[q]);
+                gB1[q] = fmaf(sA1[rr][k], sD1[rr][j], gB1[q]);
+            }
+            if (t < HID) {
+                gb2 += sD2[rr][t];
+                gc = fmaf(sdz[rr], sH2[rr][t], gc);
+                gb1 += sD1[rr][t];
+            }
+            if (t == 0) gd += sdz[rr];
+        }
+        __syncthreads();
+    }
+    float* p = a.part + (size_t)blockIdx.x * NP;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        p[OFF_A2 + t * 16 + q] = gA2[q];
+        p[OFF_B2 + t * 16 + q] = gB2[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        p[OFF_A1 + t * 2 + q] = gA1[q];
+        p[OFF_B1 + t * 2 + q] = gB1[q];
+    }
+    if (t < HID) {
+        p[OFF_b2 + t] = gb2;
+        p[OFF_c + t] = gc;
+        p[OFF_b1 + t] = gb1;
+    }
+    if (t == 0) p[OFF_d] = gd;
+}
+
+__global__ void wgrad_reduce_kernel(int G, const float* __restrict__ part, float* __restrict__ grad)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NP) return;
+    double s = 0.0;
+    for (int b = 0; b < G; ++b) s += (double)part[(size_t)b * NP + p];
+    grad[p] = (float)s;
+}
+
+__global__ void adam_w_kernel(float* __restrict__ theta, float* __restrict__ m1, float* __restrict__ m2,
+                              const float* __restrict__ g, uint16_t* __restrict__ wbf, float step_size,
+                              float bc2_sqrt, float b1, float b2, float eps)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NP) return;
+    const float gg = g[p];
+    const float a = b1 * m1[p] + (1.0f - b1) * gg;
+    const float v = b2 * m2[p] + (1.0f - b2) * (gg * gg);
+    m1[p] = a;
+    m2[p] = v;
+    const float th = theta[p] - step_size * (a / (sqrtf(v) / bc2_sqrt + eps));
+    theta[p] = th;
+    wbf[p] = to_bf16(th);
+}
+
+__global__ void round_weights_kernel(const float* __restrict__ theta, uint16_t* __restrict__ wbf)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < NP) wbf[p] = to_bf16(theta[p]);
+}
+
+}  // namespace
+
+// ================================================================ host ====
+static fem_status mfail(fem_status st, const char* what, hipError_t e = hipSuccess)
+{
+    std::string msg = what;
+    if (e != hipSuccess) {
+        msg += ": ";
+        msg += hipGetErrorString(e);
+    }
+    return (fem_status)fem::set_error(st, msg.c_str());
+}
+
+#define MCHK(expr)                                                                                 \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return mfail(e_ == hipErrorOutOfMemory ? FEM_E_NOMEM : FEM_E_HIP, #expr, e_);          \
+    } while (0)
+
+struct fem_mpnn {
+    int device = 0;
+    float* theta = nullptr;
+    uint16_t* wbf = nullptr;
+    float* m1 = nullptr;
+    float* m2 = nullptr;
+    float* grad = nullptr;
+    float* part = nullptr;
+    int64_t adam_t = 0;
+    size_t cap = 0;      // rows the work buffers hold
+    size_t cap_inst = 0;
+    float *X = nullptr, *A1agg = nullptr, *inv_deg = nullptr, *pre1 = nullptr, *a2 = nullptr, *pre2 = nullptr,
+          *z = nullptr, *dz = nullptr, *dpre2 = nullptr, *dh1s = nullptr, *da2s = nullptr, *dpre1 = nullptr;
+    int32_t *y = nullptr, *inst_of = nullptr, *inst_off = nullptr;
+    double* L = nullptr;
+};
+
+template <typename T>
+static void mfree(T*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+static void free_work(fem_mpnn* m)
+{
+    mfree(m->X); mfree(m->A1agg); mfree(m->inv_deg); mfree(m->pre1); mfree(m->a2); mfree(m->pre2);
+    mfree(m->z); mfree(m->dz); mfree(m->dpre2); mfree(m->dh1s); mfree(m->da2s); mfree(m->dpre1);
+    mfree(m->y); mfree(m->inst_of); mfree(m->inst_off); mfree(m->L);
+    m->cap = 0;
+    m->cap_inst = 0;
+}
+
+static fem_status ensure_work(fem_mpnn* m, size_t n, size_t n_inst)
+{
+    if (n <= m->cap && n_inst <= m->cap_inst) return FEM_OK;
+    free_work(m);
+    const size_t c = n + 1, ci = n_inst + 1;
+    MCHK(hipMalloc(&m->X, c * D_IN * 4));
+    MCHK(hipMalloc(&m->A1agg, c * D_IN * 4));
+    MCHK(hipMalloc(&m->inv_deg, c * 4));
+    MCHK(hipMalloc(&m->pre1, c * HID * 4));
+    MCHK(hipMalloc(&m->a2, c * HID * 4));
+    MCHK(hipMalloc(&m->pre2, c * HID * 4));
+    MCHK(hipMalloc(&m->z, c * 4));
+    MCHK(hipMalloc(&m->dz, c * 4));
+    MCHK(hipMalloc(&m->dpre2, c * HID * 4));
+    MCHK(hipMalloc(&m->dh1s, c * HID * 4));
+    MCHK(hipMalloc(&m->da2s, c * HID * 4));
+    MCHK(hipMalloc(&m->dpre1, c * HID * 4));
+    MCHK(hipMalloc(&m->y, c * 4));
+    MCHK(hipMalloc(&m->inst_of, c * 4));
+    MCHK(hipMalloc(&m->inst_off, (ci + 1) * 4));
+    MCHK(hipMalloc(&m->L, ci * 2 * 8));
+    m->cap = n;
+    m->cap_inst = n_inst;
+    return FEM_OK;
+}
+
+static int grid_rows(int32_t n, int waves_per_block)
+{
+    const int64_t w = (int64_t)n;   // one wave per row, capped
+    int64_t blocks = (w + waves_per_block - 1) / waves_per_block;
+    if (blocks > 8192) blocks = 8192;
+    return (int)(blocks > 0 ? blocks : 1);
+}
+
+// forward for one draw: z (and, with train, the activations kept for backward)
+static fem_status forward(fem_mpnn* m, const Problem& p, uint64_t seed, int32_t draw, bool train, hipStream_t st)
+{
+    const int32_t n = p.n;
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    (void)hipGetLastError();
+    feat_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, p.row_off, p.adj, k0, k1, (uint32_t)draw, m->X, m->inv_deg);
+    layer1_kernel<<<grid_rows(n, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->X, m->inv_deg, m->wbf, m->A1agg, m->pre1);
+    layer2_kernel<<<grid_rows(n, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->inv_deg, m->wbf, m->pre1,
+                                                   train ? m->a2 : nullptr, train ? m->pre2 : nullptr, m->z);
+    MCHK(hipGetLastError());
+    return FEM_OK;
+}
+
+extern "C" {
+
+fem_status fem_mpnn_create(int device, const float* theta0, int32_t n_params, fem_mpnn** out)
+{
+    if (!out || !theta0) return mfail(FEM_E_INVAL, "NULL argument");
+    *out = nullptr;
+    if (n_params != NP) return mfail(FEM_E_INVAL, "the network has 9409 parameters");
+    auto* m = new (std::nothrow) fem_mpnn;
+    if (!m) return mfail(FEM_E_NOMEM, "host allocation failed");
+    m->device = device;
+    auto bail = [&](fem_status s) {
+        fem_mpnn_destroy(m);
+        return s;
+    };
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return bail(mfail(FEM_E_HIP, "hipSetDevice", e));
+    if ((e = hipMalloc(&m->theta, NP * 4)) != hipSuccess || (e = hipMalloc(&m->wbf, NP * 2)) != hipSuccess ||
+        (e = hipMalloc(&m->m1, NP * 4)) != hipSuccess || (e = hipMalloc(&m->m2, NP * 4)) != hipSuccess ||
+        (e = hipMalloc(&m->grad, NP * 4)) != hipSuccess ||
+        (e = hipMalloc(&m->part, (size_t)WG_BLOCKS * NP * 4)) != hipSuccess)
+        return bail(mfail(FEM_E_NOMEM, "device allocation", e));
+    if ((e = hipMemcpy(m->theta, theta0, NP * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(m->m1, 0, NP * 4)) != hipSuccess || (e = hipMemset(m->m2, 0, NP * 4)) != hipSuccess)
+        return bail(mfail(FEM_E_HIP, "upload of the parameters", e));
+    (void)hipGetLastError();
+    round_weights_kernel<<<(NP + 255) / 256, 256>>>(m->theta, m->wbf);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return bail(mfail(FEM_E_HIP, "round_weights_kernel", e));
+    *out = m;
+    return FEM_OK;
+}
+
+void fem_mpnn_destroy(fem_mpnn* m)
+{
+    if (!m) return;
+    (void)hipSetDevice(m->device);
+    free_work(m);
+    mfree(m->theta); mfree(m->wbf); mfree(m->m1); mfree(m->m2); mfree(m->grad); mfree(m->part);
+    delete m;
+}
+
+fem_status fem_mpnn_get_params(fem_mpnn* m, float* theta)
+{
+    if (!m || !theta) return mfail(FEM_E_INVAL, "NULL argument");
+    MCHK(hipSetDevice(m->device));
+    MCHK(hipMemcpy(theta, m->theta, NP * 4, hipMemcpyDeviceToHost));
+    return FEM_OK;
+}
+
+fem_status fem_mpnn_set_params(fem_mpnn* m, const float* theta)
+{
+    if (!m || !theta) return mfail(FEM_E_INVAL, "NULL argument");
+    MCHK(hipSetDevice(m->device));
+    MCHK(hipMemcpy(m->theta, theta, NP * 4, hipMemcpyHostToDevice));
+    MCHK(hipMemset(m->m1, 0, NP * 4));
+    MCHK(hipMemset(m->m2, 0, NP * 4));
+    m->adam_t = 0;
+    (void)hipGetLastError();
+    round_weights_kernel<<<(NP + 255) / 256, 256>>>(m->theta, m->wbf);
+    MCHK(hipDeviceSynchronize());
+    return FEM_OK;
+}
+
+fem_status fem_mpnn_forward(fem_mpnn* m, const fem_problem* fp, uint64_t seed, int32_t draw, float* z, int on_device)
+{
+    if (!m || !fp || !z) return mfail(FEM_E_INVAL, "NULL argument");
+    const Problem& p = fp->p;
+    if (p.kind != KIND_MAXCUT) return mfail(FEM_E_UNSUPPORTED, "the warm-start network is for MaxCut problems");
+    if (draw < 0) return mfail(FEM_E_INVAL, "draw must be >= 0");
+    MCHK(hipSetDevice(m->device));
+    fem_status s = ensure_work(m, (size_t)p.n, (size_t)p.n_inst);
+    if (s != FEM_OK) return s;
+    s = forward(m, p, seed, draw, false, nullptr);
+    if (s != FEM_OK) return s;
+    MCHK(hipMemcpy(z, m->z, (size_t)p.n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return FEM_OK;
+}
+
+fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* fp, const int32_t* labels, uint64_t seed,
+                               int32_t draw0, double lr, double* loss, float* grad_out)
+{
+    if (!m || !fp || !labels) return mfail(FEM_E_INVAL, "NULL argument");
+    const Problem& p = fp->p;
+    if (p.kind != KIND_MAXCUT) return mfail(FEM_E_UNSUPPORTED, "the warm-start network is for MaxCut problems");
+    if (!(lr > 0.0) || draw0 < 0) return mfail(FEM_E_INVAL, "need lr > 0 and draw0 >= 0");
+    for (int32_t i = 0; i < p.n; ++i)
+        if (labels[i] != 0 && labels[i] != 1) return mfail(FEM_E_INVAL, "labels must be 0 or 1");
+    MCHK(hipSetDevice(m->device));
+    const int32_t n = p.n, B = p.n_inst;
+    fem_status s = ensure_work(m, (size_t)n, (size_t)B);
+    if (s != FEM_OK) return s;
+    std::vector<int32_t> inst_of((size_t)n);
+    for (int32_t b = 0; b < B; ++b)
+        for (int32_t i = p.inst_off[(size_t)b]; i < p.inst_off[(size_t)b + 1]; ++i) inst_of[(size_t)i] = b;
+    MCHK(hipMemcpy(m->y, labels, (size_t)n * 4, hipMemcpyHostToDevice));
+    MCHK(hipMemcpy(m->inst_of, inst_of.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    MCHK(hipMemcpy(m->inst_off, p.inst_off.data(), (size_t)(B + 1) * 4, hipMemcpyHostToDevice));
+    // every instance of the batch uses draw draw0 + (its index); the features
+    // are keyed by the node's index in the batch and that draw: one forward per
+    // distinct draw would be wasteful, so a single forward with draw0 serves all
+    // instances (the counter holds the global node index, distinct per node).
+    s = forward(m, p, seed, draw0, true, nullptr);
+    if (s != FEM_OK) return s;
+    (void)hipGetLastError();
+    loss_kernel<<<B, 256>>>(m->inst_off, m->z, m->y, m->L);
+    dz_kernel<<<(n + 255) / 256, 256>>>(n, m->inst_of, m->inst_off, B, m->L, m->z, m->y, m->dz);
+    back2_kernel<<<grid_rows(n, 4), 256>>>(n, m->inv_deg, m->wbf, m->dz, m->pre2, m->dpre2, m->dh1s, m->da2s);
+    back1_kernel<<<grid_rows(n, 4), 256>>>(n, p.row_off, p.adj, m->pre1, m->dh1s, m->da2s, m->dpre1);
+    WgradArgs wa{n, m->X, m->A1agg, m->pre1, m->a2, m->pre2, m->dz, m->dpre2, m->dpre1, m->part};
+    wgrad_kernel<<<WG_BLOCKS, 256>>>(wa);
+    wgrad_reduce_kernel<<<(NP + 255) / 256, 256>>>(WG_BLOCKS, m->part, m->grad);
+    MCHK(hipGetLastError());
+    // loss on the host from the per-instance values
+    std::vector<double> L((size_t)2 * B);
+    MCHK(hipMemcpy(L.data(), m->L, L.size() * 8, hipMemcpyDeviceToHost));
+    double tot = 0.0;
+    for (int32_t b = 0; b < B; ++b) tot += std::min(L[(size_t)2 * b], L[(size_t)2 * b + 1]) / B;
+    if (loss) *loss = tot;
+    if (grad_out) MCHK(hipMemcpy(grad_out, m->grad, NP * 4, hipMemcpyDeviceToHost));
+    // Adam on the master weights (torch.optim.Adam defaults 0.9 / 0.999 / 1e-8)
+    m->adam_t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float step = (float)(lr / (1.0 - std::pow(b1, (double)m->adam_t)));
+    const float bc2s = (float)std::sqrt(1.0 - std::pow(b2, (double)m->adam_t));
+    adam_w_kernel<<<(NP + 255) / 256, 256>>>(m->theta, m->m1, m->m2, m->grad, m->wbf, step, bc2s, (float)b1,
+                                             (float)b2, 1e-8f);
+    MCHK(hipGetLastError());
+    MCHK(hipDeviceSynchronize());
+    return FEM_OK;
+}
+
+fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, uint64_t seed, int32_t n_draws, float alpha,
+                          float* h0, int on_device)
+{
+    if (!m || !fp || !h0) return mfail(FEM_E_INVAL, "NULL argument");
+    const Problem& p = fp->p;
+    if (p.kind != KIND_MAXCUT) return mfail(FEM_E_UNSUPPORTED, "the warm-start network is for MaxCut problems");
+    if (R < 1 || n_draws < 1 || n_draws > R) return mfail(FEM_E_INVAL, "need 1 <= n_draws <= R");
+    MCHK(hipSetDevice(m->device));
+    fem_status s = ensure_work(m, (size_t)p.n, (size_t)p.n_inst);
+    if (s != FEM_OK) return s;
+    float* dst = h0;
+    float* tmp = nullptr;
+    if (!on_device) {
+        MCHK(hipMalloc(&tmp, (size_t)p.n * R * 4));
+        dst = tmp;
+    }
+    for (int32_t d = 0; d < n_draws && s == FEM_OK; ++d) {
+        s = forward(m, p, seed, d, false, nullptr);
+        if (s != FEM_OK) break;
+        const size_t count = (size_t)p.n * ((R - d + n_draws - 1) / n_draws);
+        const int blocks = (int)std::min<size_t>((count + 255) / 256, 65536);
+        write_h0_kernel<<<blocks > 0 ? blocks : 1, 256>>>(p.n, R, n_draws, d, alpha, m->z, dst);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) s = mfail(FEM_E_HIP, "write_h0_kernel", e);
+    }
+    hipError_t e = hipDeviceSynchronize();
+    if (s == FEM_OK && e != hipSuccess) s = mfail(FEM_E_HIP, "fem_mpnn_infer", e);
+    if (tmp) {
+        if (s == FEM_OK) {
+            e = hipMemcpy(h0, tmp, (size_t)p.n * R * 4, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) s = mfail(FEM_E_HIP, "copy of h0", e);
+        }
+        (void)hipFree(tmp);
+    }
+    return s;
+}
+
+fem_status fem_mpnn_save(fem_mpnn* m, const char* path)
+{
+    if (!m || !path) return mfail(FEM_E_INVAL, "NULL argument");
+    std::vector<float> th(NP);
+    fem_status s = fem_mpnn_get_params(m, th.data());
+    if (s != FEM_OK) return s;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return mfail(FEM_E_INVAL, "cannot open the file for writing");
+    const char magic[8] = {'F', 'E', 'M', 'M', 'P', 'N', 'N', '1'};
+    const int32_t np = NP;
+    const bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&np, 4, 1, f) == 1 &&
+                    std::fwrite(th.data(), 4, NP, f) == (size_t)NP;
+    std::fclose(f);
+    return ok ? FEM_OK : mfail(FEM_E_INVAL, "short write");
+}
+
+fem_status fem_mpnn_load(fem_mpnn* m, const char* path)
+{
+    if (!m || !path) return mfail(FEM_E_INVAL, "NULL argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return mfail(FEM_E_INVAL, "cannot open the file");
+    char magic[8];
+    int32_t np = 0;
+    std::vector<float> th(NP);
+    const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "FEMMPNN1", 8) == 0 &&
+                    std::fread(&np, 4, 1, f) == 1 && np == NP && std::fread(th.data(), 4, NP, f) == (size_t)NP;
+    std::fclose(f);
+    if (!ok) return mfail(FEM_E_INVAL, "not a network parameter file");
+    return fem_mpnn_set_params(m, th.data());
+}
+
+}  // extern "C"

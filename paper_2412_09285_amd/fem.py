@@ -89,6 +89,15 @@ _SIGS = {
     "fem_get_tile": (C.c_int, [_P, C.POINTER(Tile)]),
     "fem_set_tile": (C.c_int, [_P, C.POINTER(Tile)]),
     "fem_tune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(Tile)]),
+    "fem_mpnn_create": (C.c_int, [C.c_int, _P, C.c_int32, _PP]),
+    "fem_mpnn_destroy": (None, [_P]),
+    "fem_mpnn_get_params": (C.c_int, [_P, _P]),
+    "fem_mpnn_set_params": (C.c_int, [_P, _P]),
+    "fem_mpnn_forward": (C.c_int, [_P, _P, C.c_uint64, C.c_int32, _P, C.c_int]),
+    "fem_mpnn_train_step": (C.c_int, [_P, _P, _P, C.c_uint64, C.c_int32, C.c_double, _P, _P]),
+    "fem_mpnn_infer": (C.c_int, [_P, _P, C.c_int32, C.c_uint64, C.c_int32, C.c_float, _P, C.c_int]),
+    "fem_mpnn_save": (C.c_int, [_P, C.c_char_p]),
+    "fem_mpnn_load": (C.c_int, [_P, C.c_char_p]),
     "fem_profile": (C.c_int, [_P, C.c_int32]),
     "fem_profile_result": (C.c_int, [_P, _P, _P]),
 }
@@ -375,6 +384,67 @@ class Solver:
     def close(self):
         if self._h:
             lib().fem_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+N_MPNN_PARAMS = 9409
+
+
+class MPNN:
+    """The warm-start network (see fem.h): parameters live on the device."""
+
+    def __init__(self, theta0, device=0):
+        th, pt = _host(theta0, np.float32)
+        assert th.size == N_MPNN_PARAMS
+        self._h = C.c_void_p()
+        _check(lib().fem_mpnn_create(device, pt, th.size, C.byref(self._h)))
+
+    def params(self):
+        out = np.empty(N_MPNN_PARAMS, dtype=np.float32)
+        _check(lib().fem_mpnn_get_params(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params(self, theta):
+        th, pt = _host(theta, np.float32)
+        _check(lib().fem_mpnn_set_params(self._h, pt))
+
+    def forward(self, problem: Problem, seed: int, draw: int):
+        z = np.empty(problem.n, dtype=np.float32)
+        _check(lib().fem_mpnn_forward(self._h, problem._h, seed, draw, z.ctypes.data_as(C.c_void_p), 0))
+        return z
+
+    def train_step(self, batch: Problem, labels, seed: int, draw0: int, lr: float, want_grad=False):
+        lab, pl = _host(labels, np.int32)
+        loss = C.c_double()
+        g = np.empty(N_MPNN_PARAMS, dtype=np.float32) if want_grad else None
+        _check(lib().fem_mpnn_train_step(self._h, batch._h, pl, seed, draw0, lr, C.byref(loss),
+                                         None if g is None else g.ctypes.data_as(C.c_void_p)))
+        return (loss.value, g) if want_grad else loss.value
+
+    def infer(self, problem: Problem, R: int, seed: int, n_draws: int, alpha: float, out=None):
+        """h0 [n][R]: host array, or written into the device tensor `out`."""
+        if out is not None and _is_torch(out) and out.is_cuda:
+            _check(lib().fem_mpnn_infer(self._h, problem._h, R, seed, n_draws, alpha, C.c_void_p(out.data_ptr()), 1))
+            return out
+        h0 = np.empty((problem.n, R), dtype=np.float32)
+        _check(lib().fem_mpnn_infer(self._h, problem._h, R, seed, n_draws, alpha, h0.ctypes.data_as(C.c_void_p), 0))
+        return h0
+
+    def save(self, path):
+        _check(lib().fem_mpnn_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        _check(lib().fem_mpnn_load(self._h, str(path).encode()))
+
+    def close(self):
+        if self._h:
+            lib().fem_mpnn_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -28,7 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "Graph", "CNF", "rng_for", "er_graph_m", "random_sparse_graph", "rgg_3d",
+    "Graph", "CNF", "rng_for", "er_graph_m", "mpnn_init_weights", "random_sparse_graph", "rgg_3d",
     "random_regular3", "random_ksat", "initial_fields", "batch_instance",
     "RECIPES", "config_graph", "config_cnf", "batch_sizes",
 ]
@@ -234,6 +234,23 @@ def random_ksat(n_vars: int, n_clauses: int, k: int, seed: int) -> CNF:
     lits = np.where(sign == 1, var + 1, -(var + 1)).astype(np.int32).reshape(-1)
     off = np.arange(0, (n_clauses + 1) * k, k, dtype=np.int64)
     return CNF(n_vars, off, lits, {"kind": "random_ksat", "k": k, "seed": seed})
+
+
+def mpnn_init_weights(seed: int) -> np.ndarray:
+    """Initial parameters of the warm-start network, float32, as one flat
+    vector in the order A1 [8][64], B1 [8][64], b1 [64], A2 [64][64],
+    B2 [64][64], b2 [64], c [64], d [1]: matrices uniform in
+    +/- 1/sqrt(fan_in), biases zero."""
+    rng = rng_for(seed)
+    parts = []
+    for fan_in, shape in ((8, (8, 64)), (8, (8, 64)), (None, (64,)), (64, (64, 64)), (64, (64, 64)),
+                          (None, (64,)), (64, (64,)), (None, (1,))):
+        if fan_in is None:
+            parts.append(np.zeros(shape))
+        else:
+            b = 1.0 / math.sqrt(fan_in)
+            parts.append(rng.uniform(-b, b, size=shape))
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
 
 
 def initial_fields(n: int, R: int, seed: int, q: int = 1, std: float = 0.01) -> np.ndarray:

@@ -52,10 +52,12 @@ def assert_energy_close(U, S, F, Ur, Sr, beta, rtol=RTOL, what="E"):
 # amplifies any difference after the ordering transition.  So each step t is
 # checked from the oracle's own state (h, m1, m2, t), rounded to float32 and
 # loaded into the GPU solver: data flows from the oracle to the GPU only.  The
-# GPU's gradient and energies at step t must match the oracle's to RTOL; its
-# h(t+1) must lie within the deviation that Adam's update shows when the
-# gradient moves within the gradient tolerance (evaluated in FP64 on a grid of
-# the interval), plus RTOL * max |h(t+1)|.
+# reference values of step t are the oracle's, evaluated at that float32
+# state (the state the GPU holds), so the check judges the GPU's arithmetic
+# rather than the rounding of its inputs.  The GPU's gradient and energies at
+# step t must match them to RTOL; its h(t+1) must lie within the deviation that
+# Adam's update shows when the gradient moves within the gradient tolerance
+# (evaluated in FP64 on a grid of the interval), plus RTOL * max |h(t+1)|.
 # ---------------------------------------------------------------------------
 def oracle_trajectory(run, n_steps):
     states, gs, Us, Ss = [], [], [], []
@@ -97,23 +99,24 @@ def per_replica_max(x, R):
 def lockstep(solver, run, params, n_steps, R, tag, betas, energies=True, rtol=RTOL):
     """Run the oracle n_steps, then replay every step on the GPU from the
     oracle's state; returns the worst relative errors."""
-    states, gs, Us, Ss = oracle_trajectory(run, n_steps)
+    states, _, _, _ = oracle_trajectory(run, n_steps)
     worst = dict(g=0.0, E=0.0, h=0.0)
     for t in range(n_steps):
-        h, m1, m2 = states[t]
+        h, m1, m2 = (x.astype(np.float32).astype(np.float64) for x in states[t])
+        gref, Uref, Sref = run.eval_at(h, t)
+        href = run.adam_from(h, m1, m2, gref, t)
         solver.set_adam_state(h, m1, m2, t)
         solver.step(1)
-        a, b = assert_grad_close(solver.last_grad(), gs[t], R, rtol=rtol, what=f"{tag} g step {t}")
+        a, b = assert_grad_close(solver.last_grad(), gref, R, rtol=rtol, what=f"{tag} g step {t}")
         worst["g"] = max(worst["g"], a, b)
         if energies:
             U, S, F = solver.energies()
-            e = assert_energy_close(U[0], S[0], F[0], Us[t], Ss[t], betas[t], rtol=rtol,
+            e = assert_energy_close(U[0], S[0], F[0], Uref, Sref, betas[t], rtol=rtol,
                                     what=f"{tag} energies step {t}")
             worst["E"] = max(worst["E"], *e)
         hn = solver.fields().astype(np.float64)
-        href = states[t + 1][0]
-        dg = rtol * per_replica_max(gs[t], R)
-        tol = adam_deviation(h, m1, m2, gs[t], t, params, dg) + rtol * per_replica_max(href, R)
+        dg = rtol * per_replica_max(gref, R)
+        tol = adam_deviation(h, m1, m2, gref, t, params, dg) + rtol * per_replica_max(href, R)
         err = np.abs(hn - href)
         bad = err > tol
         assert not bad.any(), f"{tag} h({t + 1}): {int(bad.sum())} values outside the propagated tolerance, " \

@@ -98,8 +98,8 @@ def test_round_ties_lowest_state():
 
 
 def test_bf16_gradient_bound_step0():
-    """BF16 copies of P change each gathered value by at most 2^-9 P_j(s), so
-    |dPhi_i(s)| <= 2^-9 sum_j W_ij P_j(s) =: e(s) and
+    """BF16 copies of P change each gathered value by at most 2^-8 P_j(s), so
+    |dPhi_i(s)| <= 2^-8 sum_j W_ij P_j(s) =: e(s) and
     |dg_i(s)| <= 2 P_i(s) [e(s) + sum_s' P_i(s') e(s')]  (plus float32 slack)."""
     g = W.rgg_3d(700, 14.0, seed=3)
     q, R = 8, 16
@@ -110,7 +110,7 @@ def test_bf16_gradient_bound_step0():
     phi = np.zeros_like(P)
     np.add.at(phi, g.u, g.w[:, None, None] * P[g.v])
     np.add.at(phi, g.v, g.w[:, None, None] * P[g.u])
-    e = 2.0 ** -9 * phi
+    e = 2.0 ** -8 * phi
     bound = 2 * P * (e + (P * e).sum(2, keepdims=True)) + 1e-5 * np.abs(res["gref"][0]).max()
     err = np.abs(res["grads"][0] - res["gref"][0])
     assert np.all(err <= bound), float((err - bound).max())
@@ -157,7 +157,7 @@ def test_config3_full_size_bf16_step0():
     phi = np.zeros_like(P)
     np.add.at(phi, g.u, g.w[:, None, None] * P[g.v])
     np.add.at(phi, g.v, g.w[:, None, None] * P[g.u])
-    e = 2.0 ** -9 * phi
+    e = 2.0 ** -8 * phi
     bound = 2 * P * (e + (P * e).sum(2, keepdims=True)) + 1e-5 * np.abs(gref).max()
     err = np.abs(gg[:, cols] - gref)
     assert np.all(err <= bound), float((err - bound).max())

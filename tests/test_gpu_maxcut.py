@@ -146,8 +146,8 @@ def test_config2_full_size_two_steps():
 
 def test_bf16_marginals_gradient_bound():
     """BF16 storage of m = tanh(h/2) changes each gathered value by at most
-    2^-9 |m_j| (round to nearest, 8 significant bits), so
-    |g_bf16 - g| <= P(1-P) * 2 * sum_j |W_ij| |m_j| 2^-9 on top of the float32
+    2^-8 |m_j| (round to nearest, 8 significant bits), so
+    |g_bf16 - g| <= P(1-P) * 2 * sum_j |W_ij| |m_j| 2^-8 on top of the float32
     rounding.  Checked on the first steps of C1 against the FP64 oracle; the
     free-running error over 100 steps is printed, not asserted."""
     g = W.config_graph(1)
@@ -161,7 +161,7 @@ def test_bf16_marginals_gradient_bound():
     np.add.at(phi_abs, g.u, np.abs(g.w)[:, None] * np.abs(m[g.v]))
     np.add.at(phi_abs, g.v, np.abs(g.w)[:, None] * np.abs(m[g.u]))
     p = 1 / (1 + np.exp(-h0))
-    bound = p * (1 - p) * 2 * phi_abs * 2.0 ** -9 + 1e-5 * np.abs(res["gref"][0]).max()
+    bound = p * (1 - p) * 2 * phi_abs * 2.0 ** -8 + 1e-5 * np.abs(res["gref"][0]).max()
     err = np.abs(res["grads"][0] - res["gref"][0])
     assert np.all(err <= bound), float((err - bound).max())
     rel, mx = grad_errors(res["grads"][-1], res["gref"][-1], R)

@@ -109,8 +109,8 @@ def test_bf16_close():
     res = free_run(cnf, R=64, T=2000, n_steps=30, seed=104, dtype=fem.BF16)
     rel, _ = grad_errors(res["grads"][0], res["gref"][0], 64)
     # stored min(P, 1-P) keeps 8 significant bits: each factor of a cavity
-    # product is off by <= 2^-9 relative
-    assert rel.max() < 4 * 2.0 ** -9, rel.max()
+    # product is off by <= 2^-8 relative
+    assert rel.max() < 4 * 2.0 ** -8, rel.max()
     rel2, _ = grad_errors(res["grads"][-1], res["gref"][-1], 64)
     print(f"[3sat bf16] step-0 grad rel {rel.max():.2e}, step-29 grad rel {rel2.max():.2e}", flush=True)
 
