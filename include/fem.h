@@ -129,10 +129,20 @@ typedef struct {
     int32_t record_energies;   /* keep the energies of every evaluated step */
     int32_t eval_every;        /* anytime read-out every k steps (0 = only on request) */
     int32_t keep_grad;         /* keep the last gradient for fem_last_grad */
+    int32_t optimizer;         /* FEM_OPT_ADAM | FEM_OPT_RMSPROP | FEM_OPT_SGD */
+    double momentum;           /* RMSprop / SGD momentum */
+    double rms_alpha;          /* RMSprop smoothing constant */
+    double dampening;          /* SGD dampening */
 } fem_params;
 
+/* Optimisers, torch.optim semantics (the paper uses PyTorch's Adam, RMSprop
+ * and SGD; Methods, "Hyperparameter tuning").  The Adam moments m1, m2 hold
+ * RMSprop's momentum buffer and square average, or SGD's momentum buffer. */
+enum { FEM_OPT_ADAM = 0, FEM_OPT_RMSPROP = 1, FEM_OPT_SGD = 2 };
+
 /* Adam 0.9 / 0.999 / 1e-8, lr 0.1, no weight decay, linear beta 0.01 -> 5,
- * R = 16, T = 500, F32 marginals, energies every step, no recording. */
+ * R = 16, T = 500, F32 marginals, energies every step, no recording;
+ * RMSprop alpha 0.99, no momentum or dampening. */
 void fem_params_default(fem_params* p);
 
 /* hip_stream: a hipStream_t on the problem's device (NULL = the null stream).

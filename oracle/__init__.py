@@ -50,6 +50,7 @@ class _Problem(C.Structure):
         ("beta_min", C.c_double), ("beta_max", C.c_double), ("lam", C.c_double),
         ("lr", C.c_double), ("b1", C.c_double), ("b2", C.c_double),
         ("eps", C.c_double), ("wd", C.c_double),
+        ("opt", C.c_int32), ("momentum", C.c_double), ("rms_alpha", C.c_double), ("dampening", C.c_double),
     ]
 
 
@@ -74,6 +75,11 @@ def lib():
         L.orc_adam.restype = None
         L.orc_adam.argtypes = [C.c_int64, P, P, P, P, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_double, C.c_int64]
+        L.orc_rmsprop.restype = None
+        L.orc_rmsprop.argtypes = [C.c_int64, P, P, P, P, C.c_double, C.c_double, C.c_double, C.c_double,
+                                  C.c_double]
+        L.orc_sgd.restype = None
+        L.orc_sgd.argtypes = [C.c_int64, P, P, P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64]
         L.orc_round.restype = None
         L.orc_round.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P]
         L.orc_cut.restype = None
@@ -160,6 +166,22 @@ def maxsat_grad(n, off, lits, h, beta_, want_grad=True):
     return g, U, S
 
 
+def rmsprop(g, h, m1, m2, lr, alpha, eps, wd, momentum):
+    """In-place RMSprop (torch semantics, not centred) on float64 arrays."""
+    for a in (h, m1, m2):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib().orc_rmsprop(h.size, _p(g), _p(h), _p(m1), _p(m2), lr, alpha, eps, wd, momentum)
+
+
+def sgd(g, h, m1, lr, wd, momentum, dampening, n_step):
+    """In-place SGD with momentum (torch semantics) on float64 arrays."""
+    for a in (h, m1):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib().orc_sgd(h.size, _p(g), _p(h), _p(m1), lr, wd, momentum, dampening, int(n_step))
+
+
 def adam(g, h, m1, m2, lr, b1, b2, eps, wd, n_step):
     """In-place Adam on float64 arrays h, m1, m2 (all contiguous)."""
     for a in (h, m1, m2):
@@ -223,6 +245,10 @@ class Params:
     wd: float = 0.0
     lam: float = 0.0
     lam_ramp: int = 0
+    opt: int = 0            # 0 Adam, 1 RMSprop, 2 SGD
+    momentum: float = 0.0
+    rms_alpha: float = 0.99
+    dampening: float = 0.0
 
 
 class Run:
@@ -250,6 +276,8 @@ class Run:
             pb.eu, pb.ev, pb.w = u.ctypes.data, v.ctypes.data, w.ctypes.data
         pb.beta_min, pb.beta_max, pb.lam = params.beta_min, params.beta_max, params.lam
         pb.lr, pb.b1, pb.b2, pb.eps, pb.wd = params.lr, params.b1, params.b2, params.eps, params.wd
+        pb.opt, pb.momentum, pb.rms_alpha, pb.dampening = params.opt, params.momentum, params.rms_alpha, \
+            params.dampening
         self._pb = pb
 
     def step(self, n_steps: int, record: bool = False):
@@ -287,10 +315,16 @@ class Run:
         return maxsat_grad(self.n, off, lits, h, b)
 
     def adam_from(self, h, m1, m2, g, t):
-        """Fields after the Adam step of step t from (h, m1, m2) with gradient g."""
+        """Fields after the optimiser step of step t from (h, m1, m2) with
+        gradient g (Adam, RMSprop or SGD as the parameters say)."""
         p = self.p
         hh, a, b = (np.array(x, dtype=np.float64, copy=True) for x in (h, m1, m2))
-        adam(g, hh, a, b, p.lr, p.b1, p.b2, p.eps, p.wd, t + 1)
+        if p.opt == 1:
+            rmsprop(g, hh, a, b, p.lr, p.rms_alpha, p.eps, p.wd, p.momentum)
+        elif p.opt == 2:
+            sgd(g, hh, a, p.lr, p.wd, p.momentum, p.dampening, t + 1)
+        else:
+            adam(g, hh, a, b, p.lr, p.b1, p.b2, p.eps, p.wd, t + 1)
         return hh
 
 

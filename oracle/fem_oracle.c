@@ -341,6 +341,40 @@ void orc_adam(int64_t count, const double* g_in, double* h, double* m1, double* 
     }
 }
 
+/* RMSprop, PyTorch semantics (not centred): m2 = square average, m1 = the
+ * momentum buffer (used when momentum > 0).  The paper tunes lr, alpha,
+ * momentum and weight decay (Methods, "Hyperparameter tuning"). */
+void orc_rmsprop(int64_t count, const double* g_in, double* h, double* m1, double* m2,
+                 double lr, double alpha, double eps, double wd, double momentum)
+{
+    for (int64_t k = 0; k < count; ++k) {
+        double g = g_in[k] + wd * h[k];
+        m2[k] = alpha * m2[k] + (1.0 - alpha) * g * g;
+        double avg = sqrt(m2[k]) + eps;
+        if (momentum > 0.0) {
+            m1[k] = momentum * m1[k] + g / avg;
+            h[k] -= lr * m1[k];
+        } else {
+            h[k] -= lr * g / avg;
+        }
+    }
+}
+
+/* SGD, PyTorch semantics: with momentum, the buffer starts as the first
+ * gradient and then follows buf = momentum buf + (1 - dampening) g. */
+void orc_sgd(int64_t count, const double* g_in, double* h, double* m1, double lr, double wd,
+             double momentum, double dampening, int64_t n_step)
+{
+    for (int64_t k = 0; k < count; ++k) {
+        double g = g_in[k] + wd * h[k];
+        if (momentum != 0.0) {
+            m1[k] = (n_step == 1) ? g : momentum * m1[k] + (1.0 - dampening) * g;
+            g = m1[k];
+        }
+        h[k] -= lr * g;
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Read-out (Results, "Free-Energy Machine": argmax of each replica's         */
 /* marginals, then the replica of lowest energy).                             */
@@ -424,6 +458,8 @@ typedef struct {
     const int64_t* off;     /* SAT */
     const int32_t* lits;
     double beta_min, beta_max, lam, lr, b1, b2, eps, wd;
+    int32_t opt;            /* 0 Adam, 1 RMSprop, 2 SGD */
+    double momentum, rms_alpha, dampening;
 } orc_problem;
 
 int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, double* m1,
@@ -448,7 +484,12 @@ int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, doubl
             rc = orc_maxsat_grad(pb->n, pb->ne, pb->off, pb->lits, pb->R, h, beta, g, U, S);
         if (rc) { free(g); return rc; }
         if (g_hist) memcpy(g_hist + (size_t)k * vals, g, sizeof(double) * vals);
-        orc_adam((int64_t)vals, g, h, m1, m2, pb->lr, pb->b1, pb->b2, pb->eps, pb->wd, (int64_t)t + 1);
+        if (pb->opt == 1)
+            orc_rmsprop((int64_t)vals, g, h, m1, m2, pb->lr, pb->rms_alpha, pb->eps, pb->wd, pb->momentum);
+        else if (pb->opt == 2)
+            orc_sgd((int64_t)vals, g, h, m1, pb->lr, pb->wd, pb->momentum, pb->dampening, (int64_t)t + 1);
+        else
+            orc_adam((int64_t)vals, g, h, m1, m2, pb->lr, pb->b1, pb->b2, pb->eps, pb->wd, (int64_t)t + 1);
     }
     free(g);
     return 0;

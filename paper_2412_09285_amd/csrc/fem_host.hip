@@ -542,6 +542,13 @@ static StepScalars step_scalars(const fem_solver* s, int t)
     sc.one_m_b2 = (float)(1.0 - p.adam_b2);
     sc.eps = (float)p.adam_eps;
     sc.wd = (float)p.weight_decay;
+    sc.opt = p.optimizer;
+    sc.first = (t == 0) ? 1 : 0;
+    sc.mom = (float)p.momentum;
+    sc.damp = (float)p.dampening;
+    sc.rms_alpha = (float)p.rms_alpha;
+    sc.one_m_rms = (float)(1.0 - p.rms_alpha);
+    sc.lr = (float)p.lr;
     return sc;
 }
 
@@ -877,6 +884,10 @@ void fem_params_default(fem_params* p)
     p->record_energies = 0;
     p->eval_every = 0;
     p->keep_grad = 0;
+    p->optimizer = FEM_OPT_ADAM;
+    p->momentum = 0.0;
+    p->rms_alpha = 0.99;
+    p->dampening = 0.0;
 }
 
 fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void* hip_stream, fem_solver** out)
@@ -894,6 +905,9 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
         !(P.adam_eps >= 0.0) || !(P.weight_decay >= 0.0))
         return fail(FEM_E_INVAL, "invalid Adam hyper-parameters");
     if (!std::isfinite(P.lambda) || P.lambda < 0.0) return fail(FEM_E_INVAL, "lambda must be finite and >= 0");
+    if (P.optimizer < 0 || P.optimizer > 2) return fail(FEM_E_INVAL, "unknown optimizer %d", P.optimizer);
+    if (!(P.momentum >= 0.0) || !(P.rms_alpha >= 0.0 && P.rms_alpha < 1.0) || !(P.dampening >= 0.0 && P.dampening <= 1.0))
+        return fail(FEM_E_INVAL, "invalid momentum, rms_alpha or dampening");
     if (P.marginal_dtype != FEM_F32 && P.marginal_dtype != FEM_BF16) return fail(FEM_E_INVAL, "unknown marginal dtype");
     if (P.energy_every < 0 || P.eval_every < 0) return fail(FEM_E_INVAL, "energy_every and eval_every must be >= 0");
     const Problem& p = fp->p;

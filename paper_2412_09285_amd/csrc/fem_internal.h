@@ -77,6 +77,9 @@ struct StepScalars {
     float step_size;   // lr / (1 - b1^n)
     float bc2_sqrt;    // sqrt(1 - b2^n)
     float b1, one_m_b1, b2, one_m_b2, eps, wd;
+    int opt;            // 0 Adam, 1 RMSprop, 2 SGD
+    int first;          // SGD: first step (the momentum buffer starts as g)
+    float mom, damp, rms_alpha, one_m_rms, lr;
 };
 
 struct LaunchGeom {

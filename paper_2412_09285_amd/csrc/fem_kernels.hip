@@ -184,19 +184,60 @@ __device__ __forceinline__ void st_state(float* __restrict__ p, const float (&x)
     }
 }
 
-// Adam, torch.optim.Adam semantics: g += wd*h; m1 = b1 m1 + (1-b1) g;
-// m2 = b2 m2 + (1-b2) g^2; h -= step_size * m1 / (sqrt(m2)/sqrt(1-b2^n) + eps)
+// The optimiser step, torch.optim semantics (a uniform branch):
+//  Adam:    g += wd h; m1 = b1 m1 + (1-b1) g; m2 = b2 m2 + (1-b2) g^2;
+//           h -= step_size * m1 / (sqrt(m2)/sqrt(1-b2^n) + eps)
+//  RMSprop: g += wd h; m2 = a m2 + (1-a) g^2; d = sqrt(m2) + eps;
+//           momentum > 0: m1 = mu m1 + g/d, h -= lr m1;  else h -= lr g/d
+//  SGD:     g += wd h; momentum != 0: m1 = g (first step) or mu m1 + (1-damp) g,
+//           g = m1;  h -= lr g
 __device__ __forceinline__ float adam_update(float x, float g, float& m1, float& m2, const StepScalars& s)
 {
     g = g + s.wd * x;
-    m1 = s.b1 * m1 + s.one_m_b1 * g;
-    m2 = s.b2 * m2 + s.one_m_b2 * (g * g);
-    float denom = sqrtf(m2) / s.bc2_sqrt + s.eps;
-    return x - s.step_size * (m1 / denom);
+    if (s.opt == 0) {
+        m1 = s.b1 * m1 + s.one_m_b1 * g;
+        m2 = s.b2 * m2 + s.one_m_b2 * (g * g);
+        float denom = sqrtf(m2) / s.bc2_sqrt + s.eps;
+        return x - s.step_size * (m1 / denom);
+    }
+    if (s.opt == 1) {
+        m2 = s.rms_alpha * m2 + s.one_m_rms * (g * g);
+        const float d = sqrtf(m2) + s.eps;
+        if (s.mom > 0.0f) {
+            m1 = s.mom * m1 + g / d;
+            return x - s.lr * m1;
+        }
+        return x - s.lr * (g / d);
+    }
+    if (s.mom != 0.0f) {
+        m1 = s.first ? g : s.mom * m1 + (1.0f - s.damp) * g;
+        g = m1;
+    }
+    return x - s.lr * g;
 }
 
 // 2^-40 fixed point of a probability in [0, 1]
-__device__ __forceinline__ long long to_fixed(float p) { return (long long)rintf(p * 1099511627776.0f); }
+__device__ __forceinline__ long long to_fixed(double p) { return (long long)rint(p * 1099511627776.0); }
+
+// Column-sum contributions of one replica's softmax, formed in double: the sum
+// over all nodes of float32 marginals would carry their rounding into the
+// global balance term.
+template <int Q>
+__device__ __forceinline__ void colsum_add(const float (&h)[Q], long long (&cs)[Q])
+{
+    float mx = h[0];
+#pragma unroll
+    for (int s = 1; s < Q; ++s) mx = fmaxf(mx, h[s]);
+    double e[Q], Z = 0.0;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+        e[s] = exp((double)h[s] - (double)mx);
+        Z += e[s];
+    }
+    const double iz = 1.0 / Z;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) cs[s] += to_fixed(e[s] * iz);
+}
 
 // Max-k-SAT stored marginal: the smaller of P(x=1) and P(x=0), negative (sign
 // bit set) when P(x=1) > 1/2.  Both tails keep full relative precision.
@@ -283,9 +324,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
     const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
-    double eacc[2 * V];
+    // per-lane energy terms over the few rows of one team (float), widened
+    // to double for the workgroup and tile sums
+    float eacc[2 * V];
 #pragma unroll
-    for (int k = 0; k < 2 * V; ++k) eacc[k] = 0.0;
+    for (int k = 0; k < 2 * V; ++k) eacc[k] = 0.0f;
 
     if (act) {
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
@@ -337,8 +380,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 const float g = (float)((double)pq * (2.0 * acc[v] + (double)x * sc.inv_beta_d));
                 gv[v] = g;
                 if constexpr (EN) {
-                    eacc[v] += (double)tanhf(0.5f * x) * acc[v];
-                    eacc[V + v] += (double)(log1pf(e) + ax * (e / ope));
+                    eacc[v] += (float)((double)tanhf(0.5f * x) * acc[v]);
+                    eacc[V + v] += log1pf(e) + ax * (e / ope);
                 }
                 const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
                 hv[v] = nh;
@@ -353,7 +396,10 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
     }
     if constexpr (EN) {
         extern __shared__ double lds_d[];
-        block_reduce_store<double, 2 * V>(eacc, ti, a.lanes_log2, lds_d, [&](int k, int l, double s) {
+        double ed[2 * V];
+#pragma unroll
+        for (int k = 0; k < 2 * V; ++k) ed[k] = (double)eacc[k];
+        block_reduce_store<double, 2 * V>(ed, ti, a.lanes_log2, lds_d, [&](int k, int l, double s) {
             const int term = k / V, v = k % V;
             const int r = (blockIdx.y * ti.L + l) * V + v;
             if (r < R) a.epart[((size_t)tile.slot * 2 + term) * R + r] = s;
@@ -473,10 +519,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             for (int s = 0; s < Q; ++s) { Pn[s] = expf(hv[s] - mx2); Z2 += Pn[s]; }
             const float invZ2 = 1.0f / Z2;
 #pragma unroll
-            for (int s = 0; s < Q; ++s) {
-                Pn[s] *= invZ2;
-                cs[s] += to_fixed(Pn[s]);
-            }
+            for (int s = 0; s < Q; ++s) Pn[s] *= invZ2;
+            colsum_add<Q>(hv, cs);
             st_state<Q, NT>(a.h + base, hv);
             st_state<Q, NT>(a.m1 + base, m1v);
             st_state<Q, NT>(a.m2 + base, m2v);
@@ -529,9 +573,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
     const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
-    double eacc[2 * V];
+    float eacc[2 * V];
 #pragma unroll
-    for (int k = 0; k < 2 * V; ++k) eacc[k] = 0.0;
+    for (int k = 0; k < 2 * V; ++k) eacc[k] = 0.0f;
     using Rec = typename SatRec<W>::T;
     const Rec* __restrict__ inc = reinterpret_cast<const Rec*>(W == 2 ? (const void*)a.inc2 : (const void*)a.inc4);
 
@@ -587,7 +631,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                     if constexpr (EN) {
                         if (owner) {
                             const float uo = (own_pos == own_hi[v]) ? own_small[v] : 1.0f - own_small[v];
-                            eacc[v] += (double)(uo * c[v]);
+                            eacc[v] += uo * c[v];
                         }
                     }
                 }
@@ -602,7 +646,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 const float pq = e / (ope * ope);
                 const float g = (float)((double)pq * (d[v] + (double)x * sc.inv_beta_d));
                 gv[v] = g;
-                if constexpr (EN) eacc[V + v] += (double)(log1pf(e) + ax * (e / ope));
+                if constexpr (EN) eacc[V + v] += log1pf(e) + ax * (e / ope);
                 const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
                 hv[v] = nh;
                 snew[v] = sat_encode(nh);
@@ -616,7 +660,10 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
     }
     if constexpr (EN) {
         extern __shared__ double lds_d[];
-        block_reduce_store<double, 2 * V>(eacc, ti, a.lanes_log2, lds_d, [&](int k, int l, double s) {
+        double ed[2 * V];
+#pragma unroll
+        for (int k = 0; k < 2 * V; ++k) ed[k] = (double)eacc[k];
+        block_reduce_store<double, 2 * V>(ed, ti, a.lanes_log2, lds_d, [&](int k, int l, double s) {
             const int term = k / V, v = k % V;
             const int r = (blockIdx.y * ti.L + l) * V + v;
             if (r < R) a.epart[((size_t)tile.slot * 2 + term) * R + r] = s;
@@ -638,7 +685,7 @@ __global__ void init_q1_kernel(int kind, const float* __restrict__ h, MT* __rest
 }
 
 template <int Q, typename MT>
-__global__ void __launch_bounds__(1024) potts_init_kernel(StepArgs a)
+__global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_init_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blockIdx.x];
     const TeamIdx ti = team_idx(a.lanes_log2);
@@ -662,7 +709,8 @@ __global__ void __launch_bounds__(1024) potts_init_kernel(StepArgs a)
             for (int s = 0; s < Q; ++s) { P[s] = expf(hv[s] - mx); Z += P[s]; }
             const float invZ = 1.0f / Z;
 #pragma unroll
-            for (int s = 0; s < Q; ++s) { P[s] *= invZ; cs[s] += to_fixed(P[s]); }
+            for (int s = 0; s < Q; ++s) P[s] *= invZ;
+            colsum_add<Q>(hv, cs);
             st_marg<MT, Q>(mn + base, P);
         }
     }

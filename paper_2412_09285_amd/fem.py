@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libfem.so")
 FEM_OK, FEM_E_INVAL, FEM_E_NOMEM, FEM_E_HIP, FEM_E_STATE, FEM_E_NUMERIC, FEM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MAXCUT, BMINCUT, MAXSAT = 0, 1, 2
 SCHED_LINEAR, SCHED_EXP, SCHED_INVPROP = 0, 1, 2
+OPT_ADAM, OPT_RMSPROP, OPT_SGD = 0, 1, 2
 F32, BF16 = 0, 1
 
 
@@ -41,6 +42,7 @@ class Params(C.Structure):
         ("lam", C.c_double), ("lambda_ramp", C.c_int32),
         ("marginal_dtype", C.c_int32), ("energy_every", C.c_int32),
         ("record_energies", C.c_int32), ("eval_every", C.c_int32), ("keep_grad", C.c_int32),
+        ("optimizer", C.c_int32), ("momentum", C.c_double), ("rms_alpha", C.c_double), ("dampening", C.c_double),
     ]
 
 

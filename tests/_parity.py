@@ -70,13 +70,25 @@ def oracle_trajectory(run, n_steps):
 
 
 def adam_deviation(h, m1, m2, g, t, p, dg, npts=9):
-    """max_{|e| <= dg} |Adam(h, m1, m2, g + e) - Adam(h, m1, m2, g)| (FP64)."""
+    """max_{|e| <= dg} |U(h, m1, m2, g + e) - U(h, m1, m2, g)| (FP64), U the
+    optimiser update (Adam, or RMSprop / SGD when p.opt says so)."""
     n = t + 1
     bc1 = 1 - p.b1 ** n
     bc2s = np.sqrt(1 - p.b2 ** n)
+    opt = getattr(p, "opt", 0)
 
     def upd(gg):
         gg = gg + p.wd * h
+        if opt == 1:
+            b = p.rms_alpha * m2 + (1 - p.rms_alpha) * gg * gg
+            d = np.sqrt(b) + p.eps
+            if p.momentum > 0:
+                return h - p.lr * (p.momentum * m1 + gg / d)
+            return h - p.lr * gg / d
+        if opt == 2:
+            if p.momentum != 0:
+                gg = gg if t == 0 else p.momentum * m1 + (1 - p.dampening) * gg
+            return h - p.lr * gg
         a = p.b1 * m1 + (1 - p.b1) * gg
         b = p.b2 * m2 + (1 - p.b2) * gg * gg
         return h - (p.lr / bc1) * a / (np.sqrt(b) / bc2s + p.eps)

@@ -43,6 +43,7 @@ def test_params_default_layout():
     assert (p.adam_b1, p.adam_b2, p.adam_eps, p.weight_decay) == (0.9, 0.999, 1e-8, 0.0)
     assert (p.lam, p.lambda_ramp, p.marginal_dtype) == (0.0, 0, 0)
     assert (p.energy_every, p.record_energies, p.eval_every, p.keep_grad) == (1, 0, 0, 0)
+    assert (p.optimizer, p.momentum, p.rms_alpha, p.dampening) == (0, 0.0, 0.99, 0.0)
 
 
 @pytest.mark.parametrize("args,msg", [

@@ -167,3 +167,24 @@ def test_bf16_marginals_gradient_bound():
     rel, mx = grad_errors(res["grads"][-1], res["gref"][-1], R)
     hrel, _ = grad_errors(res["h"], res["href"], R)
     print(f"[C1 bf16] step-99 grad rel err {rel.max():.2e}, h(100) rel err {hrel.max():.2e}", flush=True)
+
+
+@pytest.mark.parametrize("opt,kw", [(fem.OPT_RMSPROP, dict(momentum=0.63, rms_alpha=0.56, lr=0.03, weight_decay=0.013)),
+                                    (fem.OPT_RMSPROP, dict(momentum=0.0, rms_alpha=0.9, lr=0.02)),
+                                    (fem.OPT_SGD, dict(momentum=0.9, dampening=0.1, lr=0.05, weight_decay=0.01))])
+def test_rmsprop_and_sgd_lockstep(opt, kw):
+    """The paper's other optimisers (RMSprop with momentum, SGD), fused in the
+    same kernel: 40 lockstep steps on the ER-800 workload, inverse-proportional
+    schedule as in the paper's MaxCut runs."""
+    g = W.config_graph(1)
+    R, T = 16, 400
+    h0 = W.initial_fields(g.n, R, seed=11)
+    prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1, optimizer=opt, schedule=2,
+                                            beta_min=1 / 1.16, beta_max=50.0, **kw))
+    P = O.Params(R=R, T=T, opt=opt, sched=2, beta_min=1 / 1.16, beta_max=50.0, lr=kw["lr"],
+                 wd=kw.get("weight_decay", 0.0), momentum=kw.get("momentum", 0.0),
+                 rms_alpha=kw.get("rms_alpha", 0.99), dampening=kw.get("dampening", 0.0))
+    run = O.maxcut_run(g, P, h0)
+    betas = [O.beta(2, P.beta_min, P.beta_max, T, t) for t in range(40)]
+    lockstep(s, run, P, 40, R, f"opt{opt}", betas)

@@ -487,3 +487,40 @@ def test_replica_independence(orc):
     b = orc.maxcut_run(g, P1, h0[:, 4:5])
     b.step(50)
     assert np.array_equal(a.h[:, 4:5], b.h)
+
+
+@pytest.mark.parametrize("momentum,wd", [(0.0, 0.0), (0.63, 0.013)])
+def test_rmsprop_matches_torch(orc, momentum, wd):
+    import torch
+
+    rng = np.random.default_rng(1)
+    h = rng.normal(size=123)
+    m1 = np.zeros_like(h)
+    m2 = np.zeros_like(h)
+    th = torch.tensor(h.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.RMSprop([th], lr=0.03, alpha=0.56, eps=1e-8, weight_decay=wd, momentum=momentum)
+    for step in range(30):
+        gr = rng.normal(size=h.shape) * (10.0 ** rng.uniform(-4, 1))
+        orc.rmsprop(gr, h, m1, m2, 0.03, 0.56, 1e-8, wd, momentum)
+        opt.zero_grad()
+        th.grad = torch.tensor(gr)
+        opt.step()
+        assert np.allclose(h, th.detach().numpy(), rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("momentum,damp,wd", [(0.0, 0.0, 0.0), (0.9, 0.0, 0.02), (0.7, 0.3, 0.0)])
+def test_sgd_matches_torch(orc, momentum, damp, wd):
+    import torch
+
+    rng = np.random.default_rng(2)
+    h = rng.normal(size=77)
+    m1 = np.zeros_like(h)
+    th = torch.tensor(h.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.SGD([th], lr=0.05, momentum=momentum, dampening=damp, weight_decay=wd)
+    for step in range(1, 30):
+        gr = rng.normal(size=h.shape)
+        orc.sgd(gr, h, m1, 0.05, wd, momentum, damp, step)
+        opt.zero_grad()
+        th.grad = torch.tensor(gr)
+        opt.step()
+        assert np.allclose(h, th.detach().numpy(), rtol=1e-13, atol=1e-14)
