@@ -51,6 +51,7 @@ class _Problem(C.Structure):
         ("lr", C.c_double), ("b1", C.c_double), ("b2", C.c_double),
         ("eps", C.c_double), ("wd", C.c_double),
         ("opt", C.c_int32), ("momentum", C.c_double), ("rms_alpha", C.c_double), ("dampening", C.c_double),
+        ("manip", C.c_int32), ("gamma", C.c_double),
     ]
 
 
@@ -72,6 +73,15 @@ def lib():
                                        C.c_int32, P, C.c_double, P, P, P]
         L.orc_maxsat_grad.restype = C.c_int
         L.orc_maxsat_grad.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P, C.c_double, P, P, P]
+        L.orc_maxcut_grad_manip.restype = C.c_int
+        L.orc_maxcut_grad_manip.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, C.c_double,
+                                            C.c_double, P]
+        L.orc_bmincut_grad_manip.restype = C.c_int
+        L.orc_bmincut_grad_manip.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, C.c_double,
+                                             C.c_int32, P, C.c_double, C.c_double, P]
+        L.orc_maxsat_grad_manip.restype = C.c_int
+        L.orc_maxsat_grad_manip.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P, C.c_double,
+                                            C.c_double, P]
         L.orc_adam.restype = None
         L.orc_adam.argtypes = [C.c_int64, P, P, P, P, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_double, C.c_int64]
@@ -166,6 +176,41 @@ def maxsat_grad(n, off, lits, h, beta_, want_grad=True):
     return g, U, S
 
 
+def maxcut_grad_manip(n, u, v, w, h, beta_, gamma=1.0):
+    """Manipulated MaxCut gradient (one-hot neighbours, 1/sum|W| normalisation);
+    h: [n][R] float64.  Returns g [n][R]."""
+    h = _f64(h)
+    u, v, w = _i32(u), _i32(v), _f64(w)
+    g = np.zeros_like(h)
+    rc = lib().orc_maxcut_grad_manip(n, u.shape[0], _p(u), _p(v), _p(w), h.shape[1], _p(h), beta_, gamma, _p(g))
+    if rc:
+        raise MemoryError(rc)
+    return g
+
+
+def bmincut_grad_manip(n, u, v, w, q, lam_, h, beta_, gamma=1.0):
+    """Manipulated bMinCut gradient; h: [n][R][q] float64.  Returns g."""
+    h = _f64(h)
+    u, v, w = _i32(u), _i32(v), _f64(w)
+    g = np.zeros_like(h)
+    rc = lib().orc_bmincut_grad_manip(n, u.shape[0], _p(u), _p(v), _p(w), q, lam_, h.shape[1], _p(h), beta_,
+                                      gamma, _p(g))
+    if rc:
+        raise MemoryError(rc)
+    return g
+
+
+def maxsat_grad_manip(n, off, lits, h, beta_, gamma=1.0):
+    h = _f64(h)
+    off, lits = _i64(off), _i32(lits)
+    g = np.zeros_like(h)
+    rc = lib().orc_maxsat_grad_manip(n, off.shape[0] - 1, _p(off), _p(lits), h.shape[1], _p(h), beta_, gamma,
+                                     _p(g))
+    if rc:
+        raise MemoryError(rc)
+    return g
+
+
 def rmsprop(g, h, m1, m2, lr, alpha, eps, wd, momentum):
     """In-place RMSprop (torch semantics, not centred) on float64 arrays."""
     for a in (h, m1, m2):
@@ -249,6 +294,8 @@ class Params:
     momentum: float = 0.0
     rms_alpha: float = 0.99
     dampening: float = 0.0
+    manip: int = 0          # 1: manipulated gradients (energies are not formed)
+    gamma: float = 1.0      # gamma_grad of the manipulated form
 
 
 class Run:
@@ -278,6 +325,7 @@ class Run:
         pb.lr, pb.b1, pb.b2, pb.eps, pb.wd = params.lr, params.b1, params.b2, params.eps, params.wd
         pb.opt, pb.momentum, pb.rms_alpha, pb.dampening = params.opt, params.momentum, params.rms_alpha, \
             params.dampening
+        pb.manip, pb.gamma = int(params.manip), params.gamma
         self._pb = pb
 
     def step(self, n_steps: int, record: bool = False):
@@ -302,9 +350,20 @@ class Run:
 
     def eval_at(self, h, t):
         """(g, U, S) of step t (beta(t), lambda(t)) at fields h, without
-        touching the run's own state."""
+        touching the run's own state.  With manipulated gradients U and S are
+        None."""
         p = self.p
         b = beta(p.sched, p.beta_min, p.beta_max, p.T, t)
+        if p.manip:
+            if self.kind == KIND_MAXCUT:
+                u, v, w = self._keep
+                return maxcut_grad_manip(self.n, u, v, w, h, b, p.gamma), None, None
+            if self.kind == KIND_BMINCUT:
+                u, v, w = self._keep
+                return bmincut_grad_manip(self.n, u, v, w, self.q, lam(p.lam_ramp, p.lam, p.T, t), h, b,
+                                          p.gamma), None, None
+            off, lits = self._keep
+            return maxsat_grad_manip(self.n, off, lits, h, b, p.gamma), None, None
         if self.kind == KIND_MAXCUT:
             u, v, w = self._keep
             return maxcut_grad(self.n, u, v, w, h, b)

@@ -324,6 +324,141 @@ int orc_maxsat_grad(int32_t n, int64_t M, const int64_t* off, const int32_t* lit
 }
 
 /* ------------------------------------------------------------------------- */
+/* Manipulated gradients (supplementary "The explicit gradient formulations" */
+/* and "The explicit gradients and manipulated gradients for the             */
+/* benchmarking problems").  The gradient with respect to P is replaced by a */
+/* modified one, ghat, which is not the derivative of any free energy, and   */
+/* the softmax chain rule gives                                              */
+/*   g^h_i(s) = gamma [ghat_i(s) - sum_s' P_i(s') ghat_i(s')] P_i(s).        */
+/* The neighbours enter only through one-hot vectors e_j of their current    */
+/* read-out (the discretisation), with per-node normalisation factors.       */
+/* One-hot read-out: the state of largest field, ties to the lowest state;   */
+/* for one logit, state (+) iff h > 0.  A node without incident weight gets  */
+/* normalisation factor 0 (its sums are empty).                              */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * MaxCut, states (+) and (-), P_i(+) = sigmoid(h_i):
+ *   ghat_i(s) = c_i sum_j W_ij e_j(s) + (ln P_i(s) + 1) / beta,
+ *   c_i = 1 / sum_j |W_ij|,
+ *   g^h_i = g^h_i(+) of the chain rule above with q = 2.
+ */
+int orc_maxcut_grad_manip(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
+                          const double* w, int32_t R, const double* h, double beta,
+                          double gamma, double* g)
+{
+    double* L1 = (double*)calloc((size_t)n, sizeof(double));     /* sum_j |W_ij| */
+    double* Eplus = (double*)malloc(sizeof(double) * (size_t)n); /* sum_j W_ij e_j(+) */
+    double* Eminus = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!L1 || !Eplus || !Eminus) { free(L1); free(Eplus); free(Eminus); return -2; }
+    for (int64_t e = 0; e < ne; ++e) {
+        L1[eu[e]] += fabs(w[e]);
+        L1[ev[e]] += fabs(w[e]);
+    }
+    for (int32_t r = 0; r < R; ++r) {
+        for (int32_t i = 0; i < n; ++i) Eplus[i] = Eminus[i] = 0.0;
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t i = eu[e], j = ev[e];
+            /* one-hot read-out of each endpoint: (+) iff its field is positive */
+            int plus_j = h[(size_t)j * R + r] > 0.0, plus_i = h[(size_t)i * R + r] > 0.0;
+            if (plus_j) Eplus[i] += w[e]; else Eminus[i] += w[e];
+            if (plus_i) Eplus[j] += w[e]; else Eminus[j] += w[e];
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            double x = h[(size_t)i * R + r];
+            double c = L1[i] > 0.0 ? 1.0 / L1[i] : 0.0;
+            double lp = log_sigmoid(x), lm = log_sigmoid(-x);
+            double pp = exp(lp), pm = exp(lm);
+            double gh_plus = c * Eplus[i] + (lp + 1.0) / beta;
+            double gh_minus = c * Eminus[i] + (lm + 1.0) / beta;
+            double avg = pp * gh_plus + pm * gh_minus;
+            g[(size_t)i * R + r] = gamma * (gh_plus - avg) * pp;
+        }
+    }
+    free(L1); free(Eplus); free(Eminus);
+    return 0;
+}
+
+/*
+ * bMinCut, q states, P_i = softmax h_i, weights W_ij > 0, lam = lambda(t):
+ *   ghat_i(s) = -c^f_i sum_j W_ij e_j(s) + lam c^a_i [sum_j e_j(s) - e_i(s)]
+ *               + (ln P_i(s) + 1) / beta,
+ *   c^f_i = q / sum_j W_ij,  c^a_i = q / sqrt(sum_j W_ij),
+ * where sum_j e_j(s) runs over all nodes (the size of group s in the
+ * current read-out).
+ */
+int orc_bmincut_grad_manip(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
+                           const double* w, int32_t q, double lam, int32_t R,
+                           const double* h, double beta, double gamma, double* g)
+{
+    size_t nq = (size_t)n * (size_t)q;
+    double* D = (double*)calloc((size_t)n, sizeof(double));      /* sum_j W_ij */
+    int32_t* e1 = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);  /* one-hot as a state index */
+    double* F = (double*)malloc(sizeof(double) * nq);            /* sum_j W_ij e_j(s) */
+    double* cnt = (double*)malloc(sizeof(double) * (size_t)q);   /* sum_j e_j(s) */
+    double* lnP = (double*)malloc(sizeof(double) * (size_t)q);
+    double* gh = (double*)malloc(sizeof(double) * (size_t)q);
+    if (!D || !e1 || !F || !cnt || !lnP || !gh) {
+        free(D); free(e1); free(F); free(cnt); free(lnP); free(gh);
+        return -2;
+    }
+    for (int64_t e = 0; e < ne; ++e) {
+        D[eu[e]] += w[e];
+        D[ev[e]] += w[e];
+    }
+    for (int32_t r = 0; r < R; ++r) {
+        for (int32_t s = 0; s < q; ++s) cnt[s] = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            const double* hi = h + ((size_t)i * R + r) * q;
+            int32_t best = 0;
+            for (int32_t s = 1; s < q; ++s) if (hi[s] > hi[best]) best = s;
+            e1[i] = best;
+            cnt[best] += 1.0;
+        }
+        for (size_t k = 0; k < nq; ++k) F[k] = 0.0;
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t i = eu[e], j = ev[e];
+            F[(size_t)i * q + e1[j]] += w[e];
+            F[(size_t)j * q + e1[i]] += w[e];
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            const double* hi = h + ((size_t)i * R + r) * q;
+            double mx = hi[0];
+            for (int32_t s = 1; s < q; ++s) if (hi[s] > mx) mx = hi[s];
+            double Z = 0.0;
+            for (int32_t s = 0; s < q; ++s) Z += exp(hi[s] - mx);
+            double lz = log(Z);
+            for (int32_t s = 0; s < q; ++s) lnP[s] = hi[s] - mx - lz;
+            double cf = D[i] > 0.0 ? (double)q / D[i] : 0.0;
+            double ca = D[i] > 0.0 ? (double)q / sqrt(D[i]) : 0.0;
+            double avg = 0.0;
+            for (int32_t s = 0; s < q; ++s) {
+                double own = (e1[i] == s) ? 1.0 : 0.0;
+                gh[s] = -cf * F[(size_t)i * q + s] + lam * ca * (cnt[s] - own) + (lnP[s] + 1.0) / beta;
+                avg += exp(lnP[s]) * gh[s];
+            }
+            for (int32_t s = 0; s < q; ++s)
+                g[((size_t)i * R + r) * q + s] = gamma * (gh[s] - avg) * exp(lnP[s]);
+        }
+    }
+    free(D); free(e1); free(F); free(cnt); free(lnP); free(gh);
+    return 0;
+}
+
+/*
+ * Max-k-SAT: the paper leaves the gradient unmodified (ghat = g^p), so the
+ * manipulated form is gamma times the explicit gradient.
+ */
+int orc_maxsat_grad_manip(int32_t n, int64_t M, const int64_t* off, const int32_t* lits,
+                          int32_t R, const double* h, double beta, double gamma, double* g)
+{
+    int rc = orc_maxsat_grad(n, M, off, lits, R, h, beta, g, NULL, NULL);
+    if (rc) return rc;
+    for (size_t k = 0; k < (size_t)n * (size_t)R; ++k) g[k] *= gamma;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Adam (Kingma & Ba), PyTorch semantics: n_step counts from 1.              */
 /* ------------------------------------------------------------------------- */
 void orc_adam(int64_t count, const double* g_in, double* h, double* m1, double* m2,
@@ -460,6 +595,8 @@ typedef struct {
     double beta_min, beta_max, lam, lr, b1, b2, eps, wd;
     int32_t opt;            /* 0 Adam, 1 RMSprop, 2 SGD */
     double momentum, rms_alpha, dampening;
+    int32_t manip;          /* 1: manipulated gradients (no energies) */
+    double gamma;           /* gamma_grad of the manipulated form */
 } orc_problem;
 
 int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, double* m1,
@@ -475,7 +612,15 @@ int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, doubl
         double* U = U_hist ? U_hist + (size_t)k * pb->R : NULL;
         double* S = S_hist ? S_hist + (size_t)k * pb->R : NULL;
         int rc;
-        if (pb->kind == 0)
+        if (pb->manip && pb->kind == 0)
+            rc = orc_maxcut_grad_manip(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->R, h, beta, pb->gamma, g);
+        else if (pb->manip && pb->kind == 1)
+            rc = orc_bmincut_grad_manip(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->q,
+                                        orc_lambda(pb->lam_ramp, pb->lam, pb->T, t), pb->R, h, beta,
+                                        pb->gamma, g);
+        else if (pb->manip)
+            rc = orc_maxsat_grad_manip(pb->n, pb->ne, pb->off, pb->lits, pb->R, h, beta, pb->gamma, g);
+        else if (pb->kind == 0)
             rc = orc_maxcut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->R, h, beta, g, U, S);
         else if (pb->kind == 1)
             rc = orc_bmincut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->q,
