@@ -11,10 +11,22 @@ and per-replica energies U, S, F; the read-out runs at the end of the anneal.
 Metric: replica-edge updates per second = nnz * R * steps / seconds, with
 nnz = 2 x edges, timed over one captured HIP graph of all K steps with the
 inputs resident in HBM.  Prints one JSON line.
+
+--gradient manipulated runs the same workload with the paper's manipulated
+gradients (one-hot neighbour read-outs, 1/sum|W| normalisation): the gather
+then reads sign bits, and no energies are formed.
+
+roofline.traffic is the HBM traffic of one step-kernel launch measured with
+the FETCH_SIZE and WRITE_SIZE counters (scaled by a plain copy of known
+size), read from the committed counter summary of this workload; it is null
+when the kernel sources, launch shape or marginal type differ from the ones
+the counters were taken with.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,6 +50,44 @@ def step_kernel_bytes(n, R, nnz, mbytes, n_tiles, NE=2):
     csr = 8 * (n + 1) + 8 * nnz
     parts = 8 * NE * R * n_tiles
     return state + csr + parts
+
+
+def manip_kernel_bytes(n, R, nnz):
+    """Algorithmic bytes of one manipulated-gradient MaxCut launch: h, m1, m2
+    read and written, the sign bits (ceil(R/32) words per row) read once and
+    written once, the CSR and the per-node normaliser (8 B)."""
+    rw = (R + 31) // 32
+    return n * R * 24 + 2 * 4 * n * rw + 8 * (n + 1) + 8 * nnz + 8 * n
+
+
+KERNEL_SOURCES = {
+    "explicit": ["fem_kernels.hip", "fem_device.h", "fem_internal.h"],
+    "manipulated": ["fem_manip.hip", "fem_device.h", "fem_internal.h"],
+}
+
+
+def kernel_sources_sha(gradient):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[gradient]:
+        with open(os.path.join(ROOT, "paper_2412_09285_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(path, gradient, tile, marginals):
+    """Bytes per launch from a committed counter summary, or None when the
+    summary is missing or was taken with other kernel sources / launch shape."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        m = re.search(r"^counters-json: (\{.*\})\s*$", f.read(), re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha(gradient) or list(rec.get("tile", [])) != list(tile) \
+            or rec.get("marginals") != marginals:
+        return None
+    return int(rec["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(graph, R_sample, steps_sample):
@@ -65,6 +115,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000, help="timed steps K (one anneal of K steps)")
     ap.add_argument("--warmup", type=int, default=50, help="untimed warm-up steps W")
     ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32")
+    ap.add_argument("--gradient", choices=["explicit", "manipulated"], default="explicit")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--cpu-replicas", type=int, default=8)
@@ -128,13 +179,14 @@ def main():
     prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w, device=0)
     stream = torch.cuda.Stream()
     T = max(K, Wm, 1)
-    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, marginal_dtype=dtype, energy_every=1),
-                   stream=stream)
+    manip = args.gradient == "manipulated"
+    extra = dict(gradient=fem.GRAD_MANIPULATED, energy_every=0) if manip else dict(energy_every=1)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, marginal_dtype=dtype, **extra), stream=stream)
     s.set_fields(h0)
     tile = s.tile()
     if not args.no_tune:
         tile = s.tune(trial_steps=10, use_cache=True)
-    log(f"launch shape (vec, waves, rows) = {tile}")
+    log(f"launch shape (vec, waves, rows, nt, lanes) = {tile}")
     # warm-up: W eager steps, then capture the K-step graph
     s.set_fields(h0)
     s.step(min(Wm, T))
@@ -149,7 +201,7 @@ def main():
     s.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    U, S, F = s.energies()
+    U = s.energies()[0] if not manip else None
     rep, val, _ = s.best()
     mean_cut = float(np.mean(prob.eval_int(s.round())[0]))
     updates = g.nnz * R * K
@@ -165,16 +217,21 @@ def main():
     s.step(n_prof)
     kern_ms, n_k = s.profile_result()
     s.profile(False)
-    vec, waves, rows = tile[:3]
-    lanes = min(64, 1 << (max(1, -(-R // vec)) - 1).bit_length())
+    vec, waves, rows, nt, lanes = tile
     n_tiles = -(-g.n // (waves * (64 // lanes) * rows))
     mbytes = 2 if dtype == fem.BF16 else 4
-    alg_bytes = step_kernel_bytes(g.n, R, g.nnz, mbytes, n_tiles)
+    if manip:
+        alg_bytes = manip_kernel_bytes(g.n, R, g.nnz)
+        kname, counters = "maxcut_manip_kernel", "maxcut_manip_n1e5_R256_hbm_counters.md"
+    else:
+        alg_bytes = step_kernel_bytes(g.n, R, g.nnz, mbytes, n_tiles)
+        kname, counters = "maxcut_step_kernel", f"maxcut_n1e5_R256_{args.dtype}_hbm_counters.md"
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    traffic = measured_traffic(os.path.join(ROOT, "profiles", counters), args.gradient, tile, args.dtype)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "maxcut_step_kernel", "kernel_avg_ms": round(kern_ms, 5), "kernel_launches": n_k,
-            "alg_bytes_per_launch": int(alg_bytes)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kname, "kernel_avg_ms": round(kern_ms, 5), "kernel_launches": n_k,
+            "alg_bytes_per_launch": int(alg_bytes), "kernel_sources_sha256": kernel_sources_sha(args.gradient)}
     out = {
         "metric": "replica-edge updates/s (nnz*R*steps/s)",
         "value": value,
@@ -186,13 +243,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if dtype == fem.F32 else "f32+bf16-marginals",
+        "dtype": ("f32+sign-bit-readouts" if manip else "f32" if dtype == fem.F32 else "f32+bf16-marginals"),
         "data": "synthetic (seeded generator: random sparse graph, uniform endpoints, +/-1 weights)",
         "config": {"workload": "maxcut_sparse_n100000_e300000_pm1", "n": g.n, "edges": g.n_edges,
                    "nnz": g.nnz, "replicas": R, "anneal_steps": K, "marginals": args.dtype,
+                   "gradient": args.gradient,
                    "schedule": "linear beta 0.01->5, Adam lr 0.1", "tile": list(tile),
                    "parallelism": "single GPU"},
-        "result": {"best_cut": int(val[0]), "mean_cut": mean_cut, "U_mean_final": float(np.mean(U))},
+        "result": {"best_cut": int(val[0]), "mean_cut": mean_cut,
+                   "U_mean_final": float(np.mean(U)) if U is not None else None},
         "roofline": roof,
     }
     if not args.no_cpu:

@@ -133,7 +133,28 @@ typedef struct {
     double momentum;           /* RMSprop / SGD momentum */
     double rms_alpha;          /* RMSprop smoothing constant */
     double dampening;          /* SGD dampening */
+    int32_t gradient;          /* FEM_GRAD_EXPLICIT | FEM_GRAD_MANIPULATED */
+    double gamma_grad;         /* gamma_grad of the manipulated gradients */
 } fem_params;
+
+/* Gradient with respect to the fields (supplementary "The explicit gradient
+ * formulations" and "The explicit gradients and manipulated gradients for the
+ * benchmarking problems"):
+ *  FEM_GRAD_EXPLICIT: the exact gradient of the mean-field free energy.
+ *  FEM_GRAD_MANIPULATED: the paper's modified gradient, gamma_grad times the
+ *    softmax chain rule applied to
+ *      MaxCut:  c_i sum_j W_ij e_j(s) + (ln P_i(s) + 1)/beta, c_i = 1/sum_j|W_ij|;
+ *      bMinCut: -c^f_i sum_j W_ij e_j(s) + lambda c^a_i [sum_j e_j(s) - e_i(s)]
+ *               + (ln P_i(s) + 1)/beta, c^f_i = q/sum_j W_ij,
+ *               c^a_i = q/sqrt(sum_j W_ij);
+ *      Max-k-SAT: the explicit gradient (left unmodified by the paper);
+ *    e_j is the one-hot read-out of node j (fem_round's rule) and a node
+ *    without incident weight gets c = 0.  The marginal copy becomes that
+ *    read-out (1 bit per replica for MaxCut, 1 byte for bMinCut), so
+ *    marginal_dtype is ignored for those kinds.  Not the gradient of F: the
+ *    per-replica energies are not formed, and energy_every must be 0
+ *    (else FEM_E_UNSUPPORTED). */
+enum { FEM_GRAD_EXPLICIT = 0, FEM_GRAD_MANIPULATED = 1 };
 
 /* Optimisers, torch.optim semantics (the paper uses PyTorch's Adam, RMSprop
  * and SGD; Methods, "Hyperparameter tuning").  The Adam moments m1, m2 hold
@@ -142,7 +163,8 @@ enum { FEM_OPT_ADAM = 0, FEM_OPT_RMSPROP = 1, FEM_OPT_SGD = 2 };
 
 /* Adam 0.9 / 0.999 / 1e-8, lr 0.1, no weight decay, linear beta 0.01 -> 5,
  * R = 16, T = 500, F32 marginals, energies every step, no recording;
- * RMSprop alpha 0.99, no momentum or dampening. */
+ * RMSprop alpha 0.99, no momentum or dampening; explicit gradients,
+ * gamma_grad 1. */
 void fem_params_default(fem_params* p);
 
 /* hip_stream: a hipStream_t on the problem's device (NULL = the null stream).
@@ -221,10 +243,16 @@ fem_status fem_set_state(fem_solver* s, const void* buf, size_t bytes);
 /* Launch shape of the step kernels.  vec: values per lane along the replica
  * axis (1, 2, 4, 8; Potts uses q); waves: wavefronts per workgroup (1..16,
  * fewer for register-heavy kernels); rows: rows per team per tile (1..64);
- * nt: 1 = non-temporal loads and stores of h and the Adam moments.  All shapes
- * give bit-identical fields. */
+ * nt: 1 = non-temporal loads and stores of h and the Adam moments; lanes: cap
+ * on the lanes of a team (0 = 64, else a power of two <= 64).  A team of L
+ * lanes covers L*vec replicas of a row; where that is fewer than R the
+ * replicas are split into segments and consecutive workgroups take different
+ * segments of the same rows, so that each XCD (workgroups are dealt to the
+ * eight XCDs round-robin) gathers from its own columns of the marginal copy.
+ * fem_get_tile reports the lanes actually used.  All shapes give
+ * bit-identical fields. */
 typedef struct {
-    int32_t vec, waves, rows, nt;
+    int32_t vec, waves, rows, nt, lanes;
 } fem_tile;
 fem_status fem_get_tile(const fem_solver* s, fem_tile* t);
 fem_status fem_set_tile(fem_solver* s, const fem_tile* t);

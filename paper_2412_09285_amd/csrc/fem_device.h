@@ -1,0 +1,299 @@
+// Device helpers shared by the step kernels (fem_kernels.hip, fem_manip.hip):
+// bfloat16 conversion, vector loads and stores of the state and the marginal
+// copy, the optimiser update, fixed-point column sums, the Max-k-SAT marginal
+// encoding, and the team / workgroup reductions.
+#pragma once
+
+#include "fem_internal.h"
+
+namespace fem {
+
+// ---------------------------------------------------------------- helpers --
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+// round-to-nearest-even float -> bfloat16 (NaN kept quiet)
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// V consecutive float32 values
+template <int V>
+__device__ __forceinline__ void ld_f32(const float* __restrict__ p, float (&x)[V])
+{
+    if constexpr (V == 1) {
+        x[0] = p[0];
+    } else if constexpr (V == 2) {
+        f32x2 t = *reinterpret_cast<const f32x2*>(p);
+        x[0] = t.x; x[1] = t.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k) {
+            f32x4 t = reinterpret_cast<const f32x4*>(p)[k];
+            x[4 * k] = t.x; x[4 * k + 1] = t.y; x[4 * k + 2] = t.z; x[4 * k + 3] = t.w;
+        }
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void st_f32(float* __restrict__ p, const float (&x)[V])
+{
+    if constexpr (V == 1) {
+        p[0] = x[0];
+    } else if constexpr (V == 2) {
+        f32x2 t; t.x = x[0]; t.y = x[1];
+        *reinterpret_cast<f32x2*>(p) = t;
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k) {
+            f32x4 t; t.x = x[4 * k]; t.y = x[4 * k + 1]; t.z = x[4 * k + 2]; t.w = x[4 * k + 3];
+            reinterpret_cast<f32x4*>(p)[k] = t;
+        }
+    }
+}
+
+// V consecutive bfloat16 values, widened
+template <int V>
+__device__ __forceinline__ void ld_bf16(const uint16_t* __restrict__ p, float (&x)[V])
+{
+    if constexpr (V == 1) {
+        x[0] = bf16_to_f32(p[0]);
+    } else if constexpr (V == 2) {
+        uint32_t t = *reinterpret_cast<const uint32_t*>(p);
+        x[0] = __uint_as_float(t << 16); x[1] = __uint_as_float(t & 0xffff0000u);
+    } else if constexpr (V == 4) {
+        u32x2 t = *reinterpret_cast<const u32x2*>(p);
+        x[0] = __uint_as_float(t.x << 16); x[1] = __uint_as_float(t.x & 0xffff0000u);
+        x[2] = __uint_as_float(t.y << 16); x[3] = __uint_as_float(t.y & 0xffff0000u);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 8; ++k) {
+            u32x4 t = reinterpret_cast<const u32x4*>(p)[k];
+            x[8 * k + 0] = __uint_as_float(t.x << 16); x[8 * k + 1] = __uint_as_float(t.x & 0xffff0000u);
+            x[8 * k + 2] = __uint_as_float(t.y << 16); x[8 * k + 3] = __uint_as_float(t.y & 0xffff0000u);
+            x[8 * k + 4] = __uint_as_float(t.z << 16); x[8 * k + 5] = __uint_as_float(t.z & 0xffff0000u);
+            x[8 * k + 6] = __uint_as_float(t.w << 16); x[8 * k + 7] = __uint_as_float(t.w & 0xffff0000u);
+        }
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void st_bf16(uint16_t* __restrict__ p, const float (&x)[V])
+{
+    if constexpr (V == 1) {
+        p[0] = f32_to_bf16(x[0]);
+    } else if constexpr (V == 2) {
+        *reinterpret_cast<uint32_t*>(p) = (uint32_t)f32_to_bf16(x[0]) | ((uint32_t)f32_to_bf16(x[1]) << 16);
+    } else if constexpr (V == 4) {
+        u32x2 t;
+        t.x = (uint32_t)f32_to_bf16(x[0]) | ((uint32_t)f32_to_bf16(x[1]) << 16);
+        t.y = (uint32_t)f32_to_bf16(x[2]) | ((uint32_t)f32_to_bf16(x[3]) << 16);
+        *reinterpret_cast<u32x2*>(p) = t;
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 8; ++k) {
+            u32x4 t;
+            t.x = (uint32_t)f32_to_bf16(x[8 * k + 0]) | ((uint32_t)f32_to_bf16(x[8 * k + 1]) << 16);
+            t.y = (uint32_t)f32_to_bf16(x[8 * k + 2]) | ((uint32_t)f32_to_bf16(x[8 * k + 3]) << 16);
+            t.z = (uint32_t)f32_to_bf16(x[8 * k + 4]) | ((uint32_t)f32_to_bf16(x[8 * k + 5]) << 16);
+            t.w = (uint32_t)f32_to_bf16(x[8 * k + 6]) | ((uint32_t)f32_to_bf16(x[8 * k + 7]) << 16);
+            reinterpret_cast<u32x4*>(p)[k] = t;
+        }
+    }
+}
+
+template <typename MT, int V>
+__device__ __forceinline__ void ld_marg(const MT* p, float (&x)[V])
+{
+    if constexpr (sizeof(MT) == 4) ld_f32<V>(reinterpret_cast<const float*>(p), x);
+    else ld_bf16<V>(reinterpret_cast<const uint16_t*>(p), x);
+}
+
+template <typename MT, int V>
+__device__ __forceinline__ void st_marg(MT* p, const float (&x)[V])
+{
+    if constexpr (sizeof(MT) == 4) st_f32<V>(reinterpret_cast<float*>(p), x);
+    else st_bf16<V>(reinterpret_cast<uint16_t*>(p), x);
+}
+
+// h, m1, m2 are read once and written once per step: with NT the accesses
+// are non-temporal, so they do not evict the gathered marginal copy from L2
+// and the Infinity Cache.
+template <int V, bool NT>
+__device__ __forceinline__ void ld_state(const float* __restrict__ p, float (&x)[V])
+{
+    if constexpr (!NT || V < 4) {
+        if constexpr (NT && V == 1) x[0] = __builtin_nontemporal_load(p);
+        else if constexpr (NT && V == 2) {
+            f32x2 t = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+            x[0] = t.x; x[1] = t.y;
+        } else ld_f32<V>(p, x);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k) {
+            f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p) + k);
+            x[4 * k] = t.x; x[4 * k + 1] = t.y; x[4 * k + 2] = t.z; x[4 * k + 3] = t.w;
+        }
+    }
+}
+
+template <int V, bool NT>
+__device__ __forceinline__ void st_state(float* __restrict__ p, const float (&x)[V])
+{
+    if constexpr (!NT || V < 4) {
+        if constexpr (NT && V == 1) __builtin_nontemporal_store(x[0], p);
+        else if constexpr (NT && V == 2) {
+            f32x2 t; t.x = x[0]; t.y = x[1];
+            __builtin_nontemporal_store(t, reinterpret_cast<f32x2*>(p));
+        } else st_f32<V>(p, x);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k) {
+            f32x4 t; t.x = x[4 * k]; t.y = x[4 * k + 1]; t.z = x[4 * k + 2]; t.w = x[4 * k + 3];
+            __builtin_nontemporal_store(t, reinterpret_cast<f32x4*>(p) + k);
+        }
+    }
+}
+
+// The optimiser step, torch.optim semantics (a uniform branch):
+//  Adam:    g += wd h; m1 = b1 m1 + (1-b1) g; m2 = b2 m2 + (1-b2) g^2;
+//           h -= step_size * m1 / (sqrt(m2)/sqrt(1-b2^n) + eps)
+//  RMSprop: g += wd h; m2 = a m2 + (1-a) g^2; d = sqrt(m2) + eps;
+//           momentum > 0: m1 = mu m1 + g/d, h -= lr m1;  else h -= lr g/d
+//  SGD:     g += wd h; momentum != 0: m1 = g (first step) or mu m1 + (1-damp) g,
+//           g = m1;  h -= lr g
+__device__ __forceinline__ float adam_update(float x, float g, float& m1, float& m2, const StepScalars& s)
+{
+    g = g + s.wd * x;
+    if (s.opt == 0) {
+        m1 = s.b1 * m1 + s.one_m_b1 * g;
+        m2 = s.b2 * m2 + s.one_m_b2 * (g * g);
+        float denom = sqrtf(m2) / s.bc2_sqrt + s.eps;
+        return x - s.step_size * (m1 / denom);
+    }
+    if (s.opt == 1) {
+        m2 = s.rms_alpha * m2 + s.one_m_rms * (g * g);
+        const float d = sqrtf(m2) + s.eps;
+        if (s.mom > 0.0f) {
+            m1 = s.mom * m1 + g / d;
+            return x - s.lr * m1;
+        }
+        return x - s.lr * (g / d);
+    }
+    if (s.mom != 0.0f) {
+        m1 = s.first ? g : s.mom * m1 + (1.0f - s.damp) * g;
+        g = m1;
+    }
+    return x - s.lr * g;
+}
+
+// 2^-40 fixed point of a probability in [0, 1]
+__device__ __forceinline__ long long to_fixed(double p) { return (long long)rint(p * 1099511627776.0); }
+
+// Column-sum contributions of one replica's softmax, formed in double: the sum
+// over all nodes of float32 marginals would carry their rounding into the
+// global balance term.
+template <int Q>
+__device__ __forceinline__ void colsum_add(const float (&h)[Q], long long (&cs)[Q])
+{
+    float mx = h[0];
+#pragma unroll
+    for (int s = 1; s < Q; ++s) mx = fmaxf(mx, h[s]);
+    double e[Q], Z = 0.0;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+        e[s] = exp((double)h[s] - (double)mx);
+        Z += e[s];
+    }
+    const double iz = 1.0 / Z;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) cs[s] += to_fixed(e[s] * iz);
+}
+
+// Max-k-SAT stored marginal: the smaller of P(x=1) and P(x=0), negative (sign
+// bit set) when P(x=1) > 1/2.  Both tails keep full relative precision.
+__device__ __forceinline__ float sat_encode(float h)
+{
+    float e = expf(-fabsf(h));
+    float small = e / (1.0f + e);
+    return h > 0.0f ? -small : small;
+}
+// probability that a literal of polarity pos is false, from the stored value
+__device__ __forceinline__ float sat_u(float s, bool pos)
+{
+    bool hi = signbit(s);
+    float a = fabsf(s);
+    return (pos == hi) ? a : 1.0f - a;
+}
+
+// Butterfly over the teams of one wave (lanes that hold the same replicas),
+// then a fixed-order sum over the waves of the workgroup.  vals[k] are per-lane
+// values, K per lane.  Results land in out[k * L * Vl + lane * Vl + v]-style
+// layout chosen by the caller through 'store'.
+template <typename T, int K>
+__device__ __forceinline__ void team_butterfly(T (&v)[K], int lanes_log2)
+{
+    for (int off = 1 << lanes_log2; off < 64; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    }
+}
+
+// ------------------------------------------------------- geometry helpers --
+// Block -> (tile, replica segment).  Tile-major grids are (n_tiles, nseg);
+// segment-major grids are (nseg, n_tiles), so that consecutive workgroups,
+// which the dispatcher deals round-robin to the eight XCDs, take different
+// replica segments of the same rows and each XCD's L2 serves the gathers of
+// one segment's columns.
+__device__ __forceinline__ int blk_tile(int seg_major) { return seg_major ? blockIdx.y : blockIdx.x; }
+__device__ __forceinline__ int blk_seg(int seg_major) { return seg_major ? blockIdx.x : blockIdx.y; }
+
+struct TeamIdx {
+    int lane, wave, nwaves, L, tl, team, teams;
+};
+__device__ __forceinline__ TeamIdx team_idx(int lanes_log2)
+{
+    TeamIdx t;
+    t.lane = threadIdx.x & 63;
+    t.wave = threadIdx.x >> 6;
+    t.nwaves = blockDim.x >> 6;
+    t.L = 1 << lanes_log2;
+    t.tl = t.lane & (t.L - 1);
+    t.team = t.wave * (64 >> lanes_log2) + (t.lane >> lanes_log2);
+    t.teams = t.nwaves * (64 >> lanes_log2);
+    return t;
+}
+
+// Sum K per-lane values over the workgroup's teams in a fixed order (butterfly
+// within the wave, then waves in order) and hand each total to store(k, l, s),
+// where l is the lane-in-team index.  lds must hold nwaves * L * K values.
+template <typename T, int K, typename Store>
+__device__ __forceinline__ void block_reduce_store(T (&v)[K], const TeamIdx& ti, int lanes_log2, T* lds,
+                                                   Store store)
+{
+    team_butterfly<T, K>(v, lanes_log2);
+    if (ti.lane < ti.L) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[(ti.wave * K + k) * ti.L + ti.lane] = v[k];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ti.L * K; t += blockDim.x) {
+        const int k = t / ti.L, l = t % ti.L;
+        T s = lds[k * ti.L + l];
+        for (int w = 1; w < ti.nwaves; ++w) s += lds[(w * K + k) * ti.L + l];
+        store(k, l, s);
+    }
+    __syncthreads();
+}
+
+static inline size_t lds_bytes(int waves, int L, int K) { return (size_t)waves * L * K * 8; }
+
+}  // namespace fem

@@ -95,6 +95,7 @@ static void free_problem_device(Problem& p)
     dfree(p.inc2);
     dfree(p.inc4);
     dfree(p.wdeg);
+    dfree(p.nrm);
 }
 
 static fem_status upload_problem(Problem& p)
@@ -117,6 +118,10 @@ static fem_status upload_problem(Problem& p)
     if (!p.h_wdeg.empty()) {
         HIPCHK(dalloc(&p.wdeg, p.h_wdeg.size()));
         HIPCHK(hipMemcpy(p.wdeg, p.h_wdeg.data(), p.h_wdeg.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    if (!p.h_nrm.empty()) {
+        HIPCHK(dalloc(&p.nrm, p.h_nrm.size()));
+        HIPCHK(hipMemcpy(p.nrm, p.h_nrm.data(), p.h_nrm.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     return FEM_OK;
 }
@@ -197,6 +202,13 @@ static fem_status build_graph(int kind, int device, int32_t n, int64_t n_edges, 
     for (int32_t i = 0; i < n; ++i)
         std::sort(p.h_adj.begin() + ro[(size_t)i], p.h_adj.begin() + ro[(size_t)i + 1],
                   [](const int2& a, const int2& b) { return a.x < b.x; });
+    p.h_nrm.assign((size_t)n, 0.0);
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t k = ro[(size_t)i]; k < ro[(size_t)i + 1]; ++k) {
+            float we;
+            std::memcpy(&we, &p.h_adj[(size_t)k].y, 4);
+            p.h_nrm[(size_t)i] += std::fabs((double)we);
+        }
     if (kind == KIND_BMINCUT) {
         p.h_wdeg.assign((size_t)n, 0.0f);
         for (int32_t i = 0; i < n; ++i) {
@@ -330,6 +342,8 @@ struct fem_solver {
     size_t vals = 0;
     int32_t t = 0;
     bool fields_set = false;
+    bool manip = false;   // manipulated gradients on a graph kind: read-out marginal copy
+    int32_t rw = 0;       // MaxCut manipulated: 32-bit words per row of sign bits
     // state
     float* h = nullptr;
     float* m1 = nullptr;
@@ -389,11 +403,11 @@ static int pow2ceil(int x)
     return p;
 }
 
-static LaunchGeom make_geom(int per_lane, int R, int waves)
+static LaunchGeom make_geom(int per_lane, int R, int waves, int max_lanes = 64)
 {
     LaunchGeom g{};
     const int need = (R + per_lane - 1) / per_lane;
-    g.lanes = std::min(64, pow2ceil(need));
+    g.lanes = std::min(max_lanes > 0 ? max_lanes : 64, pow2ceil(need));
     g.nseg = (need + g.lanes - 1) / g.lanes;
     g.teams_per_block = waves * (64 / g.lanes);
     return g;
@@ -402,17 +416,37 @@ static LaunchGeom make_geom(int per_lane, int R, int waves)
 // workgroup LDS used by the reductions: waves * lanes * values-per-lane * 8 B
 static const size_t LDS_LIMIT = 64 * 1024;
 
+// Tiles of tile_rows rows cut per instance.
+static size_t count_tiles(const fem_solver* s, int tile_rows)
+{
+    const Problem& p = *s->prob;
+    size_t n = 0;
+    for (int b = 0; b < s->n_inst; ++b) {
+        const size_t rows = (size_t)(p.inst_off[(size_t)b + 1] - p.inst_off[(size_t)b]);
+        n += (rows + tile_rows - 1) / tile_rows;
+    }
+    return n;
+}
+
+// grid.y of a HIP launch is limited to 65535 blocks
+static const size_t GRID_Y_MAX = 65535;
+
 static bool valid_shape(const fem_solver* s, const TileShape& t)
 {
     if (t.waves < 1 || t.waves > 16 || t.rows < 1 || t.rows > 64) return false;
+    if (t.lanes < 0 || t.lanes > 64 || (t.lanes & (t.lanes - 1)) != 0) return false;
     const int per_lane = (s->kind == KIND_BMINCUT) ? 1 : t.vec;
     if (s->kind != KIND_BMINCUT) {
         if (t.vec != 1 && t.vec != 2 && t.vec != 4 && t.vec != 8) return false;
         if (s->R % t.vec != 0) return false;
     }
     if (64 * t.waves > step_max_threads(s->kind, s->kind == KIND_BMINCUT ? s->q : t.vec)) return false;
-    const LaunchGeom g = make_geom(per_lane, s->R, t.waves);
+    const LaunchGeom g = make_geom(per_lane, s->R, t.waves, t.lanes);
     const LaunchGeom ge = make_geom(1, s->R, t.waves);
+    if ((size_t)g.nseg > GRID_Y_MAX || (size_t)ge.nseg > GRID_Y_MAX) return false;
+    // manipulated MaxCut: a 32-bit word of sign bits must not span segments
+    if (s->manip && s->kind == KIND_MAXCUT && g.nseg > 1 && g.lanes * t.vec < 32) return false;
+    if (count_tiles(s, g.teams_per_block * t.rows) > (size_t)INT32_MAX) return false;
     const int k_step = (s->kind == KIND_BMINCUT) ? std::max(s->q, 3) : 2 * t.vec;
     const int k_eval = (s->kind == KIND_BMINCUT) ? s->q : 1;
     if ((size_t)t.waves * g.lanes * k_step * 8 > LDS_LIMIT) return false;
@@ -442,9 +476,11 @@ static void drop_graphs(fem_solver* s)
 }
 
 // Tiles of tile_rows rows per instance; chunks of <= 64 consecutive tiles of
-// one instance (first reduction stage).  Dispatch order interleaves the tile
-// list so that the tiles a given XCD receives (block b goes to XCD b mod 8)
-// form one contiguous row range.
+// one instance (first reduction stage).  Block b goes to XCD b mod 8.  With
+// one replica segment the dispatch order interleaves the tile list so that the
+// tiles an XCD receives form one contiguous row range; with several segments
+// the grid is segment-major (consecutive blocks = segments of one tile; while
+// the tile count fits grid.y) and the tiles keep their natural order.
 static fem_status setup_tiling(fem_solver* s, const TileShape& shape)
 {
     const Problem& p = *s->prob;
@@ -452,7 +488,9 @@ static fem_status setup_tiling(fem_solver* s, const TileShape& shape)
     drop_graphs(s);
     s->shape = shape;
     const int per_lane = (s->kind == KIND_BMINCUT) ? 1 : shape.vec;
-    s->geo = make_geom(per_lane, s->R, shape.waves);
+    s->geo = make_geom(per_lane, s->R, shape.waves, shape.lanes);
+    s->geo.seg_major =
+        (s->geo.nseg > 1 && count_tiles(s, s->geo.teams_per_block * shape.rows) <= GRID_Y_MAX) ? 1 : 0;
     s->lanes_log2 = 0;
     while ((1 << s->lanes_log2) < s->geo.lanes) ++s->lanes_log2;
     const int tile_rows = s->geo.teams_per_block * shape.rows;
@@ -490,7 +528,8 @@ static fem_status setup_tiling(fem_solver* s, const TileShape& shape)
             start[x] = acc;
             acc += nt / X + (x < nt % X ? 1 : 0);
         }
-        for (size_t pos = 0; pos < nt; ++pos) order[pos] = tiles[start[pos % X] + pos / X];
+        for (size_t pos = 0; pos < nt; ++pos)
+            order[pos] = s->geo.seg_major ? tiles[pos] : tiles[start[pos % X] + pos / X];
     }
     s->geo.n_tiles = s->n_tiles;
     s->egeo = make_geom(1, s->R, shape.waves);
@@ -532,6 +571,7 @@ static StepScalars step_scalars(const fem_solver* s, int t)
     StepScalars sc;
     sc.inv_beta_d = 1.0 / s->beta[(size_t)t];
     sc.lam_d = s->lam[(size_t)t];
+    sc.gamma_d = p.gradient == FEM_GRAD_MANIPULATED ? p.gamma_grad : 1.0;
     sc.inv_beta = (float)sc.inv_beta_d;
     sc.lam = (float)sc.lam_d;
     sc.step_size = (float)(p.lr / (1.0 - std::pow(p.adam_b1, nstep)));
@@ -561,6 +601,7 @@ static StepArgs base_args(const fem_solver* s)
     a.inc2 = p.inc2;
     a.inc4 = p.inc4;
     a.wdeg = p.wdeg;
+    a.nrm = p.nrm;
     a.tiles = s->d_tiles;
     a.h = s->h;
     a.m1 = s->m1;
@@ -568,9 +609,12 @@ static StepArgs base_args(const fem_solver* s)
     a.grad = s->prm.keep_grad ? s->grad : nullptr;
     a.ctil = s->ctil;
     a.cpart = s->cpart;
+    a.n = s->n;
     a.R = s->R;
     a.q = s->q;
+    a.rw = s->rw;
     a.lanes_log2 = s->lanes_log2;
+    a.seg_major = s->geo.seg_major;
     return a;
 }
 
@@ -586,12 +630,14 @@ static double* energy_slot(fem_solver* s, int t)
     return s->eout;
 }
 
-// bMinCut: C(s), C~(s) of the marginal copy currently in cpart
+// bMinCut: C(s), C~(s) of the marginal copy currently in cpart (fixed-point
+// marginal sums, or state counts of the read-out with manipulated gradients)
 static fem_status finish_colsums(fem_solver* s)
 {
     HIPCHK(launch_seg_reduce<long long>(s->cpart, s->R * s->q, s->d_chunk_off, s->n_chunks, s->d_inst_chunk_off,
                                         s->n_inst, s->ctmp, s->cfix, s->stream));
-    HIPCHK(launch_colsum_combine(s->R, s->q, s->n_inst, s->cfix, s->csum, s->ctil, s->stream));
+    HIPCHK(launch_colsum_combine(s->R, s->q, s->n_inst, s->cfix, s->manip ? 1.0 : 0x1p-40, s->csum, s->ctil,
+                                 s->stream));
     return FEM_OK;
 }
 
@@ -639,7 +685,10 @@ static fem_status do_step(fem_solver* s)
         ++s->prof_used;
         HIPCHK(hipEventRecord(e0, s->stream));
     }
-    HIPCHK(launch_step(s->kind, s->dtype, s->shape.vec, s->shape.nt != 0, s->geo, s->shape.waves, a, s->stream));
+    if (s->manip)
+        HIPCHK(launch_manip_step(s->kind, s->shape.vec, s->shape.nt != 0, s->geo, s->shape.waves, a, s->stream));
+    else
+        HIPCHK(launch_step(s->kind, s->dtype, s->shape.vec, s->shape.nt != 0, s->geo, s->shape.waves, a, s->stream));
     if (e1) HIPCHK(hipEventRecord(e1, s->stream));
     if (en) {
         double* slot = energy_slot(s, t);
@@ -659,7 +708,10 @@ static fem_status init_marginals(fem_solver* s)
 {
     StepArgs a = base_args(s);
     a.marg_nxt = s->marg[s->t & 1];
-    HIPCHK(launch_init_marginals(s->kind, s->dtype, s->geo, s->shape.waves, a, s->vals, s->stream));
+    if (s->manip)
+        HIPCHK(launch_manip_init(s->kind, s->geo, s->shape.waves, a, s->stream));
+    else
+        HIPCHK(launch_init_marginals(s->kind, s->dtype, s->geo, s->shape.waves, a, s->vals, s->stream));
     if (s->kind == KIND_BMINCUT) STCHK(finish_colsums(s));
     return FEM_OK;
 }
@@ -741,7 +793,7 @@ const char* fem_status_str(int status)
 }
 
 const char* fem_last_error(void) { return g_err.c_str(); }
-int32_t fem_abi_version(void) { return 1; }
+int32_t fem_abi_version(void) { return 2; }
 
 fem_status fem_maxcut_create(int device, int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v,
                              const float* w, fem_problem** out)
@@ -818,6 +870,7 @@ fem_status fem_batch_create(int32_t nparts, fem_problem* const* parts, fem_probl
             p.n_clauses += pb.n_clauses;
         }
         p.h_wdeg.insert(p.h_wdeg.end(), pb.h_wdeg.begin(), pb.h_wdeg.end());
+        p.h_nrm.insert(p.h_nrm.end(), pb.h_nrm.begin(), pb.h_nrm.end());
         p.integral = p.integral && pb.integral;
         p.n += pb.n;
         p.nnz += pb.nnz;
@@ -888,6 +941,8 @@ void fem_params_default(fem_params* p)
     p->momentum = 0.0;
     p->rms_alpha = 0.99;
     p->dampening = 0.0;
+    p->gradient = FEM_GRAD_EXPLICIT;
+    p->gamma_grad = 1.0;
 }
 
 fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void* hip_stream, fem_solver** out)
@@ -910,6 +965,11 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
         return fail(FEM_E_INVAL, "invalid momentum, rms_alpha or dampening");
     if (P.marginal_dtype != FEM_F32 && P.marginal_dtype != FEM_BF16) return fail(FEM_E_INVAL, "unknown marginal dtype");
     if (P.energy_every < 0 || P.eval_every < 0) return fail(FEM_E_INVAL, "energy_every and eval_every must be >= 0");
+    if (P.gradient != FEM_GRAD_EXPLICIT && P.gradient != FEM_GRAD_MANIPULATED)
+        return fail(FEM_E_INVAL, "unknown gradient mode %d", P.gradient);
+    if (!std::isfinite(P.gamma_grad)) return fail(FEM_E_INVAL, "gamma_grad must be finite");
+    if (P.gradient == FEM_GRAD_MANIPULATED && P.energy_every != 0)
+        return fail(FEM_E_UNSUPPORTED, "manipulated gradients form no energies: set energy_every = 0");
     const Problem& p = fp->p;
     if ((int64_t)p.n * P.replicas * (p.kind == KIND_BMINCUT ? p.q : 1) > ((int64_t)1 << 40))
         return fail(FEM_E_NOMEM, "state of %lld values does not fit", (long long)p.n * P.replicas);
@@ -929,6 +989,8 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     s->n_inst = p.n_inst;
     s->vals = (size_t)s->n * s->R * s->Q;
     s->NE = (p.kind == KIND_BMINCUT) ? 3 : 2;
+    s->manip = P.gradient == FEM_GRAD_MANIPULATED && p.kind != KIND_MAXSAT;
+    s->rw = (s->R + 31) / 32;
     s->beta.resize((size_t)P.steps);
     s->lam.resize((size_t)P.steps);
     for (int t = 0; t < P.steps; ++t) {
@@ -944,12 +1006,15 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     hipError_t e = hipSetDevice(p.device);
     if (e != hipSuccess) return bail(fail(FEM_E_HIP, "hipSetDevice: %s", hipGetErrorString(e)));
     const size_t msz = s->dtype == FEM_BF16 ? 2 : 4;
+    // bytes of one marginal-copy buffer
+    const size_t mbytes = !s->manip ? s->vals * msz
+                          : s->kind == KIND_MAXCUT ? (size_t)s->n * s->rw * 4 : (size_t)s->n * s->R;
     const size_t IR = (size_t)s->n_inst * s->R;
     {
         size_t free_b = 0, total_b = 0;
         e = hipMemGetInfo(&free_b, &total_b);
         if (e != hipSuccess) return bail(fail(FEM_E_HIP, "hipMemGetInfo: %s", hipGetErrorString(e)));
-        const double need = (double)s->vals * (12.0 + 2.0 * msz + (P.keep_grad ? 4.0 : 0.0));
+        const double need = (double)s->vals * (12.0 + (P.keep_grad ? 4.0 : 0.0)) + 2.0 * (double)mbytes;
         if (need > (double)free_b)
             return bail(fail(FEM_E_NOMEM, "solver state needs %.3g GB, %.3g GB free on device %d", need * 1e-9,
                              free_b * 1e-9, p.device));
@@ -966,7 +1031,7 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     ALLOC(s->m2, s->vals);
     if (P.keep_grad) ALLOC(s->grad, s->vals);
     for (int k = 0; k < 2; ++k) {
-        e = hipMalloc(&s->marg[k], s->vals * msz);
+        e = hipMalloc(&s->marg[k], mbytes ? mbytes : 4);
         if (e != hipSuccess) return bail(fail(FEM_E_NOMEM, "device allocation of the marginal copy: %s", hipGetErrorString(e)));
     }
     ALLOC(s->eraw, IR * s->NE);
@@ -1405,6 +1470,7 @@ fem_status fem_get_tile(const fem_solver* s, fem_tile* t)
     t->waves = s->shape.waves;
     t->rows = s->shape.rows;
     t->nt = s->shape.nt;
+    t->lanes = s->geo.lanes;
     return FEM_OK;
 }
 
@@ -1416,8 +1482,11 @@ fem_status fem_set_tile(fem_solver* s, const fem_tile* t)
     sh.waves = t->waves;
     sh.rows = t->rows;
     sh.nt = t->nt ? 1 : 0;
+    sh.lanes = t->lanes;
     if (t->nt != 0 && t->nt != 1) return fail(FEM_E_INVAL, "nt must be 0 or 1");
-    if (!valid_shape(s, sh)) return fail(FEM_E_INVAL, "invalid tile shape (vec %d, waves %d, rows %d) for R = %d", t->vec, t->waves, t->rows, s->R);
+    if (!valid_shape(s, sh))
+        return fail(FEM_E_INVAL, "invalid tile shape (vec %d, waves %d, rows %d, lanes %d) for R = %d", t->vec, t->waves,
+                    t->rows, t->lanes, s->R);
     HIPCHK(hipSetDevice(s->prob->device));
     HIPCHK(hipStreamSynchronize(s->stream));
     STCHK(setup_tiling(s, sh));
@@ -1441,8 +1510,9 @@ static std::string tune_cache_path()
 static std::string tune_key(const fem_solver* s)
 {
     char buf[256];
-    snprintf(buf, sizeof buf, "k%d_n%d_nnz%lld_R%d_q%d_dt%d_inst%d_en%d", s->kind, s->n, (long long)s->prob->nnz, s->R,
-             s->q, s->dtype, s->n_inst, s->prm.energy_every > 0 ? 1 : 0);
+    snprintf(buf, sizeof buf, "v2_k%d_n%d_nnz%lld_R%d_q%d_dt%d_inst%d_en%d_g%d", s->kind, s->n,
+             (long long)s->prob->nnz, s->R, s->q, s->dtype, s->n_inst, s->prm.energy_every > 0 ? 1 : 0,
+             s->manip ? 1 : 0);
     return buf;
 }
 
@@ -1456,21 +1526,23 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     if (use_cache) {
         FILE* f = std::fopen(path.c_str(), "r");
         if (f) {
-            char k[256];
-            int v, w, r, ntf;
+            char line[512], k[256];
+            int v, w, r, ntf, ln;
             bool found = false;
             TileShape sh;
-            while (std::fscanf(f, "%255s %d %d %d %d", k, &v, &w, &r, &ntf) == 5)
-                if (key == k) {
+            // one "key vec waves rows nt lanes" line per tuning; the last match wins
+            while (std::fgets(line, sizeof line, f))
+                if (std::sscanf(line, "%255s %d %d %d %d %d", k, &v, &w, &r, &ntf, &ln) == 6 && key == k) {
                     sh.vec = v;
                     sh.waves = w;
                     sh.rows = r;
                     sh.nt = ntf;
+                    sh.lanes = ln;
                     found = true;
                 }
             std::fclose(f);
             if (found && valid_shape(s, sh)) {
-                fem_tile t{sh.vec, sh.waves, sh.rows, sh.nt};
+                fem_tile t{sh.vec, sh.waves, sh.rows, sh.nt, sh.lanes};
                 STCHK(fem_set_tile(s, &t));
                 if (chosen) STCHK(fem_get_tile(s, chosen));
                 return FEM_OK;
@@ -1510,17 +1582,24 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     const int vecs[4] = {1, 2, 4, 8};
     const int wavess[4] = {2, 4, 8, 16};
     const int rowss[4] = {1, 2, 4, 8};
+    const int laness[4] = {0, 32, 16, 8};
     for (int vi = 0; vi < (s->kind == KIND_BMINCUT ? 1 : 4); ++vi)
-        for (int wv : wavess)
-            for (int rw : rowss)
-                for (int ntf = 0; ntf < 2; ++ntf) {
-                    TileShape sh;
-                    sh.vec = vecs[vi];
-                    sh.waves = wv;
-                    sh.rows = rw;
-                    sh.nt = ntf;
-                    if (valid_shape(s, sh)) cands.push_back(sh);
-                }
+        for (int ln : laness) {
+            // a lane cap only matters where it splits the replicas
+            const int per_lane = s->kind == KIND_BMINCUT ? 1 : vecs[vi];
+            if (ln != 0 && make_geom(per_lane, s->R, 1, ln).nseg == make_geom(per_lane, s->R, 1).nseg) continue;
+            for (int wv : wavess)
+                for (int rw : rowss)
+                    for (int ntf = 0; ntf < 2; ++ntf) {
+                        TileShape sh;
+                        sh.vec = vecs[vi];
+                        sh.waves = wv;
+                        sh.rows = rw;
+                        sh.nt = ntf;
+                        sh.lanes = ln;
+                        if (valid_shape(s, sh)) cands.push_back(sh);
+                    }
+        }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1530,7 +1609,7 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     s->profile = false;
     fem_status st = FEM_OK;
     for (const TileShape& sh : cands) {
-        fem_tile t{sh.vec, sh.waves, sh.rows, sh.nt};
+        fem_tile t{sh.vec, sh.waves, sh.rows, sh.nt, sh.lanes};
         st = fem_set_tile(s, &t);
         if (st != FEM_OK) break;
         st = save_restore(false);
@@ -1554,7 +1633,7 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     s->profile = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    fem_tile bt{best_sh.vec, best_sh.waves, best_sh.rows, best_sh.nt};
+    fem_tile bt{best_sh.vec, best_sh.waves, best_sh.rows, best_sh.nt, best_sh.lanes};
     fem_status st2 = fem_set_tile(s, &bt);
     if (st2 == FEM_OK) st2 = save_restore(false);
     dfree(backup);
@@ -1562,7 +1641,8 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     if (st2 != FEM_OK) return st2;
     FILE* f = std::fopen(path.c_str(), "a");
     if (f) {
-        std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), best_sh.vec, best_sh.waves, best_sh.rows, best_sh.nt);
+        std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), best_sh.vec, best_sh.waves, best_sh.rows, best_sh.nt,
+                     best_sh.lanes);
         std::fclose(f);
     }
     if (chosen) STCHK(fem_get_tile(s, chosen));

@@ -36,12 +36,14 @@ struct Problem {
     int2* inc2 = nullptr;            // Max-k-SAT, <= 2 other literals per incidence
     int4* inc4 = nullptr;            // Max-k-SAT, <= 3 other literals per incidence
     float* wdeg = nullptr;           // bMinCut: sum_j W_ij per node
+    double* nrm = nullptr;           // graphs: sum_j |W_ij| per node (normalisers of the manipulated gradients)
     // host copies kept for batching and validation
     std::vector<int64_t> h_row_off;
     std::vector<int2> h_adj;
     std::vector<int2> h_inc2;
     std::vector<int4> h_inc4;
     std::vector<float> h_wdeg;
+    std::vector<double> h_nrm;
 };
 
 // Marginal-copy literal packing for Max-k-SAT incidence records:
@@ -65,13 +67,15 @@ __host__ __device__ constexpr int step_max_threads(int kind, int per_lane)
 
 struct TileShape {
     int vec = 1, waves = 4, rows = 4;
-    int nt = 0;   // non-temporal access to h, m1, m2
+    int nt = 0;      // non-temporal access to h, m1, m2
+    int lanes = 0;   // cap on lanes per team (power of two <= 64; 0 = 64)
 };
 
 // Per-step scalars, computed on the host in double and passed as float.
 struct StepScalars {
     double inv_beta_d;   // 1/beta and lambda in double for the gradient combination
     double lam_d;
+    double gamma_d;      // gamma_grad (manipulated gradients and Max-k-SAT; 1 otherwise)
     float inv_beta;
     float lam;
     float step_size;   // lr / (1 - b1^n)
@@ -84,9 +88,10 @@ struct StepScalars {
 
 struct LaunchGeom {
     int lanes;        // lanes per team (power of two, <= 64)
-    int nseg;         // replica segments (grid.y)
+    int nseg;         // replica segments
     int teams_per_block;
     int n_tiles;
+    int seg_major;    // grid (nseg, n_tiles) instead of (n_tiles, nseg)
 };
 
 // Arguments shared by the step kernels.
@@ -96,6 +101,7 @@ struct StepArgs {
     const int2* inc2;
     const int4* inc4;
     const float* wdeg;
+    const double* nrm;            // per-node sum_j |W_ij| (manipulated gradients)
     const Tile* tiles;
     const void* marg_cur;
     void* marg_nxt;
@@ -106,9 +112,12 @@ struct StepArgs {
     double* epart;                // [n_tiles][NE][R] or null (no energies this step)
     const double* ctil;           // bMinCut: centred column sums C~ [inst][R][q]
     long long* cpart;             // bMinCut: column-sum partials of the new P [n_tiles][R][q]
+    int32_t n;
     int32_t R;
     int32_t q;
+    int32_t rw;                   // MaxCut manipulated: 32-bit words per row of the sign bits
     int32_t lanes_log2;
+    int32_t seg_major;            // block -> (tile, segment) mapping of the grid
     StepScalars sc;
 };
 
@@ -130,7 +139,14 @@ hipError_t launch_seg_reduce(const T* part, int cols, const int32_t* chunk_off, 
 hipError_t launch_energy_combine(int kind, int R, int q, int n_inst, const double* raw,
                                  const double* wtot, const double* csum, double lam, double beta,
                                  double* eout, hipStream_t st);
-hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, double* csum,
+// manipulated gradients (fem_manip.hip): the step kernel, and the read-out copy
+// of a.h (sign bits or argmax states, with per-tile state counts for bMinCut)
+hipError_t launch_manip_step(int kind, int vec, bool nt, const LaunchGeom& g, int waves, const StepArgs& a,
+                             hipStream_t st);
+hipError_t launch_manip_init(int kind, const LaunchGeom& g, int waves, const StepArgs& a, hipStream_t st);
+// csum = fx * scale (2^-40 for fixed-point marginal sums, 1 for state counts),
+// ctil = csum minus its mean over the states
+hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, double scale, double* csum,
                                  double* ctil, hipStream_t st);
 hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h,
                         uint8_t* sigma, hipStream_t st);

@@ -23,6 +23,7 @@ FEM_OK, FEM_E_INVAL, FEM_E_NOMEM, FEM_E_HIP, FEM_E_STATE, FEM_E_NUMERIC, FEM_E_U
 MAXCUT, BMINCUT, MAXSAT = 0, 1, 2
 SCHED_LINEAR, SCHED_EXP, SCHED_INVPROP = 0, 1, 2
 OPT_ADAM, OPT_RMSPROP, OPT_SGD = 0, 1, 2
+GRAD_EXPLICIT, GRAD_MANIPULATED = 0, 1
 F32, BF16 = 0, 1
 
 
@@ -43,11 +44,13 @@ class Params(C.Structure):
         ("marginal_dtype", C.c_int32), ("energy_every", C.c_int32),
         ("record_energies", C.c_int32), ("eval_every", C.c_int32), ("keep_grad", C.c_int32),
         ("optimizer", C.c_int32), ("momentum", C.c_double), ("rms_alpha", C.c_double), ("dampening", C.c_double),
+        ("gradient", C.c_int32), ("gamma_grad", C.c_double),
     ]
 
 
 class Tile(C.Structure):
-    _fields_ = [("vec", C.c_int32), ("waves", C.c_int32), ("rows", C.c_int32), ("nt", C.c_int32)]
+    _fields_ = [("vec", C.c_int32), ("waves", C.c_int32), ("rows", C.c_int32), ("nt", C.c_int32),
+                ("lanes", C.c_int32)]
 
 
 _lib = None
@@ -360,19 +363,20 @@ class Solver:
 
     # ---- tiling
     def tile(self):
-        """(vec, waves, rows, nt)"""
+        """(vec, waves, rows, nt, lanes)"""
         t = Tile()
         _check(lib().fem_get_tile(self._h, C.byref(t)))
-        return (t.vec, t.waves, t.rows, t.nt)
+        return (t.vec, t.waves, t.rows, t.nt, t.lanes)
 
-    def set_tile(self, vec, waves, rows, nt=0):
-        t = Tile(vec, waves, rows, nt)
+    def set_tile(self, vec, waves, rows, nt=0, lanes=0):
+        t = Tile(vec, waves, rows, nt, lanes)
         _check(lib().fem_set_tile(self._h, C.byref(t)))
 
     def tune(self, trial_steps=5, use_cache=True):
+        """Time every valid launch shape; returns the chosen (vec, waves, rows, nt, lanes)."""
         t = Tile()
         _check(lib().fem_tune(self._h, trial_steps, int(use_cache), C.byref(t)))
-        return (t.vec, t.waves, t.rows, t.nt)
+        return (t.vec, t.waves, t.rows, t.nt, t.lanes)
 
     # ---- profiling
     def profile(self, on=True):

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version_and_status_strings():
-    assert fem.lib().fem_abi_version() == 1
+    assert fem.lib().fem_abi_version() == 2
     assert fem.status_str(0) == "FEM_OK"
     assert fem.status_str(-1) == "FEM_E_INVAL"
     assert fem.status_str(-6) == "FEM_E_UNSUPPORTED"

@@ -62,10 +62,10 @@ def test_lambda_ramp():
     lockstep_potts(W.rgg_3d(300, 10.0, seed=5), 4, R=8, T=60, n_steps=60, seed=4, lam=0.8, ramp=1, tag="ramp")
 
 
-@pytest.mark.parametrize("waves,rows", [(1, 1), (8, 3), (2, 16)])
-def test_tile_shapes(waves, rows):
-    lockstep_potts(W.rgg_3d(500, 14.0, seed=6), 8, R=16, T=100, n_steps=10, seed=8, tile=(8, waves, rows),
-                   tag=f"tile{waves}x{rows}")
+@pytest.mark.parametrize("waves,rows,lanes", [(1, 1, 0), (8, 3, 0), (2, 16, 0), (4, 2, 4)])
+def test_tile_shapes(waves, rows, lanes):
+    lockstep_potts(W.rgg_3d(500, 14.0, seed=6), 8, R=16, T=100, n_steps=10, seed=8, tile=(8, waves, rows, 0, lanes),
+                   tag=f"tile{waves}x{rows}L{lanes}")
 
 
 def test_integer_eval_sizes_bitexact():

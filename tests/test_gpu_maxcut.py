@@ -90,11 +90,14 @@ def test_isolated_nodes_and_tiny_graphs():
     lockstep_maxcut(g1, R=4, T=10, n_steps=5, seed=4, tag="single node")
 
 
-@pytest.mark.parametrize("vec,waves,rows,nt", [(1, 1, 1, 0), (2, 8, 3, 1), (4, 2, 16, 0), (8, 4, 4, 1)])
-def test_every_tile_shape_matches_oracle(vec, waves, rows, nt):
+@pytest.mark.parametrize("vec,waves,rows,nt,lanes", [(1, 1, 1, 0, 0), (2, 8, 3, 1, 0), (4, 2, 16, 0, 0),
+                                                   (8, 4, 4, 1, 0), (4, 4, 2, 1, 2), (1, 8, 3, 0, 8),
+                                                   (2, 2, 5, 1, 16)])
+def test_every_tile_shape_matches_oracle(vec, waves, rows, nt, lanes):
+    # lanes < R/vec splits the replicas into segments (segment-major grid)
     g = W.random_sparse_graph(900, 2700, seed=5, weights="pm1")
-    lockstep_maxcut(g, R=64, T=100, n_steps=15, seed=9, tile=(vec, waves, rows, nt),
-                    tag=f"tile{vec}x{waves}x{rows}nt{nt}")
+    lockstep_maxcut(g, R=64, T=100, n_steps=15, seed=9, tile=(vec, waves, rows, nt, lanes),
+                    tag=f"tile{vec}x{waves}x{rows}nt{nt}L{lanes}")
 
 
 def test_integer_eval_bitexact():

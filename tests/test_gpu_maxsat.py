@@ -73,10 +73,11 @@ def test_mixed_lengths_repeats_tautologies(R):
     lockstep_sat(mixed_cnf(300, 1500, seed=R), R=R, T=300, n_steps=40, seed=R + 1, tag=f"mixed_R{R}")
 
 
-@pytest.mark.parametrize("vec,waves,rows", [(1, 2, 1), (2, 4, 5), (4, 8, 2)])
-def test_tile_shapes(vec, waves, rows):
-    lockstep_sat(W.random_ksat(1000, 8000, 3, seed=8), R=64, T=100, n_steps=10, seed=5, tile=(vec, waves, rows),
-                 tag=f"tile{vec}x{waves}x{rows}")
+@pytest.mark.parametrize("vec,waves,rows,lanes", [(1, 2, 1, 0), (2, 4, 5, 0), (4, 8, 2, 0), (4, 4, 3, 4),
+                                                (2, 2, 2, 8)])
+def test_tile_shapes(vec, waves, rows, lanes):
+    lockstep_sat(W.random_ksat(1000, 8000, 3, seed=8), R=64, T=100, n_steps=10, seed=5,
+                 tile=(vec, waves, rows, 0, lanes), tag=f"tile{vec}x{waves}x{rows}L{lanes}")
 
 
 def test_unsat_count_bitexact():

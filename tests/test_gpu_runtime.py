@@ -103,19 +103,20 @@ def test_every_tile_shape_gives_identical_fields(kind):
     if kind == "maxcut":
         g, prob = maxcut_problem(n=1500, seed=9)
         h0 = W.initial_fields(g.n, R, seed=9)
-        shapes = [(1, 4, 4), (2, 1, 1, 1), (4, 8, 2), (4, 8, 2, 1), (8, 2, 16), (8, 4, 4, 1), (4, 16, 1)]
+        shapes = [(1, 4, 4), (2, 1, 1, 1), (4, 8, 2), (4, 8, 2, 1), (8, 2, 16), (8, 4, 4, 1), (4, 16, 1),
+                  (4, 4, 4, 1, 2), (1, 8, 2, 0, 8)]
         kw = {}
     elif kind == "maxsat":
         cnf = W.random_ksat(1500, 12000, 3, seed=9)
         prob = fem.Problem.maxsat(cnf.n_vars, cnf.clause_off, cnf.lits)
         h0 = W.initial_fields(cnf.n_vars, R, seed=9)
-        shapes = [(1, 4, 4), (2, 2, 3, 1), (4, 8, 1), (8, 1, 8, 1)]
+        shapes = [(1, 4, 4), (2, 2, 3, 1), (4, 8, 1), (8, 1, 8, 1), (4, 4, 2, 1, 4)]
         kw = {}
     else:
         g = W.rgg_3d(900, 14.0, seed=9)
         prob = fem.Problem.bmincut(g.n, g.u, g.v, g.w, 4)
         h0 = W.initial_fields(g.n, R, seed=9, q=4)
-        shapes = [(4, 4, 4), (4, 1, 1, 1), (4, 8, 3), (4, 2, 16, 1)]
+        shapes = [(4, 4, 4), (4, 1, 1, 1), (4, 8, 3), (4, 2, 16, 1), (4, 4, 2, 0, 16)]
         kw = {"lam": 1.0}
     ref = None
     for sh in shapes:
