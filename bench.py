@@ -125,10 +125,10 @@ def main():
                          "instances; copy: a plain device copy (calibrates HBM counters)")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--plain-steps", type=int, default=1000)
-    ap.add_argument("--warm-steps", type=int, default=600)
-    ap.add_argument("--beta-start", type=float, default=0.5)
-    ap.add_argument("--alpha", type=float, default=1.0)
-    ap.add_argument("--draws", type=int, default=32)
+    ap.add_argument("--early-steps", type=int, default=100, help="batch512: plain steps before the proposal")
+    ap.add_argument("--warm-steps", type=int, default=300, help="batch512: length of the continued anneal")
+    ap.add_argument("--beta-start", type=float, default=0.3, help="batch512: beta at the start of the continuation")
+    ap.add_argument("--alpha", type=float, default=1.0, help="batch512: scale of the network's proposal")
     ap.add_argument("--eval-every", type=int, default=25)
     ap.add_argument("--params", default=os.path.join(ROOT, "paper_2412_09285_amd", "data", "mpnn_maxcut.bin"))
     args = ap.parse_args()

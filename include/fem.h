@@ -269,16 +269,21 @@ fem_status fem_profile(fem_solver* s, int32_t on);
 fem_status fem_profile_result(fem_solver* s, double* step_kernel_ms, int32_t* n_kernels);
 
 /* ----------------------------------------------------- learned warm start */
-/* A two-layer message-passing network (width 64) proposing initial MaxCut
- * fields, trained on FEM's own solutions; an addition on top of the method
- * (the paper has no network).  Node features: [1, ln(1+deg), mean incident
- * weight, five uniforms in [-1,1) from Philox4x32-10 with counter (node, draw,
- * block, 0) and key (seed mod 2^32, seed div 2^32)].  Layers: pre1 = x A1 +
- * a(x) B1 + b1, H1 = relu(pre1); pre2 = H1 A2 + a(H1) B2 + b2, H2 = relu(pre2);
- * z = H2 c + d; a(v)_i = sum_j W_ij v_j / max(deg_i, 1).  Weights are used as
- * bfloat16 with float32 arithmetic; the 9409 float32 master parameters are
- * laid out A1 [8][64], B1 [8][64], b1 [64], A2 [64][64], B2 [64][64], b2 [64],
- * c [64], d [1]. */
+/* A two-layer message-passing network (width 64) that maps the state of one
+ * MaxCut replica part-way through an anneal to a proposal for that replica's
+ * final read-out: one logit z_i per node, from which the anneal continues
+ * with fields alpha * z and a shorter, colder schedule.  Trained on FEM's own
+ * runs; an addition on top of the method (the paper has no network).
+ * Node features from the replica's fields s: [1, ln(1+deg), mean incident
+ * weight, tanh(s_i/2), clamp(s_i/4, -2, 2), three uniforms in [-1,1) from
+ * Philox4x32-10 with counter (node, draw, 0, 0) and key (seed mod 2^32,
+ * seed div 2^32)].  Layers: pre1 = x A1 + a(x) B1 + b1, H1 = relu(pre1);
+ * pre2 = H1 A2 + a(H1) B2 + b2, H2 = relu(pre2); z = H2 c + d;
+ * a(v)_i = sum_j W_ij v_j / max(deg_i, 1).  Weights are used as bfloat16 with
+ * float32 arithmetic; the 9409 float32 master parameters are laid out
+ * A1 [8][64], B1 [8][64], b1 [64], A2 [64][64], B2 [64][64], b2 [64], c [64],
+ * d [1].  The network calls run on the null stream and return after their
+ * work has finished. */
 typedef struct fem_mpnn fem_mpnn;
 
 /* theta0: 9409 host float32 initial parameters (n_params must be 9409). */
@@ -287,23 +292,25 @@ void fem_mpnn_destroy(fem_mpnn* m);
 /* master parameters (host, 9409 float32); set also resets the Adam moments. */
 fem_status fem_mpnn_get_params(fem_mpnn* m, float* theta);
 fem_status fem_mpnn_set_params(fem_mpnn* m, const float* theta);
-/* logits z [n] of a MaxCut problem (or batch) for one feature draw. */
-fem_status fem_mpnn_forward(fem_mpnn* m, const fem_problem* p, uint64_t seed, int32_t draw, float* z,
-                            int on_device);
+/* logits z [n] of a MaxCut problem (or batch) for one replica's fields
+ * state [n] and one feature draw; state and z are both host or both device. */
+fem_status fem_mpnn_forward(fem_mpnn* m, const fem_problem* p, const float* state, uint64_t seed, int32_t draw,
+                            float* z, int on_device);
 /* One training step on a MaxCut batch (fem_batch_create, or one instance):
- * labels [n] host int32 in {0, 1} (a FEM solution per instance); features of
- * draw draw0; loss = mean over instances of min(BCE(z, y), BCE(z, 1 - y)),
+ * state [n] host float32, the fields of one replica of each instance at the
+ * early step; labels [n] host int32 in {0, 1}, the final read-out of the same
+ * replica; features of draw draw0; loss = mean over instances of BCE(z, y),
  * BCE = mean over the instance's nodes of softplus(z) - y z; the gradient is
  * taken wrt the bfloat16 weights and applied to the master weights by Adam
  * (0.9, 0.999, 1e-8, learning rate lr).  loss and grad_out (9409, host) may
  * be NULL. */
-fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* batch, const int32_t* labels, uint64_t seed,
-                               int32_t draw0, double lr, double* loss, float* grad_out);
-/* Initial fields for R replicas: h0[i][r] = alpha * z_i of draw (r mod
- * n_draws), 1 <= n_draws <= R, written in the [n][R] layout (host or device);
- * pass it to fem_set_fields. */
-fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* p, int32_t R, uint64_t seed, int32_t n_draws,
-                          float alpha, float* h0, int on_device);
+fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* batch, const float* state, const int32_t* labels,
+                               uint64_t seed, int32_t draw0, double lr, double* loss, float* grad_out);
+/* Proposal for R replicas: h_out[i][r] = alpha * z_i, z the logits of
+ * replica r's fields state[i][r] with feature draw r; state and h_out are
+ * [n][R] float32, both host or both device (they may not overlap). */
+fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* p, int32_t R, const float* state, uint64_t seed,
+                          float alpha, float* h_out, int on_device);
 /* parameter file: 8-byte magic "FEMMPNN1", int32 9409, 9409 float32. */
 fem_status fem_mpnn_save(fem_mpnn* m, const char* path);
 fem_status fem_mpnn_load(fem_mpnn* m, const char* path);

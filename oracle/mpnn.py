@@ -2,24 +2,27 @@
 only; the product path never imports it).
 
 The paper has no neural network: this is the learned warm start built on top
-of FEM.  Its specification, which the HIP kernels implement independently:
+of FEM.  It maps the state of one replica part-way through an anneal to a
+proposal for that replica's final read-out, from which a shorter anneal
+continues.  Its specification, which the HIP kernels implement independently:
 
 * Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
   "Parallel random numbers: as easy as 1, 2, 3", SC 2011), written here from
-  that definition; random features are uniform in [-1, 1) from the top 24 bits
-  of a Philox word, so they are exact in float32 and float64 alike.
-* Node features x_i (8): [1, ln(1 + deg_i), mean_{j in N(i)} W_ij (0 if
-  isolated), u_i^1 .. u_i^5] with u from Philox(counter = (i, draw, 0, 0) and
-  (i, draw, 1, 0), key = (seed mod 2^32, seed div 2^32)): words 0..3 of the
-  first block and word 0 of the second.
+  that definition; uniforms in [-1, 1) from the top 24 bits of a Philox word,
+  so they are exact in float32 and float64 alike.
+* Node features x_i (8) from one replica's fields s (float32, length n):
+  [1, ln(1 + deg_i), mean_{j in N(i)} W_ij (0 if isolated), tanh(s_i / 2),
+  clamp(s_i / 4, -2, 2), u_i^1, u_i^2, u_i^3] with u words 0..2 of
+  Philox(counter = (i, draw, 0, 0), key = (seed mod 2^32, seed div 2^32)).
 * Two layers, width 64, mean aggregation a_i = (1 / max(deg_i, 1)) sum_j W_ij v_j:
       pre1 = x A1 + a1(x) B1 + b1,      H1 = relu(pre1)
       pre2 = H1 A2 + a2(H1) B2 + b2,    H2 = relu(pre2)
-      z = H2 c + d                      (one logit per node and draw)
+      z = H2 c + d                      (one logit per node)
   with every weight rounded to bfloat16 (round to nearest even) before use.
-* Loss of an instance with label y (0/1 per node, a FEM solution): flip
-  invariant, L = min(BCE(z, y), BCE(z, 1 - y)), BCE(z, y) = mean_i
-  [softplus(z_i) - y_i z_i]; a batch averages its instances.
+* Loss of a batch of instances (a block-diagonal union), each with its own
+  replica's fields and label y (0/1 per node, the final read-out of that
+  replica): the mean over instances of BCE(z, y) = mean_i [softplus(z_i) -
+  y_i z_i].
 * Flat parameter vector (9409 values): A1 [8][64], B1 [8][64], b1 [64],
   A2 [64][64], B2 [64][64], b2 [64], c [64], d [1].
 
@@ -111,29 +114,29 @@ class GraphOps:
         return self.W.T @ (self.inv[:, None] * G)
 
 
-def features(ops: GraphOps, seed: int, draw: int):
+def features(ops: GraphOps, state, seed: int, draw: int):
     n = ops.n
+    st = np.asarray(state, dtype=np.float64).reshape(n)
     i = np.arange(n, dtype=np.uint64)
     k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
     r0 = philox4x32_10(i, np.uint64(draw), 0, 0, k0, k1)
-    r1 = philox4x32_10(i, np.uint64(draw), 1, 0, k0, k1)
     x = np.empty((n, D_IN))
     x[:, 0] = 1.0
     x[:, 1] = np.log1p(ops.deg)
     x[:, 2] = ops.wmean
-    x[:, 3] = uniform_pm1(r0[0])
-    x[:, 4] = uniform_pm1(r0[1])
-    x[:, 5] = uniform_pm1(r0[2])
-    x[:, 6] = uniform_pm1(r0[3])
-    x[:, 7] = uniform_pm1(r1[0])
+    x[:, 3] = np.tanh(st / 2.0)
+    x[:, 4] = np.clip(st / 4.0, -2.0, 2.0)
+    x[:, 5] = uniform_pm1(r0[0])
+    x[:, 6] = uniform_pm1(r0[1])
+    x[:, 7] = uniform_pm1(r0[2])
     return x
 
 
-def forward(ops: GraphOps, theta, seed: int, draw: int, quantize: bool = True):
+def forward(ops: GraphOps, theta, state, seed: int, draw: int, quantize: bool = True):
     """quantize=False skips the bfloat16 rounding (used to check the backward
     pass by finite differences, where the rounding would hide the steps)."""
     P = unpack(bf16_round(np.asarray(theta, dtype=np.float32)) if quantize else np.asarray(theta, dtype=np.float64))
-    x = features(ops, seed, draw)
+    x = features(ops, state, seed, draw)
     a1 = ops.agg(x)
     pre1 = x @ P["A1"] + a1 @ P["B1"] + P["b1"]
     H1 = np.maximum(pre1, 0.0)
@@ -148,72 +151,29 @@ def softplus(z):
     return np.maximum(z, 0.0) + np.log1p(np.exp(-np.abs(z)))
 
 
-def instance_loss(z, y):
-    """(L, flip): L = min over the two labellings; flip = 1 if 1 - y won."""
-    L0 = np.mean(softplus(z) - y * z)
-    L1 = np.mean(softplus(z) - (1.0 - y) * z)
-    return (L0, 0) if L0 <= L1 else (L1, 1)
+def bce(z, y):
+    """mean_i softplus(z_i) - y_i z_i"""
+    return float(np.mean(softplus(z) - y * z))
 
 
-def loss_and_grad(items, theta, seed: int, draws, quantize: bool = True):
-    """items: list of (GraphOps, label array); draws: the draw used per item.
-    Returns (mean loss, gradient wrt the bf16-rounded parameters, as a flat
-    vector)."""
-    grads = {name: np.zeros(shp) for name, shp in SHAPES}
-    total = 0.0
-    B = len(items)
-    for (ops, y), draw in zip(items, draws):
-        f = forward(ops, theta, seed, draw, quantize)
-        P = f["P"]
-        L, flip = instance_loss(f["z"], y)
-        total += L / B
-        yt = (1.0 - y) if flip else y
-        n = ops.n
-        dz = (1.0 / (1.0 + np.exp(-f["z"])) - yt) / n / B
-        grads["c"] += f["H2"].T @ dz
-        grads["d"] += dz.sum()
-        dpre2 = np.outer(dz, P["c"]) * (f["pre2"] > 0)
-        grads["A2"] += f["H1"].T @ dpre2
-        grads["B2"] += f["a2"].T @ dpre2
-        grads["b2"] += dpre2.sum(0)
-        dH1 = dpre2 @ P["A2"].T + ops.agg_T(dpre2 @ P["B2"].T)
-        dpre1 = dH1 * (f["pre1"] > 0)
-        grads["A1"] += f["x"].T @ dpre1
-        grads["B1"] += f["a1"].T @ dpre1
-        grads["b1"] += dpre1.sum(0)
-    return total, pack(grads)
-
-
-def loss_only(items, theta, seed, draws, quantize: bool = True):
-    total = 0.0
-    for (ops, y), draw in zip(items, draws):
-        f = forward(ops, theta, seed, draw, quantize)
-        total += instance_loss(f["z"], y)[0] / len(items)
-    return total
-
-
-def batch_loss_and_grad(ops: GraphOps, inst_off, labels, theta, seed: int, draw: int, quantize: bool = True):
-    """The loss and gradient of one training step on a block-diagonal batch:
-    one forward over the union graph (features keyed by the node's index in
-    the union and one draw), per-instance flip-invariant BCE, mean over the
-    instances.  Returns (loss, grad, per-instance (L0, L1))."""
-    f = forward(ops, theta, seed, draw, quantize)
+def batch_loss_and_grad(ops: GraphOps, inst_off, state, labels, theta, seed: int, draw: int,
+                        quantize: bool = True):
+    """Loss and gradient of one training step on a block-diagonal batch: one
+    forward over the union graph (features keyed by the node's index in the
+    union), BCE per instance, mean over the instances.  Returns (loss, grad,
+    per-instance losses)."""
+    f = forward(ops, theta, state, seed, draw, quantize)
     P = f["P"]
     z = f["z"]
     y = np.asarray(labels, dtype=np.float64)
     B = len(inst_off) - 1
     dz = np.zeros_like(z)
-    total = 0.0
     Ls = []
     for b in range(B):
         sl = slice(inst_off[b], inst_off[b + 1])
         nb = inst_off[b + 1] - inst_off[b]
-        L0 = np.mean(softplus(z[sl]) - y[sl] * z[sl])
-        L1 = np.mean(softplus(z[sl]) - (1.0 - y[sl]) * z[sl])
-        Ls.append((L0, L1))
-        yt = (1.0 - y[sl]) if L1 < L0 else y[sl]
-        total += min(L0, L1) / B
-        dz[sl] = (1.0 / (1.0 + np.exp(-z[sl])) - yt) / nb / B
+        Ls.append(bce(z[sl], y[sl]))
+        dz[sl] = (1.0 / (1.0 + np.exp(-z[sl])) - y[sl]) / nb / B
     grads = {}
     grads["c"] = f["H2"].T @ dz
     grads["d"] = np.array([dz.sum()])
@@ -226,7 +186,14 @@ def batch_loss_and_grad(ops: GraphOps, inst_off, labels, theta, seed: int, draw:
     grads["A1"] = f["x"].T @ dpre1
     grads["B1"] = f["a1"].T @ dpre1
     grads["b1"] = dpre1.sum(0)
-    return total, pack(grads), Ls
+    return float(np.mean(Ls)), pack(grads), Ls
+
+
+def batch_loss(ops: GraphOps, inst_off, state, labels, theta, seed: int, draw: int, quantize: bool = True):
+    z = forward(ops, theta, state, seed, draw, quantize)["z"]
+    y = np.asarray(labels, dtype=np.float64)
+    return float(np.mean([bce(z[inst_off[b]:inst_off[b + 1]], y[inst_off[b]:inst_off[b + 1]])
+                          for b in range(len(inst_off) - 1)]))
 
 
 def adam_step(theta, m1, m2, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):

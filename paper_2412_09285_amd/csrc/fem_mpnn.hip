@@ -1,10 +1,14 @@
 // Learned warm start for MaxCut FEM: a two-layer message-passing network of
-// width 64 that maps node features (bias, ln(1+deg), mean incident weight and
-// five uniform random features from a counter-based generator) to one logit
-// per node, h0 = alpha * z.  Training uses solutions that FEM itself produced,
-// a flip-invariant binary cross-entropy, the analytic backward pass and Adam;
-// every kernel here is hand-written HIP.  The paper has no such network: this
-// is an addition on top of the method, meant to let the anneal start colder.
+// width 64 that maps the state of one replica part-way through an anneal to a
+// proposal for that replica's final read-out (one logit per node); the anneal
+// then continues from h = alpha * z with a shorter, colder schedule.  Node
+// features: bias, ln(1+deg), mean incident weight, tanh(s/2) and
+// clamp(s/4, -2, 2) of the replica's fields s, and three uniform random
+// features from a counter-based generator.  Training uses FEM's own runs (the
+// state at the early step and the final read-out of the same replica), a
+// binary cross-entropy, the analytic backward pass and Adam; every kernel here
+// is hand-written HIP.  The paper has no such network: this is an addition on
+// top of the method.
 //
 // Network (per draw d, node i; a(v)_i = (1/max(deg_i,1)) sum_j W_ij v_j):
 //   pre1 = x A1 + a(x) B1 + b1,    H1 = relu(pre1)
@@ -89,25 +93,27 @@ __device__ __forceinline__ float wave_sum(float v)
 }
 
 // ------------------------------------------------------------- forward ----
+// features of node i from the replica's fields state[i * stride]
 __global__ void feat_kernel(int32_t n, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
-                            uint32_t k0, uint32_t k1, uint32_t draw, float* __restrict__ X, float* __restrict__ inv_deg)
+                            const float* __restrict__ state, int64_t stride, uint32_t k0, uint32_t k1, uint32_t draw,
+                            float* __restrict__ X, float* __restrict__ inv_deg)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int64_t b = row_off[i], e = row_off[i + 1];
         float ws = 0.0f;
         for (int64_t k = b; k < e; ++k) ws += __int_as_float(adj[k].y);
         const float deg = (float)(e - b);
+        const float sv = state[(size_t)i * stride];
         const U4 r0 = philox((uint32_t)i, draw, 0u, 0u, k0, k1);
-        const U4 r1 = philox((uint32_t)i, draw, 1u, 0u, k0, k1);
         float* x = X + (size_t)i * D_IN;
         x[0] = 1.0f;
         x[1] = log1pf(deg);
         x[2] = e > b ? ws / deg : 0.0f;
-        x[3] = upm1(r0.x);
-        x[4] = upm1(r0.y);
-        x[5] = upm1(r0.z);
-        x[6] = upm1(r0.w);
-        x[7] = upm1(r1.x);
+        x[3] = tanhf(0.5f * sv);
+        x[4] = fminf(fmaxf(0.25f * sv, -2.0f), 2.0f);
+        x[5] = upm1(r0.x);
+        x[6] = upm1(r0.y);
+        x[7] = upm1(r0.z);
         inv_deg[i] = 1.0f / fmaxf(deg, 1.0f);
     }
 }
@@ -147,104 +153,116 @@ __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* _
     }
 }
 
-// one wave per node; A2, B2 staged in LDS as float
+// Lane j of a wave owns hidden unit j.  [A2; B2] (128 x 64, float) sits in
+// LDS, shared by the workgroup; a wave takes L2_NB nodes at a time, gathers
+// their H1 rows and aggregates a2 (coalesced 256-byte rows), stages the
+// L2_NB x [H1 | a2] inputs in its own LDS slice, and then for every k reads
+// one weight per lane (a conflict-free 256-byte row) and the nodes' inputs as
+// broadcasts, so each weight read feeds L2_NB FMAs.  The sum over k runs in
+// the same order (0..63 of H1, then 0..63 of a2) as a single-node evaluation.
+constexpr int L2_NB = 8;
 __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* __restrict__ row_off,
                                                      const int2* __restrict__ adj, const float* __restrict__ inv_deg,
                                                      const uint16_t* __restrict__ w, const float* __restrict__ pre1,
                                                      float* __restrict__ a2out, float* __restrict__ pre2out,
                                                      float* __restrict__ z)
 {
-    __shared__ float sA[HID * HID], sB[HID * HID];
+    __shared__ float sW[2 * HID * HID];                // [k][j], k < 64: A2, k >= 64: B2
+    __shared__ float4 sx[4][L2_NB][2 * HID / 4];       // per wave: L2_NB nodes x [H1 | a2]
     for (int t = threadIdx.x; t < HID * HID; t += blockDim.x) {
-        sA[t] = bf(w[OFF_A2 + t]);
-        sB[t] = bf(w[OFF_B2 + t]);
+        sW[t] = bf(w[OFF_A2 + t]);
+        sW[HID * HID + t] = bf(w[OFF_B2 + t]);
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
+    const int wl = threadIdx.x >> 6;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
     const float bias = bf(w[OFF_b2 + lane]);
     const float cl = bf(w[OFF_c + lane]);
     const float dd = bf(w[OFF_d]);
-    for (int i = wave; i < n; i += nw) {
-        const float h = fmaxf(pre1[(size_t)i * HID + lane], 0.0f);
-        float a = 0.0f;
-        for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
-            const int2 e = adj[k];
-            a = fmaf(__int_as_float(e.y), fmaxf(pre1[(size_t)e.x * HID + lane], 0.0f), a);
+    float* sxf = reinterpret_cast<float*>(&sx[wl][0][0]);
+    for (int i0 = wave * L2_NB; i0 < n; i0 += nw * L2_NB) {
+        const int cnt = (n - i0) < L2_NB ? (n - i0) : L2_NB;
+        for (int q = 0; q < cnt; ++q) {
+            const int i = i0 + q;
+            const float h = fmaxf(pre1[(size_t)i * HID + lane], 0.0f);
+            float a = 0.0f;
+            for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
+                const int2 e = adj[k];
+                a = fmaf(__int_as_float(e.y), fmaxf(pre1[(size_t)e.x * HID + lane], 0.0f), a);
+            }
+            a *= inv_deg[i];
+            sxf[q * 2 * HID + lane] = h;
+            sxf[q * 2 * HID + HID + lane] = a;
+            if (a2out) a2out[(size_t)i * HID + lane] = a;
         }
-        a *= inv_deg[i];
-        float acc = bias;
+        __builtin_amdgcn_wave_barrier();
+        float acc[L2_NB];
 #pragma unroll
-        for (int k = 0; k < HID; ++k) acc = fmaf(lane_val(h, k), sA[k * HID + lane], acc);
+        for (int q = 0; q < L2_NB; ++q) acc[q] = bias;
+#pragma unroll 2
+        for (int k4 = 0; k4 < 2 * HID / 4; ++k4) {
+            const float w0 = sW[(4 * k4) * HID + lane], w1 = sW[(4 * k4 + 1) * HID + lane];
+            const float w2 = sW[(4 * k4 + 2) * HID + lane], w3 = sW[(4 * k4 + 3) * HID + lane];
 #pragma unroll
-        for (int k = 0; k < HID; ++k) acc = fmaf(lane_val(a, k), sB[k * HID + lane], acc);
-        const float zz = wave_sum(fmaxf(acc, 0.0f) * cl);
-        if (a2out) a2out[(size_t)i * HID + lane] = a;
-        if (pre2out) pre2out[(size_t)i * HID + lane] = acc;
-        if (lane == 0) z[i] = zz + dd;
+            for (int q = 0; q < L2_NB; ++q) {
+                const float4 v = sx[wl][q][k4];
+                acc[q] = fmaf(v.x, w0, acc[q]);
+                acc[q] = fmaf(v.y, w1, acc[q]);
+                acc[q] = fmaf(v.z, w2, acc[q]);
+                acc[q] = fmaf(v.w, w3, acc[q]);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int q = 0; q < cnt; ++q) {
+            const int i = i0 + q;
+            const float zz = wave_sum(fmaxf(acc[q], 0.0f) * cl);
+            if (pre2out) pre2out[(size_t)i * HID + lane] = acc[q];
+            if (lane == 0) z[i] = zz + dd;
+        }
     }
 }
 
-// h0[i][r] = alpha * z_i for the replicas r with r mod n_draws == draw
-__global__ void write_h0_kernel(int32_t n, int32_t R, int32_t n_draws, int32_t draw, float alpha,
-                                const float* __restrict__ z, float* __restrict__ h0)
+// out[i][r] = alpha * z_i (column r of the [n][R] layout)
+__global__ void write_col_kernel(int32_t n, int32_t R, int32_t r, float alpha, const float* __restrict__ z,
+                                 float* __restrict__ out)
 {
-    const int per = (R - draw + n_draws - 1) / n_draws;   // replicas of this draw
-    const size_t count = (size_t)n * per;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
-        const size_t i = k / per;
-        const int r = draw + (int)(k % per) * n_draws;
-        h0[i * R + r] = alpha * z[i];
-    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        out[(size_t)i * R + r] = alpha * z[i];
 }
 
 // ------------------------------------------------------------ training ----
 __device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
 
-// per instance: L0 = mean softplus(z) - y z, L1 = mean softplus(z) - (1-y) z
+// per instance: L = mean softplus(z) - y z
 __global__ void __launch_bounds__(256) loss_kernel(const int32_t* __restrict__ inst_off, const float* __restrict__ z,
                                                    const int32_t* __restrict__ y, double* __restrict__ L)
 {
-    __shared__ double s0[256], s1[256];
+    __shared__ double s0[256];
     const int b = blockIdx.x;
     const int i0 = inst_off[b], i1 = inst_off[b + 1];
-    double a0 = 0.0, a1 = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        const float sp = softplusf(z[i]);
-        const float yy = (float)y[i];
-        a0 += (double)(sp - yy * z[i]);
-        a1 += (double)(sp - (1.0f - yy) * z[i]);
-    }
+    double a0 = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) a0 += (double)(softplusf(z[i]) - (float)y[i] * z[i]);
     s0[threadIdx.x] = a0;
-    s1[threadIdx.x] = a1;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            s0[threadIdx.x] += s0[threadIdx.x + s];
-            s1[threadIdx.x] += s1[threadIdx.x + s];
-        }
+        if ((int)threadIdx.x < s) s0[threadIdx.x] += s0[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double nb = (double)(i1 > i0 ? i1 - i0 : 1);
-        L[2 * b] = s0[0] / nb;
-        L[2 * b + 1] = s1[0] / nb;
-    }
+    if (threadIdx.x == 0) L[b] = s0[0] / (double)(i1 > i0 ? i1 - i0 : 1);
 }
 
-// dz_i = (sigmoid(z_i) - y~_i) / (N_b * B), y~ the labelling with the lower loss
+// dz_i = (sigmoid(z_i) - y_i) / (N_b * B)
 __global__ void dz_kernel(int32_t n, const int32_t* __restrict__ inst_of, const int32_t* __restrict__ inst_off,
-                          int32_t B, const double* __restrict__ L, const float* __restrict__ z,
-                          const int32_t* __restrict__ y, float* __restrict__ dz)
+                          int32_t B, const float* __restrict__ z, const int32_t* __restrict__ y,
+                          float* __restrict__ dz)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int b = inst_of[i];
-        const bool flip = L[2 * b + 1] < L[2 * b];
-        const float yt = flip ? 1.0f - (float)y[i] : (float)y[i];
         const float sg = 1.0f / (1.0f + expf(-z[i]));
         const float nb = (float)(inst_off[b + 1] - inst_off[b]);
-        dz[i] = (sg - yt) / (nb * (float)B);
+        dz[i] = (sg - (float)y[i]) / (nb * (float)B);
     }
 }
 
@@ -448,6 +466,7 @@ struct fem_mpnn {
     size_t cap_inst = 0;
     float *X = nullptr, *A1agg = nullptr, *inv_deg = nullptr, *pre1 = nullptr, *a2 = nullptr, *pre2 = nullptr,
           *z = nullptr, *dz = nullptr, *dpre2 = nullptr, *dh1s = nullptr, *da2s = nullptr, *dpre1 = nullptr;
+    float* state = nullptr;   // one replica's fields (training input)
     int32_t *y = nullptr, *inst_of = nullptr, *inst_off = nullptr;
     double* L = nullptr;
 };
@@ -463,7 +482,7 @@ static void free_work(fem_mpnn* m)
 {
     mfree(m->X); mfree(m->A1agg); mfree(m->inv_deg); mfree(m->pre1); mfree(m->a2); mfree(m->pre2);
     mfree(m->z); mfree(m->dz); mfree(m->dpre2); mfree(m->dh1s); mfree(m->da2s); mfree(m->dpre1);
-    mfree(m->y); mfree(m->inst_of); mfree(m->inst_off); mfree(m->L);
+    mfree(m->state); mfree(m->y); mfree(m->inst_of); mfree(m->inst_off); mfree(m->L);
     m->cap = 0;
     m->cap_inst = 0;
 }
@@ -485,10 +504,11 @@ static fem_status ensure_work(fem_mpnn* m, size_t n, size_t n_inst)
     MCHK(hipMalloc(&m->dh1s, c * HID * 4));
     MCHK(hipMalloc(&m->da2s, c * HID * 4));
     MCHK(hipMalloc(&m->dpre1, c * HID * 4));
+    MCHK(hipMalloc(&m->state, c * 4));
     MCHK(hipMalloc(&m->y, c * 4));
     MCHK(hipMalloc(&m->inst_of, c * 4));
     MCHK(hipMalloc(&m->inst_off, (ci + 1) * 4));
-    MCHK(hipMalloc(&m->L, ci * 2 * 8));
+    MCHK(hipMalloc(&m->L, ci * 8));
     m->cap = n;
     m->cap_inst = n_inst;
     return FEM_OK;
@@ -502,15 +522,18 @@ static int grid_rows(int32_t n, int waves_per_block)
     return (int)(blocks > 0 ? blocks : 1);
 }
 
-// forward for one draw: z (and, with train, the activations kept for backward)
-static fem_status forward(fem_mpnn* m, const Problem& p, uint64_t seed, int32_t draw, bool train, hipStream_t st)
+// forward for one replica state (device, state[i * stride]) and draw: z (and,
+// with train, the activations kept for backward)
+static fem_status forward(fem_mpnn* m, const Problem& p, const float* state, int64_t stride, uint64_t seed,
+                          int32_t draw, bool train, hipStream_t st)
 {
     const int32_t n = p.n;
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     (void)hipGetLastError();
-    feat_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, p.row_off, p.adj, k0, k1, (uint32_t)draw, m->X, m->inv_deg);
+    feat_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, p.row_off, p.adj, state, stride, k0, k1, (uint32_t)draw, m->X,
+                                                 m->inv_deg);
     layer1_kernel<<<grid_rows(n, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->X, m->inv_deg, m->wbf, m->A1agg, m->pre1);
-    layer2_kernel<<<grid_rows(n, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->inv_deg, m->wbf, m->pre1,
+    layer2_kernel<<<grid_rows((n + L2_NB - 1) / L2_NB, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->inv_deg, m->wbf, m->pre1,
                                                    train ? m->a2 : nullptr, train ? m->pre2 : nullptr, m->z);
     MCHK(hipGetLastError());
     return FEM_OK;
@@ -578,25 +601,31 @@ fem_status fem_mpnn_set_params(fem_mpnn* m, const float* theta)
     return FEM_OK;
 }
 
-fem_status fem_mpnn_forward(fem_mpnn* m, const fem_problem* fp, uint64_t seed, int32_t draw, float* z, int on_device)
+fem_status fem_mpnn_forward(fem_mpnn* m, const fem_problem* fp, const float* state, uint64_t seed, int32_t draw,
+                            float* z, int on_device)
 {
-    if (!m || !fp || !z) return mfail(FEM_E_INVAL, "NULL argument");
+    if (!m || !fp || !state || !z) return mfail(FEM_E_INVAL, "NULL argument");
     const Problem& p = fp->p;
     if (p.kind != KIND_MAXCUT) return mfail(FEM_E_UNSUPPORTED, "the warm-start network is for MaxCut problems");
     if (draw < 0) return mfail(FEM_E_INVAL, "draw must be >= 0");
     MCHK(hipSetDevice(m->device));
     fem_status s = ensure_work(m, (size_t)p.n, (size_t)p.n_inst);
     if (s != FEM_OK) return s;
-    s = forward(m, p, seed, draw, false, nullptr);
+    const float* st = state;
+    if (!on_device) {
+        MCHK(hipMemcpy(m->state, state, (size_t)p.n * 4, hipMemcpyHostToDevice));
+        st = m->state;
+    }
+    s = forward(m, p, st, 1, seed, draw, false, nullptr);
     if (s != FEM_OK) return s;
     MCHK(hipMemcpy(z, m->z, (size_t)p.n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     return FEM_OK;
 }
 
-fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* fp, const int32_t* labels, uint64_t seed,
-                               int32_t draw0, double lr, double* loss, float* grad_out)
+fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* fp, const float* state, const int32_t* labels,
+                               uint64_t seed, int32_t draw0, double lr, double* loss, float* grad_out)
 {
-    if (!m || !fp || !labels) return mfail(FEM_E_INVAL, "NULL argument");
+    if (!m || !fp || !state || !labels) return mfail(FEM_E_INVAL, "NULL argument");
     const Problem& p = fp->p;
     if (p.kind != KIND_MAXCUT) return mfail(FEM_E_UNSUPPORTED, "the warm-start network is for MaxCut problems");
     if (!(lr > 0.0) || draw0 < 0) return mfail(FEM_E_INVAL, "need lr > 0 and draw0 >= 0");
@@ -609,18 +638,17 @@ fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* fp, const int32_t
     std::vector<int32_t> inst_of((size_t)n);
     for (int32_t b = 0; b < B; ++b)
         for (int32_t i = p.inst_off[(size_t)b]; i < p.inst_off[(size_t)b + 1]; ++i) inst_of[(size_t)i] = b;
+    MCHK(hipMemcpy(m->state, state, (size_t)n * 4, hipMemcpyHostToDevice));
     MCHK(hipMemcpy(m->y, labels, (size_t)n * 4, hipMemcpyHostToDevice));
     MCHK(hipMemcpy(m->inst_of, inst_of.data(), (size_t)n * 4, hipMemcpyHostToDevice));
     MCHK(hipMemcpy(m->inst_off, p.inst_off.data(), (size_t)(B + 1) * 4, hipMemcpyHostToDevice));
-    // every instance of the batch uses draw draw0 + (its index); the features
-    // are keyed by the node's index in the batch and that draw: one forward per
-    // distinct draw would be wasteful, so a single forward with draw0 serves all
-    // instances (the counter holds the global node index, distinct per node).
-    s = forward(m, p, seed, draw0, true, nullptr);
+    // one forward over the union: the random features are keyed by the node's
+    // index in the batch and the draw
+    s = forward(m, p, m->state, 1, seed, draw0, true, nullptr);
     if (s != FEM_OK) return s;
     (void)hipGetLastError();
     loss_kernel<<<B, 256>>>(m->inst_off, m->z, m->y, m->L);
-    dz_kernel<<<(n + 255) / 256, 256>>>(n, m->inst_of, m->inst_off, B, m->L, m->z, m->y, m->dz);
+    dz_kernel<<<(n + 255) / 256, 256>>>(n, m->inst_of, m->inst_off, B, m->z, m->y, m->dz);
     back2_kernel<<<grid_rows(n, 4), 256>>>(n, m->inv_deg, m->wbf, m->dz, m->pre2, m->dpre2, m->dh1s, m->da2s);
     back1_kernel<<<grid_rows(n, 4), 256>>>(n, p.row_off, p.adj, m->pre1, m->dh1s, m->da2s, m->dpre1);
     WgradArgs wa{n, m->X, m->A1agg, m->pre1, m->a2, m->pre2, m->dz, m->dpre2, m->dpre1, m->part};
@@ -628,10 +656,10 @@ fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* fp, const int32_t
     wgrad_reduce_kernel<<<(NP + 255) / 256, 256>>>(WG_BLOCKS, m->part, m->grad);
     MCHK(hipGetLastError());
     // loss on the host from the per-instance values
-    std::vector<double> L((size_t)2 * B);
+    std::vector<double> L((size_t)B);
     MCHK(hipMemcpy(L.data(), m->L, L.size() * 8, hipMemcpyDeviceToHost));
     double tot = 0.0;
-    for (int32_t b = 0; b < B; ++b) tot += std::min(L[(size_t)2 * b], L[(size_t)2 * b + 1]) / B;
+    for (int32_t b = 0; b < B; ++b) tot += L[(size_t)b] / B;
     if (loss) *loss = tot;
     if (grad_out) MCHK(hipMemcpy(grad_out, m->grad, NP * 4, hipMemcpyDeviceToHost));
     // Adam on the master weights (torch.optim.Adam defaults 0.9 / 0.999 / 1e-8)
@@ -646,37 +674,44 @@ fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* fp, const int32_t
     return FEM_OK;
 }
 
-fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, uint64_t seed, int32_t n_draws, float alpha,
-                          float* h0, int on_device)
+fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, const float* state, uint64_t seed,
+                          float alpha, float* h_out, int on_device)
 {
-    if (!m || !fp || !h0) return mfail(FEM_E_INVAL, "NULL argument");
+    if (!m || !fp || !state || !h_out) return mfail(FEM_E_INVAL, "NULL argument");
     const Problem& p = fp->p;
     if (p.kind != KIND_MAXCUT) return mfail(FEM_E_UNSUPPORTED, "the warm-start network is for MaxCut problems");
-    if (R < 1 || n_draws < 1 || n_draws > R) return mfail(FEM_E_INVAL, "need 1 <= n_draws <= R");
+    if (R < 1) return mfail(FEM_E_INVAL, "need R >= 1");
     MCHK(hipSetDevice(m->device));
     fem_status s = ensure_work(m, (size_t)p.n, (size_t)p.n_inst);
     if (s != FEM_OK) return s;
-    float* dst = h0;
+    const size_t bytes = (size_t)p.n * R * 4;
+    const float* src = state;
+    float* dst = h_out;
     float* tmp = nullptr;
     if (!on_device) {
-        MCHK(hipMalloc(&tmp, (size_t)p.n * R * 4));
-        dst = tmp;
+        MCHK(hipMalloc(&tmp, 2 * bytes));
+        hipError_t e = hipMemcpy(tmp, state, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return mfail(FEM_E_HIP, "copy of the state", e);
+        }
+        src = tmp;
+        dst = tmp + (size_t)p.n * R;
     }
-    for (int32_t d = 0; d < n_draws && s == FEM_OK; ++d) {
-        s = forward(m, p, seed, d, false, nullptr);
+    for (int32_t r = 0; r < R && s == FEM_OK; ++r) {
+        s = forward(m, p, src + r, R, seed, r, false, nullptr);
         if (s != FEM_OK) break;
-        const size_t count = (size_t)p.n * ((R - d + n_draws - 1) / n_draws);
-        const int blocks = (int)std::min<size_t>((count + 255) / 256, 65536);
-        write_h0_kernel<<<blocks > 0 ? blocks : 1, 256>>>(p.n, R, n_draws, d, alpha, m->z, dst);
+        const int blocks = (int)std::min<int64_t>(((int64_t)p.n + 255) / 256, 65536);
+        write_col_kernel<<<blocks > 0 ? blocks : 1, 256>>>(p.n, R, r, alpha, m->z, dst);
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) s = mfail(FEM_E_HIP, "write_h0_kernel", e);
+        if (e != hipSuccess) s = mfail(FEM_E_HIP, "write_col_kernel", e);
     }
     hipError_t e = hipDeviceSynchronize();
     if (s == FEM_OK && e != hipSuccess) s = mfail(FEM_E_HIP, "fem_mpnn_infer", e);
     if (tmp) {
         if (s == FEM_OK) {
-            e = hipMemcpy(h0, tmp, (size_t)p.n * R * 4, hipMemcpyDeviceToHost);
-            if (e != hipSuccess) s = mfail(FEM_E_HIP, "copy of h0", e);
+            e = hipMemcpy(h_out, dst, bytes, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) s = mfail(FEM_E_HIP, "copy of the proposal", e);
         }
         (void)hipFree(tmp);
     }

@@ -98,9 +98,9 @@ _SIGS = {
     "fem_mpnn_destroy": (None, [_P]),
     "fem_mpnn_get_params": (C.c_int, [_P, _P]),
     "fem_mpnn_set_params": (C.c_int, [_P, _P]),
-    "fem_mpnn_forward": (C.c_int, [_P, _P, C.c_uint64, C.c_int32, _P, C.c_int]),
-    "fem_mpnn_train_step": (C.c_int, [_P, _P, _P, C.c_uint64, C.c_int32, C.c_double, _P, _P]),
-    "fem_mpnn_infer": (C.c_int, [_P, _P, C.c_int32, C.c_uint64, C.c_int32, C.c_float, _P, C.c_int]),
+    "fem_mpnn_forward": (C.c_int, [_P, _P, _P, C.c_uint64, C.c_int32, _P, C.c_int]),
+    "fem_mpnn_train_step": (C.c_int, [_P, _P, _P, _P, C.c_uint64, C.c_int32, C.c_double, _P, _P]),
+    "fem_mpnn_infer": (C.c_int, [_P, _P, C.c_int32, _P, C.c_uint64, C.c_float, _P, C.c_int]),
     "fem_mpnn_save": (C.c_int, [_P, C.c_char_p]),
     "fem_mpnn_load": (C.c_int, [_P, C.c_char_p]),
     "fem_profile": (C.c_int, [_P, C.c_int32]),
@@ -420,27 +420,40 @@ class MPNN:
         th, pt = _host(theta, np.float32)
         _check(lib().fem_mpnn_set_params(self._h, pt))
 
-    def forward(self, problem: Problem, seed: int, draw: int):
+    def forward(self, problem: Problem, state, seed: int, draw: int):
+        """Logits z [n] for one replica's fields state [n] (host)."""
+        st, ps = _host(state, np.float32)
+        assert st.size == problem.n
         z = np.empty(problem.n, dtype=np.float32)
-        _check(lib().fem_mpnn_forward(self._h, problem._h, seed, draw, z.ctypes.data_as(C.c_void_p), 0))
+        _check(lib().fem_mpnn_forward(self._h, problem._h, ps, seed, draw, z.ctypes.data_as(C.c_void_p), 0))
         return z
 
-    def train_step(self, batch: Problem, labels, seed: int, draw0: int, lr: float, want_grad=False):
+    def train_step(self, batch: Problem, state, labels, seed: int, draw0: int, lr: float, want_grad=False):
+        st, ps = _host(state, np.float32)
         lab, pl = _host(labels, np.int32)
+        assert st.size == batch.n and lab.size == batch.n
         loss = C.c_double()
         g = np.empty(N_MPNN_PARAMS, dtype=np.float32) if want_grad else None
-        _check(lib().fem_mpnn_train_step(self._h, batch._h, pl, seed, draw0, lr, C.byref(loss),
+        _check(lib().fem_mpnn_train_step(self._h, batch._h, ps, pl, seed, draw0, lr, C.byref(loss),
                                          None if g is None else g.ctypes.data_as(C.c_void_p)))
         return (loss.value, g) if want_grad else loss.value
 
-    def infer(self, problem: Problem, R: int, seed: int, n_draws: int, alpha: float, out=None):
-        """h0 [n][R]: host array, or written into the device tensor `out`."""
-        if out is not None and _is_torch(out) and out.is_cuda:
-            _check(lib().fem_mpnn_infer(self._h, problem._h, R, seed, n_draws, alpha, C.c_void_p(out.data_ptr()), 1))
+    def infer(self, problem: Problem, state, seed: int, alpha: float, out=None):
+        """Proposal alpha * z for every replica of state [n][R] (host array,
+        or a device tensor together with a device tensor `out`)."""
+        if _is_torch(state) and state.is_cuda:
+            assert out is not None and _is_torch(out) and out.is_cuda
+            assert state.is_contiguous() and out.is_contiguous() and state.dtype == out.dtype
+            R = state.shape[1]
+            _check(lib().fem_mpnn_infer(self._h, problem._h, R, C.c_void_p(state.data_ptr()), seed, alpha,
+                                        C.c_void_p(out.data_ptr()), 1))
             return out
-        h0 = np.empty((problem.n, R), dtype=np.float32)
-        _check(lib().fem_mpnn_infer(self._h, problem._h, R, seed, n_draws, alpha, h0.ctypes.data_as(C.c_void_p), 0))
-        return h0
+        st, ps = _host(state, np.float32)
+        st = st.reshape(problem.n, -1)
+        h = np.empty_like(st)
+        _check(lib().fem_mpnn_infer(self._h, problem._h, st.shape[1], ps, seed, alpha, h.ctypes.data_as(C.c_void_p),
+                                    0))
+        return h
 
     def save(self, path):
         _check(lib().fem_mpnn_save(self._h, str(path).encode()))

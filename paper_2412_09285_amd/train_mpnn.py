@@ -1,13 +1,15 @@
-"""Train the MaxCut warm-start network on solutions that FEM itself produces.
+"""Train the MaxCut warm-start network on FEM's own runs.
 
 1. Draw the training instances of the batched MaxCut recipe (seeds 60000 + j,
    N log-uniform in [1000, 50000], even j random 3-regular, odd j G(n, 5n),
    +/-1 weights).
-2. Label them with plain FEM (float32, random h0 ~ N(0, 0.01^2), R replicas,
-   a linear beta anneal), run as block-diagonal batches on the GPU; the label
-   of an instance is its best replica's configuration.
+2. Run plain FEM on them (float32, random h0 ~ N(0, 0.01^2), R replicas, the
+   linear beta anneal 0.01 -> 5 over T steps, Adam lr 0.1) as block-diagonal
+   batches on the GPU; keep, for the first `keep` replicas, the fields after
+   T_early steps (the network's input) and the final read-out (its label).
 3. Train with fem_mpnn_train_step (hand-written forward, backward and Adam
-   kernels) on minibatches of instances, one fresh feature draw per step.
+   kernels) on minibatches of instances, each with one of its kept replicas,
+   one fresh feature draw per step.
 4. Save the parameters (fem_mpnn_save).
 
 Usage: python -m paper_2412_09285_amd.train_mpnn --out PATH [--instances 2000]
@@ -42,9 +44,12 @@ def make_instances(count, seed0=TRAIN_SEED0):
     return [W.batch_instance(j, seed0=seed0) for j in range(count)]
 
 
-def fem_labels(graphs, R=32, T=1000, group_nodes=3_000_000, stream=None):
+T_PLAIN, T_EARLY = 1000, 100
+
+
+def fem_runs(graphs, R=32, T=T_PLAIN, t_early=T_EARLY, keep=8, group_nodes=3_000_000, stream=None):
     """Plain FEM on block-diagonal groups of instances; returns per instance
-    (best cut, best configuration as 0/1)."""
+    (fields at t_early [n][keep] float32, final read-out [n][keep] int32)."""
     out = []
     k = 0
     while k < len(graphs):
@@ -59,18 +64,21 @@ def fem_labels(graphs, R=32, T=1000, group_nodes=3_000_000, stream=None):
         s = fem.Solver(batch, fem.default_params(replicas=R, steps=T, energy_every=0), stream=stream)
         h0 = np.concatenate([W.initial_fields(g.n, R, seed=1_000_000 + g.meta["seed"]) for g in grp])
         s.set_fields(h0)
-        s.run()
-        rep, val, sig = s.best()
+        s.step(t_early)
+        early = s.fields()[:, :keep].copy()
+        s.step(T - t_early)
+        final = s.round()[:keep].T.astype(np.int32)      # [n][keep]
         offs = batch.instance_offsets()
         for b in range(len(grp)):
-            out.append((int(val[b]), sig[offs[b]:offs[b + 1]].astype(np.int32)))
+            out.append((early[offs[b]:offs[b + 1]], final[offs[b]:offs[b + 1]]))
         s.close()
     return out
 
 
-def train(graphs, labels, epochs=12, batch_instances=40, lr=2e-3, seed=7, init_seed=1, log_every=20):
+def train(graphs, runs, epochs=12, batch_instances=40, lr=2e-3, seed=7, init_seed=1, log_every=20):
     net = fem.MPNN(W.mpnn_init_weights(init_seed))
     order_rng = np.random.default_rng(seed)
+    keep = runs[0][0].shape[1]
     history = []
     step = 0
     for ep in range(epochs):
@@ -78,10 +86,12 @@ def train(graphs, labels, epochs=12, batch_instances=40, lr=2e-3, seed=7, init_s
         ep_loss = []
         for s0 in range(0, len(perm), batch_instances):
             idx = perm[s0:s0 + batch_instances]
+            reps = order_rng.integers(0, keep, size=len(idx))
             parts = [fem.Problem.maxcut(graphs[j].n, graphs[j].u, graphs[j].v, graphs[j].w) for j in idx]
             batch = fem.Problem.batch(parts)
-            y = np.concatenate([labels[j] for j in idx])
-            loss = net.train_step(batch, y, seed=seed + 1000 * ep, draw0=step, lr=lr)
+            st = np.concatenate([runs[j][0][:, r] for j, r in zip(idx, reps)])
+            y = np.concatenate([runs[j][1][:, r] for j, r in zip(idx, reps)])
+            loss = net.train_step(batch, st, y, seed=seed + 1000 * ep, draw0=step, lr=lr)
             ep_loss.append(loss)
             step += 1
             if step % log_every == 0:
@@ -96,7 +106,8 @@ def main():
     ap.add_argument("--out", default=DEFAULT_PARAMS)
     ap.add_argument("--instances", type=int, default=2000)
     ap.add_argument("--epochs", type=int, default=12)
-    ap.add_argument("--label-steps", type=int, default=1000)
+    ap.add_argument("--label-steps", type=int, default=T_PLAIN)
+    ap.add_argument("--early-steps", type=int, default=T_EARLY)
     ap.add_argument("--replicas", type=int, default=32)
     args = ap.parse_args()
     import torch
@@ -107,11 +118,11 @@ def main():
     graphs = make_instances(args.instances)
     log(f"generated {len(graphs)} instances, {sum(g.n for g in graphs)} nodes, {time.time() - t0:.1f} s")
     t1 = time.time()
-    lab = fem_labels(graphs, R=args.replicas, T=args.label_steps, stream=stream)
+    runs = fem_runs(graphs, R=args.replicas, T=args.label_steps, t_early=args.early_steps, stream=stream)
     torch.cuda.synchronize()
-    log(f"labelled with plain FEM in {time.time() - t1:.1f} s")
+    log(f"ran plain FEM on the training set in {time.time() - t1:.1f} s")
     t2 = time.time()
-    net, hist = train(graphs, [l for _, l in lab], epochs=args.epochs)
+    net, hist = train(graphs, runs, epochs=args.epochs)
     log(f"trained in {time.time() - t2:.1f} s")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     net.save(args.out)

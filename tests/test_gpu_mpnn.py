@@ -1,6 +1,6 @@
 """GPU parity of the warm-start network's forward pass, backward pass and
 Adam step against the FP64 reference (oracle/mpnn.py), through the C ABI;
-parameter files; the layout of the proposed initial fields; and that a few
+parameter files; the layout of the proposal for every replica; and that a few
 training steps lower the loss."""
 import numpy as np
 import pytest
@@ -23,13 +23,22 @@ def small_batch(sizes=(300, 517, 1000), seed0=70_000):
     return graphs, off, M.GraphOps(int(off[-1]), u, v, w), fem.Problem.batch(parts)
 
 
+def state_of(n, seed, R=None):
+    """Fields shaped like a replica part-way through an anneal (|h| ~ 1, some
+    beyond the clamp at 8)."""
+    rng = np.random.default_rng(seed)
+    shape = (n,) if R is None else (n, R)
+    return (rng.standard_t(3, size=shape) * 1.5).astype(np.float32)
+
+
 def test_forward_matches_reference():
     _, off, ops, batch = small_batch()
     theta = W.mpnn_init_weights(5)
     net = fem.MPNN(theta)
+    st = state_of(batch.n, 1)
     for draw in (0, 3):
-        z = net.forward(batch, seed=1234, draw=draw).astype(np.float64)
-        zr = M.forward(ops, theta, 1234, draw)["z"]
+        z = net.forward(batch, st, seed=1234, draw=draw).astype(np.float64)
+        zr = M.forward(ops, theta, st, 1234, draw)["z"]
         err = np.abs(z - zr).max() / np.abs(zr).max()
         assert err <= 1e-5, err
     print(f"[mpnn forward] max rel err {err:.2e}", flush=True)
@@ -38,11 +47,12 @@ def test_forward_matches_reference():
 def test_train_step_gradient_and_adam_match_reference():
     _, off, ops, batch = small_batch()
     theta = W.mpnn_init_weights(6)
+    st = state_of(batch.n, 2)
     y = np.random.default_rng(2).integers(0, 2, size=int(off[-1])).astype(np.int32)
     net = fem.MPNN(theta)
     lr = 1e-3
-    loss, g = net.train_step(batch, y, seed=99, draw0=4, lr=lr, want_grad=True)
-    Lr, gr, _ = M.batch_loss_and_grad(ops, off, y, theta, 99, 4)
+    loss, g = net.train_step(batch, st, y, seed=99, draw0=4, lr=lr, want_grad=True)
+    Lr, gr, _ = M.batch_loss_and_grad(ops, off, st, y, theta, 99, 4)
     assert loss == pytest.approx(Lr, rel=1e-5)
     rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
     mx = np.abs(g - gr).max() / np.abs(gr).max()
@@ -70,22 +80,35 @@ def test_save_load_and_infer_layout(tmp_path):
     other = fem.MPNN(np.zeros_like(theta))
     other.load(p)
     assert np.array_equal(other.params(), theta)
-    R, D, alpha = 6, 4, 0.5
-    h0 = other.infer(batch, R=R, seed=5, n_draws=D, alpha=alpha)
-    for d in range(D):
-        z = other.forward(batch, seed=5, draw=d)
-        for r in range(d, R, D):
-            assert np.array_equal(h0[:, r], np.float32(alpha) * z)
+    R, alpha = 5, 0.5
+    st = state_of(batch.n, 3, R)
+    h = other.infer(batch, st, seed=5, alpha=alpha)
+    for r in range(R):
+        z = other.forward(batch, st[:, r], seed=5, draw=r)
+        assert np.array_equal(h[:, r], np.float32(alpha) * z)
+
+
+def test_infer_on_device_tensors():
+    import torch
+
+    _, off, ops, batch = small_batch((250, 400))
+    net = fem.MPNN(W.mpnn_init_weights(12))
+    st = state_of(batch.n, 4, 6)
+    host = net.infer(batch, st, seed=9, alpha=1.5)
+    dst = torch.from_numpy(st).cuda()
+    out = torch.empty_like(dst)
+    net.infer(batch, dst, seed=9, alpha=1.5, out=out)
+    assert np.array_equal(out.cpu().numpy(), host)
 
 
 def test_training_lowers_the_loss():
     _, off, ops, batch = small_batch((600, 800, 1000, 700))
-    # labels: a fixed cut of each instance (the alternating-by-index split is
-    # learnable only through the random features, so use the degree parity)
-    y = (np.arange(int(off[-1])) % 2).astype(np.int32)
+    st = state_of(batch.n, 5)
+    # a label the features determine: the read-out of the state itself
+    y = (st > 0).astype(np.int32)
     net = fem.MPNN(W.mpnn_init_weights(9))
-    first = net.train_step(batch, y, seed=1, draw0=0, lr=3e-3)
+    first = net.train_step(batch, st, y, seed=1, draw0=0, lr=3e-3)
     for it in range(60):
-        last = net.train_step(batch, y, seed=1, draw0=0, lr=3e-3)
-    assert last < first
+        last = net.train_step(batch, st, y, seed=1, draw0=0, lr=3e-3)
+    assert last < 0.5 * first
     print(f"[mpnn train] loss {first:.4f} -> {last:.4f}", flush=True)
