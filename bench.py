@@ -152,11 +152,17 @@ def main():
         n = 1 << 28   # 1 GiB of float32
         x = torch.ones(n, device="cuda")
         y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             y.copy_(x)
+        e1.record()
         torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
         print(json.dumps({"workload": "copy", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
-                          "copies": 5}))
+                          "copies": 6, "ms_per_copy": ms, "read_plus_write_GBps": 8 * n / (ms * 1e-3) / 1e9}))
         return
     if args.workload == "batch512":
         from paper_2412_09285_amd import batchbench

@@ -109,18 +109,26 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_manip
     }
 }
 
-// sign bits of the fields: one thread per word
+// sign bits of the fields: each half-wave forms one 32-bit word from 32
+// coalesced loads and a ballot
 __global__ void sign_bits_kernel(const float* __restrict__ h, int32_t n, int32_t R, int32_t rw,
                                  uint32_t* __restrict__ out)
 {
-    const size_t count = (size_t)n * rw;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
-        const size_t i = k / rw;
-        const int w = (int)(k % rw);
-        const int r0 = 32 * w, r1 = (r0 + 32 < R) ? r0 + 32 : R;
-        uint32_t bits = 0;
-        for (int r = r0; r < r1; ++r) bits |= (h[i * R + r] > 0.0f ? 1u : 0u) << (r - r0);
-        out[k] = bits;
+    const size_t words = (size_t)n * rw;
+    const int lane = threadIdx.x & 63;
+    const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
+    for (size_t p = 2 * wave; p < words; p += 2 * nwaves) {
+        const size_t k = p + (size_t)(lane >> 5);
+        bool bit = false;
+        if (k < words) {
+            const size_t i = k / rw;
+            const int r = 32 * (int)(k % rw) + (lane & 31);
+            bit = r < R && h[i * R + r] > 0.0f;
+        }
+        const uint64_t m = __ballot(bit);
+        if (lane == 0) out[p] = (uint32_t)m;
+        if (lane == 32 && p + 1 < words) out[p + 1] = (uint32_t)(m >> 32);
     }
 }
 
@@ -309,9 +317,9 @@ hipError_t launch_manip_init(int kind, const LaunchGeom& geo, int waves, const S
 {
     (void)hipGetLastError();   // drop stale errors of earlier calls
     if (kind == KIND_MAXCUT) {
-        const size_t count = (size_t)a.n * a.rw;
+        const size_t count = (size_t)a.n * a.rw;   // words, two per wave
         if (count == 0) return hipSuccess;
-        const size_t blocks = (count + 255) / 256;
+        const size_t blocks = (count + 7) / 8;
         sign_bits_kernel<<<(unsigned)(blocks < 65536 ? blocks : 65536), 256, 0, st>>>(
             a.h, a.n, a.R, a.rw, static_cast<uint32_t*>(a.marg_nxt));
         return hipGetLastError();

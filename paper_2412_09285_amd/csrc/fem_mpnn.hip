@@ -118,13 +118,19 @@ __global__ void feat_kernel(int32_t n, const int64_t* __restrict__ row_off, cons
     }
 }
 
-// one wave per node, lane = hidden unit
+// A wave takes L1_NB = 8 nodes at a time.  Gather: lane 8q + c aggregates
+// feature c of node q (four neighbour rows in flight); the nodes' [x | a(x)]
+// are staged in the wave's LDS slice.  Dense part: lane j owns hidden unit j
+// (its 16 weights in registers) and reads the staged inputs as broadcasts.
+constexpr int L1_NB = 8;
 __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* __restrict__ row_off,
                                                      const int2* __restrict__ adj, const float* __restrict__ X,
                                                      const float* __restrict__ inv_deg, const uint16_t* __restrict__ w,
                                                      float* __restrict__ A1agg, float* __restrict__ pre1)
 {
+    __shared__ float4 sxa[4][L1_NB][2 * D_IN / 4];   // per wave: L1_NB nodes x [x | a(x)]
     const int lane = threadIdx.x & 63;
+    const int wl = threadIdx.x >> 6;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
     float colA[D_IN], colB[D_IN];
@@ -134,22 +140,48 @@ __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* _
         colB[k] = bf(w[OFF_B1 + k * HID + lane]);
     }
     const float bias = bf(w[OFF_b1 + lane]);
-    for (int i = wave; i < n; i += nw) {
-        float a = 0.0f;   // lanes 0..7: component lane of the aggregate
-        if (lane < D_IN)
-            for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
-                const int2 e = adj[k];
-                a = fmaf(__int_as_float(e.y), X[(size_t)e.x * D_IN + lane], a);
+    float* sf = reinterpret_cast<float*>(&sxa[wl][0][0]);
+    const int q = lane >> 3, c = lane & 7;
+    for (int i0 = wave * L1_NB; i0 < n; i0 += nw * L1_NB) {
+        const int i = i0 + q;
+        if (i < n) {
+            float a = 0.0f;
+            int64_t k = row_off[i];
+            const int64_t kend = row_off[i + 1];
+            for (; k + 4 <= kend; k += 4) {
+                const int2 e0 = adj[k], e1 = adj[k + 1], e2 = adj[k + 2], e3 = adj[k + 3];
+                const float v0 = X[(size_t)e0.x * D_IN + c], v1 = X[(size_t)e1.x * D_IN + c];
+                const float v2 = X[(size_t)e2.x * D_IN + c], v3 = X[(size_t)e3.x * D_IN + c];
+                a = fmaf(__int_as_float(e0.y), v0, a);
+                a = fmaf(__int_as_float(e1.y), v1, a);
+                a = fmaf(__int_as_float(e2.y), v2, a);
+                a = fmaf(__int_as_float(e3.y), v3, a);
             }
-        a *= inv_deg[i];
-        const float xi = lane < D_IN ? X[(size_t)i * D_IN + lane] : 0.0f;
-        float acc = bias;
-#pragma unroll
-        for (int k = 0; k < D_IN; ++k) acc = fmaf(lane_val(xi, k), colA[k], acc);
-#pragma unroll
-        for (int k = 0; k < D_IN; ++k) acc = fmaf(lane_val(a, k), colB[k], acc);
-        pre1[(size_t)i * HID + lane] = acc;
-        if (lane < D_IN) A1agg[(size_t)i * D_IN + lane] = a;
+            for (; k < kend; ++k) {
+                const int2 e = adj[k];
+                a = fmaf(__int_as_float(e.y), X[(size_t)e.x * D_IN + c], a);
+            }
+            a *= inv_deg[i];
+            sf[q * 2 * D_IN + c] = X[(size_t)i * D_IN + c];
+            sf[q * 2 * D_IN + D_IN + c] = a;
+            A1agg[(size_t)i * D_IN + c] = a;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int cnt = (n - i0) < L1_NB ? (n - i0) : L1_NB;
+        for (int qq = 0; qq < cnt; ++qq) {
+            const float4 x0 = sxa[wl][qq][0], x1 = sxa[wl][qq][1], a0 = sxa[wl][qq][2], a1 = sxa[wl][qq][3];
+            float acc = bias;
+            acc = fmaf(x0.x, colA[0], acc); acc = fmaf(x0.y, colA[1], acc);
+            acc = fmaf(x0.z, colA[2], acc); acc = fmaf(x0.w, colA[3], acc);
+            acc = fmaf(x1.x, colA[4], acc); acc = fmaf(x1.y, colA[5], acc);
+            acc = fmaf(x1.z, colA[6], acc); acc = fmaf(x1.w, colA[7], acc);
+            acc = fmaf(a0.x, colB[0], acc); acc = fmaf(a0.y, colB[1], acc);
+            acc = fmaf(a0.z, colB[2], acc); acc = fmaf(a0.w, colB[3], acc);
+            acc = fmaf(a1.x, colB[4], acc); acc = fmaf(a1.y, colB[5], acc);
+            acc = fmaf(a1.z, colB[6], acc); acc = fmaf(a1.w, colB[7], acc);
+            pre1[(size_t)(i0 + qq) * HID + lane] = acc;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -188,7 +220,19 @@ __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* _
             const int i = i0 + q;
             const float h = fmaxf(pre1[(size_t)i * HID + lane], 0.0f);
             float a = 0.0f;
-            for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
+            int64_t k = row_off[i];
+            const int64_t kend = row_off[i + 1];
+            // four neighbour rows in flight at a time (same summation order)
+            for (; k + 4 <= kend; k += 4) {
+                const int2 e0 = adj[k], e1 = adj[k + 1], e2 = adj[k + 2], e3 = adj[k + 3];
+                const float v0 = pre1[(size_t)e0.x * HID + lane], v1 = pre1[(size_t)e1.x * HID + lane];
+                const float v2 = pre1[(size_t)e2.x * HID + lane], v3 = pre1[(size_t)e3.x * HID + lane];
+                a = fmaf(__int_as_float(e0.y), fmaxf(v0, 0.0f), a);
+                a = fmaf(__int_as_float(e1.y), fmaxf(v1, 0.0f), a);
+                a = fmaf(__int_as_float(e2.y), fmaxf(v2, 0.0f), a);
+                a = fmaf(__int_as_float(e3.y), fmaxf(v3, 0.0f), a);
+            }
+            for (; k < kend; ++k) {
                 const int2 e = adj[k];
                 a = fmaf(__int_as_float(e.y), fmaxf(pre1[(size_t)e.x * HID + lane], 0.0f), a);
             }
@@ -310,7 +354,18 @@ __global__ void __launch_bounds__(256) back1_kernel(int32_t n, const int64_t* __
     const int nw = (gridDim.x * blockDim.x) >> 6;
     for (int j = wave; j < n; j += nw) {
         float g = dh1s[(size_t)j * HID + lane];
-        for (int64_t k = row_off[j]; k < row_off[j + 1]; ++k) {
+        int64_t k = row_off[j];
+        const int64_t kend = row_off[j + 1];
+        for (; k + 4 <= kend; k += 4) {
+            const int2 e0 = adj[k], e1 = adj[k + 1], e2 = adj[k + 2], e3 = adj[k + 3];
+            const float v0 = da2s[(size_t)e0.x * HID + lane], v1 = da2s[(size_t)e1.x * HID + lane];
+            const float v2 = da2s[(size_t)e2.x * HID + lane], v3 = da2s[(size_t)e3.x * HID + lane];
+            g = fmaf(__int_as_float(e0.y), v0, g);
+            g = fmaf(__int_as_float(e1.y), v1, g);
+            g = fmaf(__int_as_float(e2.y), v2, g);
+            g = fmaf(__int_as_float(e3.y), v3, g);
+        }
+        for (; k < kend; ++k) {
             const int2 e = adj[k];
             g = fmaf(__int_as_float(e.y), da2s[(size_t)e.x * HID + lane], g);
         }
@@ -532,7 +587,7 @@ static fem_status forward(fem_mpnn* m, const Problem& p, const float* state, int
     (void)hipGetLastError();
     feat_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, p.row_off, p.adj, state, stride, k0, k1, (uint32_t)draw, m->X,
                                                  m->inv_deg);
-    layer1_kernel<<<grid_rows(n, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->X, m->inv_deg, m->wbf, m->A1agg, m->pre1);
+    layer1_kernel<<<grid_rows((n + L1_NB - 1) / L1_NB, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->X, m->inv_deg, m->wbf, m->A1agg, m->pre1);
     layer2_kernel<<<grid_rows((n + L2_NB - 1) / L2_NB, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->inv_deg, m->wbf, m->pre1,
                                                    train ? m->a2 : nullptr, train ? m->pre2 : nullptr, m->z);
     MCHK(hipGetLastError());

@@ -115,6 +115,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build() "
                                "or python paper_2412_09285_amd/build.py")
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system one that libfem links; whichever is loaded first serves the
+        # whole process, and torch cannot use a newer system runtime.  Load
+        # torch first so that both use its runtime, whatever the import order.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
