@@ -112,7 +112,8 @@ def cpu_baseline(graph, R_sample, steps_sample):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000, help="timed steps K (one anneal of K steps)")
+    ap.add_argument("--steps", type=int, default=0,
+                    help="timed steps K (one anneal of K steps; default: the workload's anneal length)")
     ap.add_argument("--warmup", type=int, default=50, help="untimed warm-up steps W")
     ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32")
     ap.add_argument("--gradient", choices=["explicit", "manipulated"], default="explicit")
@@ -120,9 +121,11 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--cpu-replicas", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=150)
-    ap.add_argument("--workload", choices=["maxcut1e5", "batch512", "copy"], default="maxcut1e5",
-                    help="maxcut1e5: the throughput line; batch512: time to target on 512 uneven MaxCut "
-                         "instances; copy: a plain device copy (calibrates HBM counters)")
+    ap.add_argument("--workload", choices=["maxcut1e5", "bmincut1e6", "max3sat1e5", "batch512", "copy"],
+                    default="maxcut1e5",
+                    help="maxcut1e5: the throughput line; bmincut1e6 / max3sat1e5: the Potts and Max-3-SAT "
+                         "kernels at full size; batch512: time to target on 512 uneven MaxCut instances; "
+                         "copy: a plain device copy (calibrates HBM counters)")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--plain-steps", type=int, default=1000)
     ap.add_argument("--early-steps", type=int, default=100, help="batch512: plain steps before the proposal")
@@ -176,17 +179,76 @@ def main():
                           "dtype": "f32 fields/Adam + bf16 marginals", "data": "synthetic",
                           "config": dict(workload="batch512_maxcut", **res["config"]), "result": res}))
         return
-    K, Wm = args.steps, args.warmup
-    R = 256
-    log("generating the graph ...")
-    g = W.config_graph(2)
-    h0 = W.initial_fields(g.n, R, seed=102)
+    throughput(args)
+
+
+# The single-GPU throughput workloads: the default line (MaxCut, N = 10^5,
+# R = 256) and the Potts / Max-3-SAT kernels at their full workload sizes.
+WORKLOADS = {
+    "maxcut1e5": dict(kind="maxcut", recipe=2, R=256, seed=102, T=2000,
+                      name="maxcut_sparse_n100000_e300000_pm1", counters="maxcut_n1e5_R256",
+                      data="random sparse graph, uniform endpoints, +/-1 weights"),
+    "bmincut1e6": dict(kind="bmincut", recipe=3, R=16, q=8, lam=1.0, seed=103, T=3000,
+                       name="bmincut_rgg3d_n1000000_deg14_q8", counters="bmincut_rgg1e6_q8_R16",
+                       data="3-D random geometric graph, mean degree 14, unit weights"),
+    "max3sat1e5": dict(kind="maxsat", recipe=4, R=64, seed=104, T=2000,
+                       name="max3sat_n100000_m800000", counters="max3sat_1e5_R64",
+                       data="random 3-SAT, distinct variables, fair signs, ratio 8"),
+}
+
+
+def potts_kernel_bytes(n, R, q, nnz, mbytes, n_tiles):
+    """Algorithmic bytes of one bMinCut launch: h, m1, m2 read and written and
+    the marginal copy read once and written once (24 + 2 b per replica-node-
+    state), the CSR, the weighted degree (4 B per node), and per tile the
+    centred column sums read, the column-sum partials and the three energy
+    partials written (8 B each per replica and state / replica)."""
+    return n * R * q * (24 + 2 * mbytes) + 8 * (n + 1) + 8 * nnz + 4 * n + 8 * R * (2 * q + 3) * n_tiles
+
+
+def sat_kernel_bytes(n, R, nnz, mbytes, n_tiles, rec_bytes=8):
+    """Algorithmic bytes of one Max-k-SAT launch: h, m1, m2 and the marginal
+    copy as for MaxCut, the incidence records (8 B each for 3-SAT), the row
+    offsets and the per-tile energy partials."""
+    return n * R * (24 + 2 * mbytes) + 8 * (n + 1) + rec_bytes * nnz + 16 * R * n_tiles
+
+
+def throughput(args):
+    import numpy as np
+    import torch
+
+    from paper_2412_09285_amd import fem
+    from paper_2412_09285_amd import workloads as W
+
+    wl = WORKLOADS[args.workload]
+    K, Wm = args.steps if args.steps else wl["T"], args.warmup
+    R = wl["R"]
+    kind = wl["kind"]
+    manip = args.gradient == "manipulated"
+    if manip and kind != "maxcut":
+        raise SystemExit("--gradient manipulated is measured on the MaxCut workload")
+    log("generating the workload ...")
+    if kind == "maxsat":
+        cnf = W.config_cnf(wl["recipe"])
+        n, nnz, q = cnf.n_vars, int(cnf.clause_off[-1]), 1
+        prob = fem.Problem.maxsat(cnf.n_vars, cnf.clause_off, cnf.lits, device=0)
+        h0 = W.initial_fields(n, R, seed=wl["seed"])
+    else:
+        g = W.config_graph(wl["recipe"])
+        n, nnz = g.n, g.nnz
+        q = wl.get("q", 1)
+        if kind == "bmincut":
+            prob = fem.Problem.bmincut(g.n, g.u, g.v, g.w, q, device=0)
+            h0 = W.initial_fields(n, R, seed=wl["seed"], q=q)
+        else:
+            prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w, device=0)
+            h0 = W.initial_fields(n, R, seed=wl["seed"])
     dtype = fem.BF16 if args.dtype == "bf16" else fem.F32
-    prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w, device=0)
     stream = torch.cuda.Stream()
     T = max(K, Wm, 1)
-    manip = args.gradient == "manipulated"
     extra = dict(gradient=fem.GRAD_MANIPULATED, energy_every=0) if manip else dict(energy_every=1)
+    if kind == "bmincut":
+        extra["lam"] = wl["lam"]
     s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, marginal_dtype=dtype, **extra), stream=stream)
     s.set_fields(h0)
     tile = s.tile()
@@ -209,35 +271,42 @@ def main():
     dt = time.perf_counter() - t0
     U = s.energies()[0] if not manip else None
     rep, val, _ = s.best()
-    mean_cut = float(np.mean(prob.eval_int(s.round())[0]))
-    updates = g.nnz * R * K
+    ints = prob.eval_int(s.round())[0]
+    updates = nnz * R * K
     value = updates / dt
-    log(f"timed {K} steps in {dt * 1e3:.1f} ms: {value:.3e} updates/s; best cut {val[0]} (replica {rep[0]}), "
-        f"mean cut {mean_cut:.1f}")
+    log(f"timed {K} steps in {dt * 1e3:.1f} ms: {value:.3e} updates/s; best {val[0]} (replica {rep[0]})")
 
     # dominant kernel: the fused step kernel, timed with HIP events on the
     # solver's stream around every launch (eager pass over the same steps)
     s.set_fields(h0)
     s.profile(True)
-    n_prof = min(K, 200)
-    s.step(n_prof)
+    s.step(min(K, 200))
     kern_ms, n_k = s.profile_result()
     s.profile(False)
     vec, waves, rows, nt, lanes = tile
-    n_tiles = -(-g.n // (waves * (64 // lanes) * rows))
+    per_lane = vec if kind != "bmincut" else 1
+    lanes = min(lanes, 64)
+    n_tiles = -(-n // (waves * (64 // lanes) * rows))
     mbytes = 2 if dtype == fem.BF16 else 4
     if manip:
-        alg_bytes = manip_kernel_bytes(g.n, R, g.nnz)
+        alg_bytes = manip_kernel_bytes(n, R, nnz)
         kname, counters = "maxcut_manip_kernel", "maxcut_manip_n1e5_R256_hbm_counters.md"
+    elif kind == "maxcut":
+        alg_bytes = step_kernel_bytes(n, R, nnz, mbytes, n_tiles)
+        kname, counters = "maxcut_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
+    elif kind == "bmincut":
+        alg_bytes = potts_kernel_bytes(n, R, q, nnz, mbytes, n_tiles)
+        kname, counters = "potts_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
     else:
-        alg_bytes = step_kernel_bytes(g.n, R, g.nnz, mbytes, n_tiles)
-        kname, counters = "maxcut_step_kernel", f"maxcut_n1e5_R256_{args.dtype}_hbm_counters.md"
+        alg_bytes = sat_kernel_bytes(n, R, nnz, mbytes, n_tiles)
+        kname, counters = "sat_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = measured_traffic(os.path.join(ROOT, "profiles", counters), args.gradient, tile, args.dtype)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kname, "kernel_avg_ms": round(kern_ms, 5), "kernel_launches": n_k,
             "alg_bytes_per_launch": int(alg_bytes), "kernel_sources_sha256": kernel_sources_sha(args.gradient)}
+    label = {"maxcut": "cut", "bmincut": "2 cut + lambda sum |Pi|(|Pi|-1)", "maxsat": "unsatisfied clauses"}[kind]
     out = {
         "metric": "replica-edge updates/s (nnz*R*steps/s)",
         "value": value,
@@ -250,17 +319,16 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": ("f32+sign-bit-readouts" if manip else "f32" if dtype == fem.F32 else "f32+bf16-marginals"),
-        "data": "synthetic (seeded generator: random sparse graph, uniform endpoints, +/-1 weights)",
-        "config": {"workload": "maxcut_sparse_n100000_e300000_pm1", "n": g.n, "edges": g.n_edges,
-                   "nnz": g.nnz, "replicas": R, "anneal_steps": K, "marginals": args.dtype,
-                   "gradient": args.gradient,
+        "data": f"synthetic (seeded generator: {wl['data']})",
+        "config": {"workload": wl["name"], "n": n, "nnz": nnz, "q": q if kind == "bmincut" else 2,
+                   "replicas": R, "anneal_steps": K, "marginals": args.dtype, "gradient": args.gradient,
                    "schedule": "linear beta 0.01->5, Adam lr 0.1", "tile": list(tile),
                    "parallelism": "single GPU"},
-        "result": {"best_cut": int(val[0]), "mean_cut": mean_cut,
+        "result": {"best": float(val[0]), "best_is": label, "mean_integer": float(np.mean(ints)),
                    "U_mean_final": float(np.mean(U)) if U is not None else None},
         "roofline": roof,
     }
-    if not args.no_cpu:
+    if kind == "maxcut" and not args.no_cpu and not manip:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_replicas, args.cpu_steps)
     print(json.dumps(out), flush=True)
