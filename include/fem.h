@@ -258,8 +258,10 @@ fem_status fem_get_tile(const fem_solver* s, fem_tile* t);
 fem_status fem_set_tile(fem_solver* s, const fem_tile* t);
 /* Autotune: time every valid shape for trial_steps steps (state is restored
  * afterwards), keep the fastest, and cache it on disk under the key (kind, n,
- * nnz, R, q, dtype) in $FEM_TUNE_CACHE (default ~/.cache/femx/tune.txt).
- * use_cache = 1 returns a cached choice without timing. */
+ * nnz, R, q, dtype, instances, energies on/off, gradient mode) in
+ * $FEM_TUNE_CACHE (default ~/.cache/femx/tune.txt).  use_cache = 1 returns a
+ * cached choice without timing: the user's cache first, then the shapes
+ * tuned on an MI355X that ship beside the library (data/tune_mi355x.txt). */
 fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_tile* chosen);
 
 /* Average duration in milliseconds of the step kernel over the last

@@ -4,6 +4,8 @@
 // the tile autotuner.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cerrno>
 #include <cmath>
@@ -1507,6 +1509,39 @@ static std::string tune_cache_path()
     return dir + "/tune.txt";
 }
 
+// Launch shapes tuned on an MI355X and shipped with the library
+// (data/tune_mi355x.txt beside libfem.so), consulted when the user's cache
+// holds no entry for a problem shape.
+static std::string packaged_tune_path()
+{
+    Dl_info info;
+    if (!dladdr(reinterpret_cast<void*>(&fem_tune), &info) || !info.dli_fname) return "";
+    std::string lib = info.dli_fname;
+    const size_t slash = lib.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/data/tune_mi355x.txt";
+}
+
+// last "key vec waves rows nt lanes" line of file path whose key matches
+static bool lookup_tuned(const std::string& path, const std::string& key, TileShape& sh)
+{
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    char line[512], k[256];
+    int v, w, r, ntf, ln;
+    bool found = false;
+    while (std::fgets(line, sizeof line, f))
+        if (std::sscanf(line, "%255s %d %d %d %d %d", k, &v, &w, &r, &ntf, &ln) == 6 && key == k) {
+            sh.vec = v;
+            sh.waves = w;
+            sh.rows = r;
+            sh.nt = ntf;
+            sh.lanes = ln;
+            found = true;
+        }
+    std::fclose(f);
+    return found;
+}
+
 static std::string tune_key(const fem_solver* s)
 {
     char buf[256];
@@ -1524,29 +1559,13 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     HIPCHK(hipSetDevice(s->prob->device));
     const std::string path = tune_cache_path(), key = tune_key(s);
     if (use_cache) {
-        FILE* f = std::fopen(path.c_str(), "r");
-        if (f) {
-            char line[512], k[256];
-            int v, w, r, ntf, ln;
-            bool found = false;
-            TileShape sh;
-            // one "key vec waves rows nt lanes" line per tuning; the last match wins
-            while (std::fgets(line, sizeof line, f))
-                if (std::sscanf(line, "%255s %d %d %d %d %d", k, &v, &w, &r, &ntf, &ln) == 6 && key == k) {
-                    sh.vec = v;
-                    sh.waves = w;
-                    sh.rows = r;
-                    sh.nt = ntf;
-                    sh.lanes = ln;
-                    found = true;
-                }
-            std::fclose(f);
-            if (found && valid_shape(s, sh)) {
-                fem_tile t{sh.vec, sh.waves, sh.rows, sh.nt, sh.lanes};
-                STCHK(fem_set_tile(s, &t));
-                if (chosen) STCHK(fem_get_tile(s, chosen));
-                return FEM_OK;
-            }
+        TileShape sh;
+        if ((lookup_tuned(path, key, sh) && valid_shape(s, sh)) ||
+            (lookup_tuned(packaged_tune_path(), key, sh) && valid_shape(s, sh))) {
+            fem_tile t{sh.vec, sh.waves, sh.rows, sh.nt, sh.lanes};
+            STCHK(fem_set_tile(s, &t));
+            if (chosen) STCHK(fem_get_tile(s, chosen));
+            return FEM_OK;
         }
     }
     // keep a device copy of the state, try every shape from it, restore

@@ -120,8 +120,9 @@ __global__ void feat_kernel(int32_t n, const int64_t* __restrict__ row_off, cons
 
 // A wave takes L1_NB = 8 nodes at a time.  Gather: lane 8q + c aggregates
 // feature c of node q (four neighbour rows in flight); the nodes' [x | a(x)]
-// are staged in the wave's LDS slice.  Dense part: lane j owns hidden unit j
-// (its 16 weights in registers) and reads the staged inputs as broadcasts.
+// are staged in the wave's LDS slice.  Dense part (only when pre1 is kept,
+// for training): lane j owns hidden unit j (its 16 weights in registers) and
+// reads the staged inputs as broadcasts.
 constexpr int L1_NB = 8;
 __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* __restrict__ row_off,
                                                      const int2* __restrict__ adj, const float* __restrict__ X,
@@ -168,7 +169,7 @@ __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* _
         }
         __builtin_amdgcn_wave_barrier();
         const int cnt = (n - i0) < L1_NB ? (n - i0) : L1_NB;
-        for (int qq = 0; qq < cnt; ++qq) {
+        for (int qq = 0; pre1 && qq < cnt; ++qq) {
             const float4 x0 = sxa[wl][qq][0], x1 = sxa[wl][qq][1], a0 = sxa[wl][qq][2], a1 = sxa[wl][qq][3];
             float acc = bias;
             acc = fmaf(x0.x, colA[0], acc); acc = fmaf(x0.y, colA[1], acc);
@@ -185,19 +186,42 @@ __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* _
     }
 }
 
-// Lane j of a wave owns hidden unit j.  [A2; B2] (128 x 64, float) sits in
-// LDS, shared by the workgroup; a wave takes L2_NB nodes at a time, gathers
-// their H1 rows and aggregates a2 (coalesced 256-byte rows), stages the
-// L2_NB x [H1 | a2] inputs in its own LDS slice, and then for every k reads
-// one weight per lane (a conflict-free 256-byte row) and the nodes' inputs as
-// broadcasts, so each weight read feeds L2_NB FMAs.  The sum over k runs in
-// the same order (0..63 of H1, then 0..63 of a2) as a single-node evaluation.
+// H1 of node j from its 16 inputs [x_j | a(x)_j], for hidden unit `lane`,
+// in the same operation order as layer1_kernel (bit-identical results)
+__device__ __forceinline__ float h1_unit(const float* __restrict__ X, const float* __restrict__ A1agg, int64_t j,
+                                         const float (&colA)[D_IN], const float (&colB)[D_IN], float bias)
+{
+    const float4 x0 = reinterpret_cast<const float4*>(X + j * D_IN)[0];
+    const float4 x1 = reinterpret_cast<const float4*>(X + j * D_IN)[1];
+    const float4 a0 = reinterpret_cast<const float4*>(A1agg + j * D_IN)[0];
+    const float4 a1 = reinterpret_cast<const float4*>(A1agg + j * D_IN)[1];
+    float acc = bias;
+    acc = fmaf(x0.x, colA[0], acc); acc = fmaf(x0.y, colA[1], acc);
+    acc = fmaf(x0.z, colA[2], acc); acc = fmaf(x0.w, colA[3], acc);
+    acc = fmaf(x1.x, colA[4], acc); acc = fmaf(x1.y, colA[5], acc);
+    acc = fmaf(x1.z, colA[6], acc); acc = fmaf(x1.w, colA[7], acc);
+    acc = fmaf(a0.x, colB[0], acc); acc = fmaf(a0.y, colB[1], acc);
+    acc = fmaf(a0.z, colB[2], acc); acc = fmaf(a0.w, colB[3], acc);
+    acc = fmaf(a1.x, colB[4], acc); acc = fmaf(a1.y, colB[5], acc);
+    acc = fmaf(a1.z, colB[6], acc); acc = fmaf(a1.w, colB[7], acc);
+    return fmaxf(acc, 0.0f);
+}
+
+// Lane j of a wave owns hidden unit j.  The aggregate a(H1) is formed from
+// the neighbours' 16 layer-1 inputs [x | a(x)] (64 bytes, the same for every
+// lane) with H1 recomputed per neighbour, instead of gathering their 256-byte
+// H1 rows.  [A2; B2] (128 x 64, float) sits in LDS, shared by the workgroup;
+// a wave takes L2_NB nodes at a time, stages their [H1 | a(H1)] in its own
+// LDS slice, and then for every k reads one weight per lane (a conflict-free
+// 256-byte row) and the nodes' inputs as broadcasts, so each weight read
+// feeds L2_NB FMAs.  The sum over k runs in the same order (0..63 of H1,
+// then 0..63 of a2) as a single-node evaluation.
 constexpr int L2_NB = 8;
 __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* __restrict__ row_off,
                                                      const int2* __restrict__ adj, const float* __restrict__ inv_deg,
-                                                     const uint16_t* __restrict__ w, const float* __restrict__ pre1,
-                                                     float* __restrict__ a2out, float* __restrict__ pre2out,
-                                                     float* __restrict__ z)
+                                                     const uint16_t* __restrict__ w, const float* __restrict__ X,
+                                                     const float* __restrict__ A1agg, float* __restrict__ a2out,
+                                                     float* __restrict__ pre2out, float* __restrict__ z)
 {
     __shared__ float sW[2 * HID * HID];                // [k][j], k < 64: A2, k >= 64: B2
     __shared__ float4 sx[4][L2_NB][2 * HID / 4];       // per wave: L2_NB nodes x [H1 | a2]
@@ -210,6 +234,13 @@ __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* _
     const int wl = threadIdx.x >> 6;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
+    float colA[D_IN], colB[D_IN];
+#pragma unroll
+    for (int k = 0; k < D_IN; ++k) {
+        colA[k] = bf(w[OFF_A1 + k * HID + lane]);
+        colB[k] = bf(w[OFF_B1 + k * HID + lane]);
+    }
+    const float bias1 = bf(w[OFF_b1 + lane]);
     const float bias = bf(w[OFF_b2 + lane]);
     const float cl = bf(w[OFF_c + lane]);
     const float dd = bf(w[OFF_d]);
@@ -218,23 +249,20 @@ __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* _
         const int cnt = (n - i0) < L2_NB ? (n - i0) : L2_NB;
         for (int q = 0; q < cnt; ++q) {
             const int i = i0 + q;
-            const float h = fmaxf(pre1[(size_t)i * HID + lane], 0.0f);
+            const float h = h1_unit(X, A1agg, i, colA, colB, bias1);
             float a = 0.0f;
             int64_t k = row_off[i];
             const int64_t kend = row_off[i + 1];
-            // four neighbour rows in flight at a time (same summation order)
-            for (; k + 4 <= kend; k += 4) {
-                const int2 e0 = adj[k], e1 = adj[k + 1], e2 = adj[k + 2], e3 = adj[k + 3];
-                const float v0 = pre1[(size_t)e0.x * HID + lane], v1 = pre1[(size_t)e1.x * HID + lane];
-                const float v2 = pre1[(size_t)e2.x * HID + lane], v3 = pre1[(size_t)e3.x * HID + lane];
-                a = fmaf(__int_as_float(e0.y), fmaxf(v0, 0.0f), a);
-                a = fmaf(__int_as_float(e1.y), fmaxf(v1, 0.0f), a);
-                a = fmaf(__int_as_float(e2.y), fmaxf(v2, 0.0f), a);
-                a = fmaf(__int_as_float(e3.y), fmaxf(v3, 0.0f), a);
+            for (; k + 2 <= kend; k += 2) {
+                const int2 e0 = adj[k], e1 = adj[k + 1];
+                const float v0 = h1_unit(X, A1agg, e0.x, colA, colB, bias1);
+                const float v1 = h1_unit(X, A1agg, e1.x, colA, colB, bias1);
+                a = fmaf(__int_as_float(e0.y), v0, a);
+                a = fmaf(__int_as_float(e1.y), v1, a);
             }
             for (; k < kend; ++k) {
                 const int2 e = adj[k];
-                a = fmaf(__int_as_float(e.y), fmaxf(pre1[(size_t)e.x * HID + lane], 0.0f), a);
+                a = fmaf(__int_as_float(e.y), h1_unit(X, A1agg, e.x, colA, colB, bias1), a);
             }
             a *= inv_deg[i];
             sxf[q * 2 * HID + lane] = h;
@@ -587,9 +615,11 @@ static fem_status forward(fem_mpnn* m, const Problem& p, const float* state, int
     (void)hipGetLastError();
     feat_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, p.row_off, p.adj, state, stride, k0, k1, (uint32_t)draw, m->X,
                                                  m->inv_deg);
-    layer1_kernel<<<grid_rows((n + L1_NB - 1) / L1_NB, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->X, m->inv_deg, m->wbf, m->A1agg, m->pre1);
-    layer2_kernel<<<grid_rows((n + L2_NB - 1) / L2_NB, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->inv_deg, m->wbf, m->pre1,
-                                                   train ? m->a2 : nullptr, train ? m->pre2 : nullptr, m->z);
+    layer1_kernel<<<grid_rows((n + L1_NB - 1) / L1_NB, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->X, m->inv_deg, m->wbf,
+                                                                         m->A1agg, train ? m->pre1 : nullptr);
+    layer2_kernel<<<grid_rows((n + L2_NB - 1) / L2_NB, 4), 256, 0, st>>>(
+        n, p.row_off, p.adj, m->inv_deg, m->wbf, m->X, m->A1agg, train ? m->a2 : nullptr, train ? m->pre2 : nullptr,
+        m->z);
     MCHK(hipGetLastError());
     return FEM_OK;
 }
