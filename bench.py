@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--gradient", choices=["explicit", "manipulated"], default="explicit")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--retune", action="store_true", help="time every launch shape even if one is cached")
     ap.add_argument("--cpu-replicas", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=150)
     ap.add_argument("--workload", choices=["maxcut1e5", "bmincut1e6", "max3sat1e5", "batch512", "copy"],
@@ -126,6 +127,9 @@ def main():
                     help="maxcut1e5: the throughput line; bmincut1e6 / max3sat1e5: the Potts and Max-3-SAT "
                          "kernels at full size; batch512: time to target on 512 uneven MaxCut instances; "
                          "copy: a plain device copy (calibrates HBM counters)")
+    ap.add_argument("--order", choices=["draw", "rcm"], default="rcm",
+                    help="bmincut1e6: node order of the graph (rcm: relabelled by fem_graph_order before the "
+                         "problem is built; draw: as generated)")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--plain-steps", type=int, default=1000)
     ap.add_argument("--early-steps", type=int, default=100, help="batch512: plain steps before the proposal")
@@ -228,6 +232,7 @@ def throughput(args):
     if manip and kind != "maxcut":
         raise SystemExit("--gradient manipulated is measured on the MaxCut workload")
     log("generating the workload ...")
+    order_s = None
     if kind == "maxsat":
         cnf = W.config_cnf(wl["recipe"])
         n, nnz, q = cnf.n_vars, int(cnf.clause_off[-1]), 1
@@ -237,6 +242,12 @@ def throughput(args):
         g = W.config_graph(wl["recipe"])
         n, nnz = g.n, g.nnz
         q = wl.get("q", 1)
+        if kind == "bmincut" and args.order == "rcm":
+            t_o = time.perf_counter()
+            order = fem.graph_order(g.n, g.u, g.v)
+            g.u, g.v = fem.relabel(order, g.u, g.v)
+            order_s = time.perf_counter() - t_o
+            log(f"relabelled in reverse Cuthill-McKee order ({order_s:.1f} s)")
         if kind == "bmincut":
             prob = fem.Problem.bmincut(g.n, g.u, g.v, g.w, q, device=0)
             h0 = W.initial_fields(n, R, seed=wl["seed"], q=q)
@@ -253,7 +264,7 @@ def throughput(args):
     s.set_fields(h0)
     tile = s.tile()
     if not args.no_tune:
-        tile = s.tune(trial_steps=10, use_cache=True)
+        tile = s.tune(trial_steps=10, use_cache=not args.retune)
     log(f"launch shape (vec, waves, rows, nt, lanes) = {tile}")
     # warm-up: W eager steps, then capture the K-step graph
     s.set_fields(h0)
@@ -296,7 +307,8 @@ def throughput(args):
         kname, counters = "maxcut_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
     elif kind == "bmincut":
         alg_bytes = potts_kernel_bytes(n, R, q, nnz, mbytes, n_tiles)
-        kname, counters = "potts_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
+        rcm = "_rcm" if args.order == "rcm" else ""
+        kname, counters = "potts_step_kernel", f"{wl['counters']}{rcm}_{args.dtype}_hbm_counters.md"
     else:
         alg_bytes = sat_kernel_bytes(n, R, nnz, mbytes, n_tiles)
         kname, counters = "sat_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
@@ -320,10 +332,13 @@ def throughput(args):
         "vs_baseline": None,
         "dtype": ("f32+sign-bit-readouts" if manip else "f32" if dtype == fem.F32 else "f32+bf16-marginals"),
         "data": f"synthetic (seeded generator: {wl['data']})",
-        "config": {"workload": wl["name"], "n": n, "nnz": nnz, "q": q if kind == "bmincut" else 2,
+        "config": {"workload": wl["name"] + ("_rcm" if kind == "bmincut" and args.order == "rcm" else ""),
+                   "n": n, "nnz": nnz, "q": q if kind == "bmincut" else 2,
                    "replicas": R, "anneal_steps": K, "marginals": args.dtype, "gradient": args.gradient,
                    "schedule": "linear beta 0.01->5, Adam lr 0.1", "tile": list(tile),
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "node_order": args.order if kind == "bmincut" else "as generated",
+                   "order_seconds": order_s if kind == "bmincut" else None},
         "result": {"best": float(val[0]), "best_is": label, "mean_integer": float(np.mean(ints)),
                    "U_mean_final": float(np.mean(U)) if U is not None else None},
         "roofline": roof,

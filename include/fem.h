@@ -115,6 +115,18 @@ fem_status fem_problem_info(const fem_problem* p, int32_t* kind, int32_t* n, int
 fem_status fem_problem_instance_offsets(const fem_problem* p, int32_t* offsets);
 void fem_problem_destroy(fem_problem* p);
 
+/* Locality order of a graph's nodes for the neighbour gathers (host only; an
+ * implementation aid, not part of the method): reverse Cuthill-McKee (Cuthill
+ * and McKee 1969, reversed as in George 1971), component by component, each
+ * started from a pseudo-peripheral node found by repeated breadth-first
+ * search (George and Liu 1979), neighbours visited by increasing degree, then
+ * index.  order[k] (n entries, caller-owned) is the node placed at position
+ * k; relabelling node order[k] as k before fem_*_create keeps most
+ * neighbours within a band of rows, so on geometric or mesh-like graphs the
+ * gathered rows stay in L2.  Results then come back in the new labels.
+ * Edges as for fem_maxcut_create (no self-loops); FEM_E_INVAL otherwise. */
+fem_status fem_graph_order(int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v, int32_t* order);
+
 /* ------------------------------------------------------------------ solver */
 typedef struct {
     int32_t replicas;          /* R >= 1 */

@@ -907,6 +907,95 @@ fem_status fem_problem_instance_offsets(const fem_problem* fp, int32_t* offsets)
     return FEM_OK;
 }
 
+fem_status fem_graph_order(int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v, int32_t* order)
+{
+    if (n < 0 || n_edges < 0 || !order || (n_edges > 0 && (!u || !v))) return fail(FEM_E_INVAL, "invalid arguments");
+    // undirected adjacency
+    std::vector<int64_t> off((size_t)n + 1, 0);
+    for (int64_t e = 0; e < n_edges; ++e) {
+        const int32_t a = u[e], b = v[e];
+        if (a < 0 || a >= n || b < 0 || b >= n || a == b)
+            return fail(FEM_E_INVAL, "edge %lld: endpoints out of range or a self-loop", (long long)e);
+        off[(size_t)a + 1]++;
+        off[(size_t)b + 1]++;
+    }
+    for (int32_t i = 0; i < n; ++i) off[(size_t)i + 1] += off[(size_t)i];
+    std::vector<int32_t> adjv((size_t)off[(size_t)n]);
+    {
+        std::vector<int64_t> fill(off.begin(), off.end() - 1);
+        for (int64_t e = 0; e < n_edges; ++e) {
+            adjv[(size_t)fill[(size_t)u[e]]++] = v[e];
+            adjv[(size_t)fill[(size_t)v[e]]++] = u[e];
+        }
+    }
+    auto deg = [&](int32_t i) { return off[(size_t)i + 1] - off[(size_t)i]; };
+    // neighbours by increasing degree, then index
+    for (int32_t i = 0; i < n; ++i)
+        std::sort(adjv.begin() + off[(size_t)i], adjv.begin() + off[(size_t)i + 1], [&](int32_t a, int32_t b) {
+            return deg(a) != deg(b) ? deg(a) < deg(b) : a < b;
+        });
+    std::vector<int32_t> level((size_t)n, -1), queue;
+    queue.reserve((size_t)n);
+    // breadth-first levels of the component of s; returns the last level's
+    // members in queue order (level[] is reset afterwards)
+    auto bfs_last = [&](int32_t s, int32_t& ecc) {
+        std::vector<int32_t> q{s};
+        level[(size_t)s] = 0;
+        for (size_t h = 0; h < q.size(); ++h) {
+            const int32_t x = q[h];
+            for (int64_t k = off[(size_t)x]; k < off[(size_t)x + 1]; ++k)
+                if (level[(size_t)adjv[(size_t)k]] < 0) {
+                    level[(size_t)adjv[(size_t)k]] = level[(size_t)x] + 1;
+                    q.push_back(adjv[(size_t)k]);
+                }
+        }
+        ecc = level[(size_t)q.back()];
+        std::vector<int32_t> last;
+        for (int32_t x : q)
+            if (level[(size_t)x] == ecc) last.push_back(x);
+        for (int32_t x : q) level[(size_t)x] = -1;
+        return last;
+    };
+    std::vector<char> placed((size_t)n, 0);
+    std::vector<int32_t> by_degree((size_t)n);
+    for (int32_t i = 0; i < n; ++i) by_degree[(size_t)i] = i;
+    std::stable_sort(by_degree.begin(), by_degree.end(), [&](int32_t a, int32_t b) { return deg(a) < deg(b); });
+    for (int32_t start : by_degree) {
+        if (placed[(size_t)start]) continue;
+        // pseudo-peripheral node: move to a minimum-degree node of the last
+        // level while the eccentricity grows
+        int32_t s = start, ecc = 0;
+        std::vector<int32_t> last = bfs_last(s, ecc);
+        for (int it = 0; it < 16; ++it) {
+            int32_t cand = last[0];
+            for (int32_t x : last)
+                if (deg(x) < deg(cand) || (deg(x) == deg(cand) && x < cand)) cand = x;
+            int32_t ecc2 = 0;
+            std::vector<int32_t> last2 = bfs_last(cand, ecc2);
+            if (ecc2 <= ecc) break;
+            s = cand;
+            ecc = ecc2;
+            last.swap(last2);
+        }
+        // Cuthill-McKee from s
+        const size_t first = queue.size();
+        queue.push_back(s);
+        placed[(size_t)s] = 1;
+        for (size_t h = first; h < queue.size(); ++h) {
+            const int32_t x = queue[h];
+            for (int64_t k = off[(size_t)x]; k < off[(size_t)x + 1]; ++k) {
+                const int32_t y = adjv[(size_t)k];
+                if (!placed[(size_t)y]) {
+                    placed[(size_t)y] = 1;
+                    queue.push_back(y);
+                }
+            }
+        }
+    }
+    for (int32_t k = 0; k < n; ++k) order[k] = queue[(size_t)(n - 1 - k)];
+    return FEM_OK;
+}
+
 void fem_problem_destroy(fem_problem* fp)
 {
     if (!fp) return;

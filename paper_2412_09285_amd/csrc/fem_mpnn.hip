@@ -186,37 +186,44 @@ __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* _
     }
 }
 
-// H1 of node j from its 16 inputs [x_j | a(x)_j], for hidden unit `lane`,
-// in the same operation order as layer1_kernel (bit-identical results)
-__device__ __forceinline__ float h1_unit(const float* __restrict__ X, const float* __restrict__ A1agg, int64_t j,
-                                         const float (&colA)[D_IN], const float (&colB)[D_IN], float bias)
+// H1 of node j, hidden units 4l..4l+3, from its 16 layer-1 inputs
+// [x_j | a(x)_j], in the same operation order as layer1_kernel (bit-identical)
+__device__ __forceinline__ void h1_units4(const float* __restrict__ X, const float* __restrict__ A1agg, int64_t j,
+                                          const float (&cA)[4][D_IN], const float (&cB)[4][D_IN],
+                                          const float (&b1)[4], float (&out)[4])
 {
     const float4 x0 = reinterpret_cast<const float4*>(X + j * D_IN)[0];
     const float4 x1 = reinterpret_cast<const float4*>(X + j * D_IN)[1];
     const float4 a0 = reinterpret_cast<const float4*>(A1agg + j * D_IN)[0];
     const float4 a1 = reinterpret_cast<const float4*>(A1agg + j * D_IN)[1];
-    float acc = bias;
-    acc = fmaf(x0.x, colA[0], acc); acc = fmaf(x0.y, colA[1], acc);
-    acc = fmaf(x0.z, colA[2], acc); acc = fmaf(x0.w, colA[3], acc);
-    acc = fmaf(x1.x, colA[4], acc); acc = fmaf(x1.y, colA[5], acc);
-    acc = fmaf(x1.z, colA[6], acc); acc = fmaf(x1.w, colA[7], acc);
-    acc = fmaf(a0.x, colB[0], acc); acc = fmaf(a0.y, colB[1], acc);
-    acc = fmaf(a0.z, colB[2], acc); acc = fmaf(a0.w, colB[3], acc);
-    acc = fmaf(a1.x, colB[4], acc); acc = fmaf(a1.y, colB[5], acc);
-    acc = fmaf(a1.z, colB[6], acc); acc = fmaf(a1.w, colB[7], acc);
-    return fmaxf(acc, 0.0f);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        float acc = b1[u];
+        acc = fmaf(x0.x, cA[u][0], acc); acc = fmaf(x0.y, cA[u][1], acc);
+        acc = fmaf(x0.z, cA[u][2], acc); acc = fmaf(x0.w, cA[u][3], acc);
+        acc = fmaf(x1.x, cA[u][4], acc); acc = fmaf(x1.y, cA[u][5], acc);
+        acc = fmaf(x1.z, cA[u][6], acc); acc = fmaf(x1.w, cA[u][7], acc);
+        acc = fmaf(a0.x, cB[u][0], acc); acc = fmaf(a0.y, cB[u][1], acc);
+        acc = fmaf(a0.z, cB[u][2], acc); acc = fmaf(a0.w, cB[u][3], acc);
+        acc = fmaf(a1.x, cB[u][4], acc); acc = fmaf(a1.y, cB[u][5], acc);
+        acc = fmaf(a1.z, cB[u][6], acc); acc = fmaf(a1.w, cB[u][7], acc);
+        out[u] = fmaxf(acc, 0.0f);
+    }
 }
 
-// Lane j of a wave owns hidden unit j.  The aggregate a(H1) is formed from
-// the neighbours' 16 layer-1 inputs [x | a(x)] (64 bytes, the same for every
-// lane) with H1 recomputed per neighbour, instead of gathering their 256-byte
-// H1 rows.  [A2; B2] (128 x 64, float) sits in LDS, shared by the workgroup;
-// a wave takes L2_NB nodes at a time, stages their [H1 | a(H1)] in its own
-// LDS slice, and then for every k reads one weight per lane (a conflict-free
-// 256-byte row) and the nodes' inputs as broadcasts, so each weight read
-// feeds L2_NB FMAs.  The sum over k runs in the same order (0..63 of H1,
-// then 0..63 of a2) as a single-node evaluation.
-constexpr int L2_NB = 8;
+// Layer 2, four nodes per wave at a time.
+// Gather: team t (16 lanes) takes node i0 + t; lane l of the team owns hidden
+// units 4l..4l+3 (their layer-1 weights in registers) and forms a(H1) from
+// the neighbours' 16 layer-1 inputs [x | a(x)] (64 bytes, the same for the
+// team's lanes) with H1 recomputed per neighbour, instead of gathering
+// 256-byte H1 rows; the four nodes' dependency chains run side by side.
+// Dense: [A2; B2] (128 x 64, float) sits in LDS, shared by the workgroup; the
+// four nodes' [H1 | a(H1)] are staged in the wave's LDS slice and lane j (=
+// output unit) reads one weight per k (a conflict-free 256-byte row) and the
+// nodes' inputs as broadcasts, so each weight read feeds four FMAs.  Every sum
+// runs in the order of a single-node evaluation (CSR order for a(H1); k =
+// 0..63 of H1, then 0..63 of a(H1), for pre2).
+constexpr int L2_NB = 4;
 __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* __restrict__ row_off,
                                                      const int2* __restrict__ adj, const float* __restrict__ inv_deg,
                                                      const uint16_t* __restrict__ w, const float* __restrict__ X,
@@ -232,42 +239,55 @@ __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* _
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wl = threadIdx.x >> 6;
+    const int team = lane >> 4, tl = lane & 15;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
-    float colA[D_IN], colB[D_IN];
+    float cA[4][D_IN], cB[4][D_IN], b1[4];
 #pragma unroll
-    for (int k = 0; k < D_IN; ++k) {
-        colA[k] = bf(w[OFF_A1 + k * HID + lane]);
-        colB[k] = bf(w[OFF_B1 + k * HID + lane]);
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int c = 0; c < D_IN; ++c) {
+            cA[u][c] = bf(w[OFF_A1 + c * HID + 4 * tl + u]);
+            cB[u][c] = bf(w[OFF_B1 + c * HID + 4 * tl + u]);
+        }
+        b1[u] = bf(w[OFF_b1 + 4 * tl + u]);
     }
-    const float bias1 = bf(w[OFF_b1 + lane]);
     const float bias = bf(w[OFF_b2 + lane]);
     const float cl = bf(w[OFF_c + lane]);
     const float dd = bf(w[OFF_d]);
-    float* sxf = reinterpret_cast<float*>(&sx[wl][0][0]);
     for (int i0 = wave * L2_NB; i0 < n; i0 += nw * L2_NB) {
         const int cnt = (n - i0) < L2_NB ? (n - i0) : L2_NB;
-        for (int q = 0; q < cnt; ++q) {
-            const int i = i0 + q;
-            const float h = h1_unit(X, A1agg, i, colA, colB, bias1);
-            float a = 0.0f;
+        const int i = i0 + team;
+        if (i < n) {
+            float h[4], a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            h1_units4(X, A1agg, i, cA, cB, b1, h);
             int64_t k = row_off[i];
             const int64_t kend = row_off[i + 1];
             for (; k + 2 <= kend; k += 2) {
                 const int2 e0 = adj[k], e1 = adj[k + 1];
-                const float v0 = h1_unit(X, A1agg, e0.x, colA, colB, bias1);
-                const float v1 = h1_unit(X, A1agg, e1.x, colA, colB, bias1);
-                a = fmaf(__int_as_float(e0.y), v0, a);
-                a = fmaf(__int_as_float(e1.y), v1, a);
+                float v0[4], v1[4];
+                h1_units4(X, A1agg, e0.x, cA, cB, b1, v0);
+                h1_units4(X, A1agg, e1.x, cA, cB, b1, v1);
+                const float w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = fmaf(w0, v0[u], a[u]);
+                    a[u] = fmaf(w1, v1[u], a[u]);
+                }
             }
             for (; k < kend; ++k) {
                 const int2 e = adj[k];
-                a = fmaf(__int_as_float(e.y), h1_unit(X, A1agg, e.x, colA, colB, bias1), a);
+                float v0[4];
+                h1_units4(X, A1agg, e.x, cA, cB, b1, v0);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[u] = fmaf(__int_as_float(e.y), v0[u], a[u]);
             }
-            a *= inv_deg[i];
-            sxf[q * 2 * HID + lane] = h;
-            sxf[q * 2 * HID + HID + lane] = a;
-            if (a2out) a2out[(size_t)i * HID + lane] = a;
+            const float id = inv_deg[i];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] *= id;
+            sx[wl][team][tl] = make_float4(h[0], h[1], h[2], h[3]);
+            sx[wl][team][HID / 4 + tl] = make_float4(a[0], a[1], a[2], a[3]);
+            if (a2out) reinterpret_cast<float4*>(a2out + (size_t)i * HID)[tl] = make_float4(a[0], a[1], a[2], a[3]);
         }
         __builtin_amdgcn_wave_barrier();
         float acc[L2_NB];
@@ -288,10 +308,10 @@ __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* _
         }
         __builtin_amdgcn_wave_barrier();
         for (int q = 0; q < cnt; ++q) {
-            const int i = i0 + q;
+            const int iq = i0 + q;
             const float zz = wave_sum(fmaxf(acc[q], 0.0f) * cl);
-            if (pre2out) pre2out[(size_t)i * HID + lane] = acc[q];
-            if (lane == 0) z[i] = zz + dd;
+            if (pre2out) pre2out[(size_t)iq * HID + lane] = acc[q];
+            if (lane == 0) z[iq] = zz + dd;
         }
     }
 }

@@ -66,6 +66,7 @@ _SIGS = {
     "fem_bmincut_create": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _P, C.c_int32, _PP]),
     "fem_maxsat_create": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _PP]),
     "fem_batch_create": (C.c_int, [C.c_int32, _P, _PP]),
+    "fem_graph_order": (C.c_int, [C.c_int32, C.c_int64, _P, _P, _P]),
     "fem_problem_info": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "fem_problem_instance_offsets": (C.c_int, [_P, _P]),
     "fem_problem_destroy": (None, [_P]),
@@ -168,6 +169,23 @@ def default_params(**kw) -> Params:
             raise TypeError(f"unknown parameter {k}")
         setattr(p, k, v)
     return p
+
+
+def graph_order(n, u, v):
+    """Reverse Cuthill-McKee order of the nodes (see fem.h): order[k] is the
+    node to relabel as k."""
+    u, pu = _host(u, np.int32)
+    v, pv = _host(v, np.int32)
+    order = np.empty(n, dtype=np.int32)
+    _check(lib().fem_graph_order(n, u.shape[0], pu, pv, order.ctypes.data_as(C.c_void_p)))
+    return order
+
+
+def relabel(order, u, v):
+    """Edge lists relabelled by order (node order[k] becomes k)."""
+    inv = np.empty_like(order)
+    inv[order] = np.arange(order.size, dtype=order.dtype)
+    return inv[np.asarray(u)], inv[np.asarray(v)]
 
 
 class Problem:
