@@ -47,6 +47,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
     const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
+    // compute type of the field sums and the gradient combination
+    using CT = typename std::conditional<sizeof(MT) == 4, double, float>::type;
     // per-lane energy terms over the few rows of one team (float), widened
     // to double for the workgroup and tile sums
     float eacc[2 * V];
@@ -61,11 +63,13 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
             ld_state<V, NT>(a.h + base, hv);
             ld_state<V, NT>(a.m1 + base, m1v);
             ld_state<V, NT>(a.m2 + base, m2v);
-            // phi accumulates in double: near equilibrium g is a small
-            // difference of 2 phi and h / beta
-            double acc[V];
+            // phi accumulates in double for float32 marginals (near
+            // equilibrium g is a small difference of 2 phi and h / beta); a
+            // bfloat16 copy carries 8 bits, so float accumulation is exact
+            // enough there
+            CT acc[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc[v] = 0.0;
+            for (int v = 0; v < V; ++v) acc[v] = (CT)0;
             int64_t k = a.row_off[i];
             const int64_t kend = a.row_off[i + 1];
             for (; k + 4 <= kend; k += 4) {
@@ -75,23 +79,23 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 ld_marg<MT, V>(mc + (size_t)e1.x * R + rb, x1);
                 ld_marg<MT, V>(mc + (size_t)e2.x * R + rb, x2);
                 ld_marg<MT, V>(mc + (size_t)e3.x * R + rb, x3);
-                const double w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
-                const double w2 = __int_as_float(e2.y), w3 = __int_as_float(e3.y);
+                const CT w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
+                const CT w2 = __int_as_float(e2.y), w3 = __int_as_float(e3.y);
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    acc[v] = fma(w0, (double)x0[v], acc[v]);
-                    acc[v] = fma(w1, (double)x1[v], acc[v]);
-                    acc[v] = fma(w2, (double)x2[v], acc[v]);
-                    acc[v] = fma(w3, (double)x3[v], acc[v]);
+                    acc[v] = fma(w0, (CT)x0[v], acc[v]);
+                    acc[v] = fma(w1, (CT)x1[v], acc[v]);
+                    acc[v] = fma(w2, (CT)x2[v], acc[v]);
+                    acc[v] = fma(w3, (CT)x3[v], acc[v]);
                 }
             }
             for (; k < kend; ++k) {
                 const int2 e0 = a.adj[k];
                 float x0[V];
                 ld_marg<MT, V>(mc + (size_t)e0.x * R + rb, x0);
-                const double w0 = __int_as_float(e0.y);
+                const CT w0 = __int_as_float(e0.y);
 #pragma unroll
-                for (int v = 0; v < V; ++v) acc[v] = fma(w0, (double)x0[v], acc[v]);
+                for (int v = 0; v < V; ++v) acc[v] = fma(w0, (CT)x0[v], acc[v]);
             }
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -100,10 +104,10 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 const float e = expf(-ax);
                 const float ope = 1.0f + e;
                 const float pq = e / (ope * ope);   // P(1-P) without cancellation
-                const float g = (float)((double)pq * (2.0 * acc[v] + (double)x * sc.inv_beta_d));
+                const float g = (float)((CT)pq * ((CT)2 * acc[v] + (CT)x * (CT)sc.inv_beta_d));
                 gv[v] = g;
                 if constexpr (EN) {
-                    eacc[v] += (float)((double)tanhf(0.5f * x) * acc[v]);
+                    eacc[v] += (float)((CT)tanhf(0.5f * x) * acc[v]);
                     eacc[V + v] += log1pf(e) + ax * (e / ope);
                 }
                 const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
@@ -154,8 +158,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
     const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
-    // Phi accumulates in double up to q = 8 (register budget above)
-    using AccT = typename std::conditional<(Q <= 8), double, float>::type;
+    // Phi accumulates and the gradient terms combine in double for float32
+    // marginals up to q = 8 (register budget above); bfloat16 marginals carry
+    // 8 bits, so float is exact enough there
+    using AccT = typename std::conditional<(Q <= 8 && sizeof(MT) == 4), double, float>::type;
+    using CT = typename std::conditional<sizeof(MT) == 4, double, float>::type;
     AccT ct[Q];
     double eacc[3] = {0.0, 0.0, 0.0};
     long long cs[Q];
@@ -211,20 +218,20 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             // The mean is normalised by the sum of the float32 marginals, so
             // their rounding perturbs only the weights, by a relative amount,
             // and the error scales with the spread of A, not its size.
+            const CT lam2 = (CT)2 * (CT)sc.lam_d, ib = (CT)sc.inv_beta_d;
             auto Aof = [&](int s) {
-                return -2.0 * (double)phi[s] + 2.0 * sc.lam_d * ((double)ct[s] - (double)P[s]) +
-                       ((double)hv[s] - (double)mx) * sc.inv_beta_d;
+                return (CT)-2 * (CT)phi[s] + lam2 * ((CT)ct[s] - (CT)P[s]) + ((CT)hv[s] - (CT)mx) * ib;
             };
-            double avg = 0.0, psum = 0.0;
+            CT avg = 0, psum = 0;
 #pragma unroll
             for (int s = 0; s < Q; ++s) {
-                avg = fma((double)P[s], Aof(s), avg);
-                psum += (double)P[s];
+                avg = fma((CT)P[s], Aof(s), avg);
+                psum += (CT)P[s];
             }
             avg /= psum;
             float gv[Q];
 #pragma unroll
-            for (int s = 0; s < Q; ++s) gv[s] = (float)((Aof(s) - avg) * (double)P[s]);
+            for (int s = 0; s < Q; ++s) gv[s] = (float)((Aof(s) - avg) * (CT)P[s]);
             if constexpr (EN) {
                 const float lz = logf(Z);
                 double dot = 0.0;
@@ -251,7 +258,16 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             const float invZ2 = 1.0f / Z2;
 #pragma unroll
             for (int s = 0; s < Q; ++s) Pn[s] *= invZ2;
-            colsum_add<Q>(hv, cs);
+            // column-sum contributions: a double-precision softmax for float32
+            // marginals (their rounding, summed over all nodes, would carry
+            // into the balance term); the float softmax for bfloat16 ones,
+            // whose own rounding is 2^-8
+            if constexpr (sizeof(MT) == 4) {
+                colsum_add<Q>(hv, cs);
+            } else {
+#pragma unroll
+                for (int s = 0; s < Q; ++s) cs[s] += to_fixed((double)Pn[s]);
+            }
             st_state<Q, NT>(a.h + base, hv);
             st_state<Q, NT>(a.m1 + base, m1v);
             st_state<Q, NT>(a.m2 + base, m2v);
@@ -305,6 +321,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
     const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
+    // compute type of the clause sums and the gradient combination
+    using CT = typename std::conditional<sizeof(MT) == 4, double, float>::type;
     float eacc[2 * V];
 #pragma unroll
     for (int k = 0; k < 2 * V; ++k) eacc[k] = 0.0f;
@@ -326,9 +344,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 own_small[v] = e / (1.0f + e);
                 own_hi[v] = hv[v] > 0.0f;
             }
-            double d[V];
+            CT d[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) d[v] = 0.0;
+            for (int v = 0; v < V; ++v) d[v] = (CT)0;
             const int64_t kend = a.row_off[i + 1];
             for (int64_t k = a.row_off[i]; k < kend; ++k) {
                 const Rec rec = inc[k];
@@ -359,7 +377,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 }
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    d[v] += own_pos ? -(double)c[v] : (double)c[v];
+                    d[v] += own_pos ? -(CT)c[v] : (CT)c[v];
                     if constexpr (EN) {
                         if (owner) {
                             const float uo = (own_pos == own_hi[v]) ? own_small[v] : 1.0f - own_small[v];
@@ -376,7 +394,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 const float e = expf(-ax);
                 const float ope = 1.0f + e;
                 const float pq = e / (ope * ope);
-                const float g = (float)(sc.gamma_d * ((double)pq * (d[v] + (double)x * sc.inv_beta_d)));
+                const float g = (float)((CT)sc.gamma_d * ((CT)pq * (d[v] + (CT)x * (CT)sc.inv_beta_d)));
                 gv[v] = g;
                 if constexpr (EN) eacc[V + v] += log1pf(e) + ax * (e / ope);
                 const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
