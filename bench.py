@@ -74,7 +74,7 @@ def kernel_sources_sha(gradient):
     return h.hexdigest()
 
 
-def measured_traffic(path, gradient, tile, marginals):
+def measured_traffic(path, gradient, tile, marginals, layout="separate"):
     """Bytes per launch from a committed counter summary, or None when the
     summary is missing or was taken with other kernel sources / launch shape."""
     if not os.path.exists(path):
@@ -85,7 +85,7 @@ def measured_traffic(path, gradient, tile, marginals):
         return None
     rec = json.loads(m.group(1))
     if rec.get("kernel_sources_sha256") != kernel_sources_sha(gradient) or list(rec.get("tile", [])) != list(tile) \
-            or rec.get("marginals") != marginals:
+            or rec.get("marginals") != marginals or rec.get("state_layout", "separate") != layout:
         return None
     return int(rec["traffic_bytes_per_launch"])
 
@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50, help="untimed warm-up steps W")
     ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32")
     ap.add_argument("--gradient", choices=["explicit", "manipulated"], default="explicit")
+    ap.add_argument("--state-layout", choices=["separate", "interleaved"], default="separate",
+                    help="device layout of h and the Adam moments (no effect on results)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--retune", action="store_true", help="time every launch shape even if one is cached")
@@ -258,6 +260,7 @@ def throughput(args):
     stream = torch.cuda.Stream()
     T = max(K, Wm, 1)
     extra = dict(gradient=fem.GRAD_MANIPULATED, energy_every=0) if manip else dict(energy_every=1)
+    extra["state_layout"] = fem.STATE_INTERLEAVED if args.state_layout == "interleaved" else fem.STATE_SEPARATE
     if kind == "bmincut":
         extra["lam"] = wl["lam"]
     s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, marginal_dtype=dtype, **extra), stream=stream)
@@ -313,7 +316,10 @@ def throughput(args):
         alg_bytes = sat_kernel_bytes(n, R, nnz, mbytes, n_tiles)
         kname, counters = "sat_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    traffic = measured_traffic(os.path.join(ROOT, "profiles", counters), args.gradient, tile, args.dtype)
+    if args.state_layout != "separate":
+        counters = counters.replace("_hbm_counters", f"_{args.state_layout}_hbm_counters")
+    traffic = measured_traffic(os.path.join(ROOT, "profiles", counters), args.gradient, tile, args.dtype,
+                               args.state_layout)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kname, "kernel_avg_ms": round(kern_ms, 5), "kernel_launches": n_k,
@@ -335,6 +341,7 @@ def throughput(args):
         "config": {"workload": wl["name"] + ("_rcm" if kind == "bmincut" and args.order == "rcm" else ""),
                    "n": n, "nnz": nnz, "q": q if kind == "bmincut" else 2,
                    "replicas": R, "anneal_steps": K, "marginals": args.dtype, "gradient": args.gradient,
+                   "state_layout": args.state_layout,
                    "schedule": "linear beta 0.01->5, Adam lr 0.1", "tile": list(tile),
                    "parallelism": "single GPU",
                    "node_order": args.order if kind == "bmincut" else "as generated",

@@ -147,7 +147,15 @@ typedef struct {
     double dampening;          /* SGD dampening */
     int32_t gradient;          /* FEM_GRAD_EXPLICIT | FEM_GRAD_MANIPULATED */
     double gamma_grad;         /* gamma_grad of the manipulated gradients */
+    int32_t state_layout;      /* FEM_STATE_SEPARATE | FEM_STATE_INTERLEAVED */
 } fem_params;
+
+/* Device layout of the optimiser state (h and the two moments); it changes
+ * no result, only how the step kernels stream it, and every getter and setter
+ * keeps the [n][R] / [n][R][q] layout of each array.
+ *  FEM_STATE_SEPARATE: three arrays.
+ *  FEM_STATE_INTERLEAVED: the three rows of a node next to each other. */
+enum { FEM_STATE_SEPARATE = 0, FEM_STATE_INTERLEAVED = 1 };
 
 /* Gradient with respect to the fields (supplementary "The explicit gradient
  * formulations" and "The explicit gradients and manipulated gradients for the

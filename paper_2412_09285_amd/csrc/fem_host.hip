@@ -346,10 +346,14 @@ struct fem_solver {
     bool fields_set = false;
     bool manip = false;   // manipulated gradients on a graph kind: read-out marginal copy
     int32_t rw = 0;       // MaxCut manipulated: 32-bit words per row of sign bits
-    // state
+    // state: one allocation of 3 vals floats holding h, m1, m2; rows of each
+    // are srow floats apart (RQ: three separate arrays; 3RQ: the three rows
+    // of a node interleaved)
+    float* state = nullptr;
     float* h = nullptr;
     float* m1 = nullptr;
     float* m2 = nullptr;
+    int64_t srow = 0;
     float* grad = nullptr;
     void* marg[2] = {nullptr, nullptr};
     // tiling
@@ -608,6 +612,7 @@ static StepArgs base_args(const fem_solver* s)
     a.h = s->h;
     a.m1 = s->m1;
     a.m2 = s->m2;
+    a.srow = s->srow;
     a.grad = s->prm.keep_grad ? s->grad : nullptr;
     a.ctil = s->ctil;
     a.cpart = s->cpart;
@@ -648,7 +653,7 @@ static fem_status readout_eval(fem_solver* s, const uint8_t* sigma_in, bool upda
 {
     const Problem& p = *s->prob;
     if (!sigma_in) {
-        HIPCHK(launch_round(s->kind, s->n, s->R, s->q, s->h, s->sigma, s->stream));
+        HIPCHK(launch_round(s->kind, s->n, s->R, s->q, s->h, s->srow, s->sigma, s->stream));
         sigma_in = s->sigma;
     }
     HIPCHK(launch_eval(p, s->egeo, s->shape.waves, s->d_tiles, s->R, sigma_in, s->vpart, s->spart, s->stream));
@@ -737,9 +742,7 @@ static void destroy_solver(fem_solver* s)
         (void)hipEventDestroy(ev.second);
     }
     free_tiling(s);
-    dfree(s->h);
-    dfree(s->m1);
-    dfree(s->m2);
+    dfree(s->state);
     dfree(s->grad);
     void* m0 = s->marg[0];
     void* m1v = s->marg[1];
@@ -1034,6 +1037,7 @@ void fem_params_default(fem_params* p)
     p->dampening = 0.0;
     p->gradient = FEM_GRAD_EXPLICIT;
     p->gamma_grad = 1.0;
+    p->state_layout = FEM_STATE_SEPARATE;
 }
 
 fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void* hip_stream, fem_solver** out)
@@ -1056,6 +1060,8 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
         return fail(FEM_E_INVAL, "invalid momentum, rms_alpha or dampening");
     if (P.marginal_dtype != FEM_F32 && P.marginal_dtype != FEM_BF16) return fail(FEM_E_INVAL, "unknown marginal dtype");
     if (P.energy_every < 0 || P.eval_every < 0) return fail(FEM_E_INVAL, "energy_every and eval_every must be >= 0");
+    if (P.state_layout != FEM_STATE_SEPARATE && P.state_layout != FEM_STATE_INTERLEAVED)
+        return fail(FEM_E_INVAL, "unknown state layout %d", P.state_layout);
     if (P.gradient != FEM_GRAD_EXPLICIT && P.gradient != FEM_GRAD_MANIPULATED)
         return fail(FEM_E_INVAL, "unknown gradient mode %d", P.gradient);
     if (!std::isfinite(P.gamma_grad)) return fail(FEM_E_INVAL, "gamma_grad must be finite");
@@ -1117,9 +1123,15 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
             return bail(fail(FEM_E_NOMEM, "device allocation of %s (%zu elements): %s", #ptr, (size_t)(cnt), \
                              hipGetErrorString(ee)));                                                      \
     } while (0)
-    ALLOC(s->h, s->vals);
-    ALLOC(s->m1, s->vals);
-    ALLOC(s->m2, s->vals);
+    ALLOC(s->state, 3 * s->vals);
+    {
+        const size_t RQ = (size_t)s->R * s->Q;
+        const bool inter = P.state_layout == FEM_STATE_INTERLEAVED;
+        s->srow = (int64_t)(inter ? 3 * RQ : RQ);
+        s->h = s->state;
+        s->m1 = s->state + (inter ? RQ : s->vals);
+        s->m2 = s->state + (inter ? 2 * RQ : 2 * s->vals);
+    }
     if (P.keep_grad) ALLOC(s->grad, s->vals);
     for (int k = 0; k < 2; ++k) {
         e = hipMalloc(&s->marg[k], mbytes ? mbytes : 4);
@@ -1159,13 +1171,27 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
 
 void fem_solver_destroy(fem_solver* s) { destroy_solver(s); }
 
+// copy n rows of RQ floats between a dense [n][RQ] array and one of the
+// solver's state arrays (rows srow floats apart)
+static hipError_t copy_state_rows(const fem_solver* s, float* dst, bool dst_state, const float* src, hipMemcpyKind kd)
+{
+    const size_t w = (size_t)s->R * s->Q * 4;
+    const size_t sp = (size_t)s->srow * 4;
+    return hipMemcpy2DAsync(dst, dst_state ? sp : w, src, dst_state ? w : sp, w, (size_t)s->n, kd, s->stream);
+}
+
+static hipError_t zero_state_rows(const fem_solver* s, float* dst)
+{
+    return hipMemset2DAsync(dst, (size_t)s->srow * 4, 0, (size_t)s->R * s->Q * 4, (size_t)s->n, s->stream);
+}
+
 fem_status fem_set_fields(fem_solver* s, const float* h, int on_device)
 {
     if (!s || !h) return fail(FEM_E_INVAL, "NULL argument");
     HIPCHK(hipSetDevice(s->prob->device));
-    HIPCHK(hipMemcpyAsync(s->h, h, s->vals * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemsetAsync(s->m1, 0, s->vals * 4, s->stream));
-    HIPCHK(hipMemsetAsync(s->m2, 0, s->vals * 4, s->stream));
+    HIPCHK(copy_state_rows(s, s->h, true, h, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    HIPCHK(zero_state_rows(s, s->m1));
+    HIPCHK(zero_state_rows(s, s->m2));
     s->t = 0;
     s->last_energy_step = -1;
     STCHK(init_marginals(s));
@@ -1181,9 +1207,9 @@ fem_status fem_set_adam_state(fem_solver* s, const float* h, const float* m1, co
     if (t < 0 || t > s->prm.steps) return fail(FEM_E_INVAL, "step %d outside [0, %d]", t, s->prm.steps);
     HIPCHK(hipSetDevice(s->prob->device));
     const hipMemcpyKind kd = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    HIPCHK(hipMemcpyAsync(s->h, h, s->vals * 4, kd, s->stream));
-    HIPCHK(hipMemcpyAsync(s->m1, m1, s->vals * 4, kd, s->stream));
-    HIPCHK(hipMemcpyAsync(s->m2, m2, s->vals * 4, kd, s->stream));
+    HIPCHK(copy_state_rows(s, s->h, true, h, kd));
+    HIPCHK(copy_state_rows(s, s->m1, true, m1, kd));
+    HIPCHK(copy_state_rows(s, s->m2, true, m2, kd));
     s->t = t;
     s->last_energy_step = -1;
     STCHK(init_marginals(s));
@@ -1292,7 +1318,7 @@ fem_status fem_get_fields(fem_solver* s, float* h, int on_device)
 {
     if (!s || !h) return fail(FEM_E_INVAL, "NULL argument");
     HIPCHK(hipSetDevice(s->prob->device));
-    HIPCHK(hipMemcpyAsync(h, s->h, s->vals * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(copy_state_rows(s, h, false, s->h, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     HIPCHK(hipStreamSynchronize(s->stream));
     return FEM_OK;
 }
@@ -1353,7 +1379,7 @@ fem_status fem_round(fem_solver* s, int32_t* sigma)
     if (!s || !sigma) return fail(FEM_E_INVAL, "NULL argument");
     if (!s->fields_set) return fail(FEM_E_STATE, "no fields set");
     HIPCHK(hipSetDevice(s->prob->device));
-    HIPCHK(launch_round(s->kind, s->n, s->R, s->q, s->h, s->sigma, s->stream));
+    HIPCHK(launch_round(s->kind, s->n, s->R, s->q, s->h, s->srow, s->sigma, s->stream));
     std::vector<uint8_t> buf((size_t)s->n * s->R);
     HIPCHK(hipMemcpyAsync(buf.data(), s->sigma, buf.size(), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -1519,9 +1545,9 @@ fem_status fem_get_state(fem_solver* s, void* buf, size_t bytes)
     char* out = static_cast<char*>(buf);
     std::memcpy(out, &hd, sizeof hd);
     char* p = out + sizeof hd;
-    HIPCHK(hipMemcpyAsync(p, s->h, s->vals * 4, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(p + s->vals * 4, s->m1, s->vals * 4, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(p + 2 * s->vals * 4, s->m2, s->vals * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(copy_state_rows(s, reinterpret_cast<float*>(p), false, s->h, hipMemcpyDeviceToHost));
+    HIPCHK(copy_state_rows(s, reinterpret_cast<float*>(p + s->vals * 4), false, s->m1, hipMemcpyDeviceToHost));
+    HIPCHK(copy_state_rows(s, reinterpret_cast<float*>(p + 2 * s->vals * 4), false, s->m2, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpyAsync(p + 3 * s->vals * 4, s->best, (size_t)s->n_inst * s->R * 8, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return FEM_OK;
@@ -1541,9 +1567,9 @@ fem_status fem_set_state(fem_solver* s, const void* buf, size_t bytes)
     if (hd.t < 0 || hd.t > s->prm.steps) return fail(FEM_E_INVAL, "state step %d outside the schedule", hd.t);
     HIPCHK(hipSetDevice(s->prob->device));
     const char* p = static_cast<const char*>(buf) + sizeof hd;
-    HIPCHK(hipMemcpyAsync(s->h, p, s->vals * 4, hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(s->m1, p + s->vals * 4, s->vals * 4, hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(s->m2, p + 2 * s->vals * 4, s->vals * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(copy_state_rows(s, s->h, true, reinterpret_cast<const float*>(p), hipMemcpyHostToDevice));
+    HIPCHK(copy_state_rows(s, s->m1, true, reinterpret_cast<const float*>(p + s->vals * 4), hipMemcpyHostToDevice));
+    HIPCHK(copy_state_rows(s, s->m2, true, reinterpret_cast<const float*>(p + 2 * s->vals * 4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpyAsync(s->best, p + 3 * s->vals * 4, (size_t)s->n_inst * s->R * 8, hipMemcpyHostToDevice, s->stream));
     s->t = hd.t;
     s->last_energy_step = -1;
@@ -1637,7 +1663,9 @@ static std::string tune_key(const fem_solver* s)
     snprintf(buf, sizeof buf, "v2_k%d_n%d_nnz%lld_R%d_q%d_dt%d_inst%d_en%d_g%d", s->kind, s->n,
              (long long)s->prob->nnz, s->R, s->q, s->dtype, s->n_inst, s->prm.energy_every > 0 ? 1 : 0,
              s->manip ? 1 : 0);
-    return buf;
+    std::string key = buf;
+    if (s->prm.state_layout == FEM_STATE_INTERLEAVED) key += "_sl1";
+    return key;
 }
 
 fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_tile* chosen)
@@ -1666,11 +1694,8 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     HIPCHK(dalloc(&backup, 3 * s->vals));
     auto save_restore = [&](bool save) -> fem_status {
         const hipMemcpyKind k = hipMemcpyDeviceToDevice;
-        float* st3[3] = {s->h, s->m1, s->m2};
-        for (int j = 0; j < 3; ++j) {
-            if (save) HIPCHK(hipMemcpyAsync(backup + j * s->vals, st3[j], s->vals * 4, k, s->stream));
-            else HIPCHK(hipMemcpyAsync(st3[j], backup + j * s->vals, s->vals * 4, k, s->stream));
-        }
+        if (save) HIPCHK(hipMemcpyAsync(backup, s->state, 3 * s->vals * 4, k, s->stream));
+        else HIPCHK(hipMemcpyAsync(s->state, backup, 3 * s->vals * 4, k, s->stream));
         if (!save) {
             s->t = t_save;
             s->last_energy_step = -1;

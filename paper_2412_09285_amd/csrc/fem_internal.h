@@ -105,10 +105,11 @@ struct StepArgs {
     const Tile* tiles;
     const void* marg_cur;
     void* marg_nxt;
-    float* h;
+    float* h;                     // rows of h, m1, m2 are srow floats apart
     float* m1;
     float* m2;
-    float* grad;                  // may be null
+    int64_t srow;
+    float* grad;                  // may be null; [n][R(q)]
     double* epart;                // [n_tiles][NE][R] or null (no energies this step)
     const double* ctil;           // bMinCut: centred column sums C~ [inst][R][q]
     long long* cpart;             // bMinCut: column-sum partials of the new P [n_tiles][R][q]
@@ -148,8 +149,8 @@ hipError_t launch_manip_init(int kind, const LaunchGeom& g, int waves, const Ste
 // ctil = csum minus its mean over the states
 hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, double scale, double* csum,
                                  double* ctil, hipStream_t st);
-hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h,
-                        uint8_t* sigma, hipStream_t st);
+hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h, int64_t srow, uint8_t* sigma,
+                        hipStream_t st);
 hipError_t launch_transpose_sigma(int32_t n, int32_t R, const int32_t* sig_rn, uint8_t* sig_nr,
                                   hipStream_t st);
 hipError_t launch_eval(const Problem& p, const LaunchGeom& g, int waves, const Tile* tiles,

@@ -59,10 +59,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             // the row's own state first: its loads overlap the neighbour gather
             const size_t base = (size_t)i * R + rb;
+            const size_t sbase = (size_t)i * a.srow + rb;   // h, m1, m2 rows
             float hv[V], m1v[V], m2v[V], mnew[V], gv[V];
-            ld_state<V, NT>(a.h + base, hv);
-            ld_state<V, NT>(a.m1 + base, m1v);
-            ld_state<V, NT>(a.m2 + base, m2v);
+            ld_state<V, NT>(a.h + sbase, hv);
+            ld_state<V, NT>(a.m1 + sbase, m1v);
+            ld_state<V, NT>(a.m2 + sbase, m2v);
             // phi accumulates in double for float32 marginals (near
             // equilibrium g is a small difference of 2 phi and h / beta); a
             // bfloat16 copy carries 8 bits, so float accumulation is exact
@@ -114,9 +115,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 hv[v] = nh;
                 mnew[v] = tanhf(0.5f * nh);
             }
-            st_state<V, NT>(a.h + base, hv);
-            st_state<V, NT>(a.m1 + base, m1v);
-            st_state<V, NT>(a.m2 + base, m2v);
+            st_state<V, NT>(a.h + sbase, hv);
+            st_state<V, NT>(a.m1 + sbase, m1v);
+            st_state<V, NT>(a.m2 + sbase, m2v);
             st_marg<MT, V>(mn + base, mnew);
             if (a.grad) st_f32<V>(a.grad + base, gv);
         }
@@ -173,10 +174,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
         for (int s = 0; s < Q; ++s) ct[s] = (AccT)a.ctil[((size_t)tile.inst * R + r) * Q + s];
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             const size_t base = ((size_t)i * R + r) * Q;
+            const size_t sbase = (size_t)i * a.srow + (size_t)r * Q;   // h, m1, m2 rows
             float hv[Q], m1v[Q], m2v[Q];
-            ld_state<Q, NT>(a.h + base, hv);
-            ld_state<Q, NT>(a.m1 + base, m1v);
-            ld_state<Q, NT>(a.m2 + base, m2v);
+            ld_state<Q, NT>(a.h + sbase, hv);
+            ld_state<Q, NT>(a.m1 + sbase, m1v);
+            ld_state<Q, NT>(a.m2 + sbase, m2v);
             AccT phi[Q];
 #pragma unroll
             for (int s = 0; s < Q; ++s) phi[s] = (AccT)0;
@@ -268,9 +270,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
 #pragma unroll
                 for (int s = 0; s < Q; ++s) cs[s] += to_fixed((double)Pn[s]);
             }
-            st_state<Q, NT>(a.h + base, hv);
-            st_state<Q, NT>(a.m1 + base, m1v);
-            st_state<Q, NT>(a.m2 + base, m2v);
+            st_state<Q, NT>(a.h + sbase, hv);
+            st_state<Q, NT>(a.m1 + sbase, m1v);
+            st_state<Q, NT>(a.m2 + sbase, m2v);
             st_marg<MT, Q>(mn + base, Pn);
             if (a.grad) st_f32<Q>(a.grad + base, gv);
         }
@@ -332,10 +334,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
     if (act) {
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             const size_t base = (size_t)i * R + rb;
+            const size_t sbase = (size_t)i * a.srow + rb;   // h, m1, m2 rows
             float hv[V], m1v[V], m2v[V];
-            ld_state<V, NT>(a.h + base, hv);
-            ld_state<V, NT>(a.m1 + base, m1v);
-            ld_state<V, NT>(a.m2 + base, m2v);
+            ld_state<V, NT>(a.h + sbase, hv);
+            ld_state<V, NT>(a.m1 + sbase, m1v);
+            ld_state<V, NT>(a.m2 + sbase, m2v);
             float own_small[V];
             bool own_hi[V];
 #pragma unroll
@@ -401,9 +404,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 hv[v] = nh;
                 snew[v] = sat_encode(nh);
             }
-            st_state<V, NT>(a.h + base, hv);
-            st_state<V, NT>(a.m1 + base, m1v);
-            st_state<V, NT>(a.m2 + base, m2v);
+            st_state<V, NT>(a.h + sbase, hv);
+            st_state<V, NT>(a.m1 + sbase, m1v);
+            st_state<V, NT>(a.m2 + sbase, m2v);
             st_marg<MT, V>(mn + base, snew);
             if (a.grad) st_f32<V>(a.grad + base, gv);
         }
@@ -426,10 +429,12 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
 // encoding, or the softmax) into marg_nxt; for Potts also the column-sum
 // partials of those marginals.
 template <typename MT>
-__global__ void init_q1_kernel(int kind, const float* __restrict__ h, MT* __restrict__ out, size_t count)
+__global__ void init_q1_kernel(int kind, const float* __restrict__ h, int32_t R, int64_t srow, MT* __restrict__ out,
+                               size_t count)
 {
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
-        float x[1] = {kind == KIND_MAXSAT ? sat_encode(h[k]) : tanhf(0.5f * h[k])};
+        const float hv = h[(k / R) * srow + k % R];
+        float x[1] = {kind == KIND_MAXSAT ? sat_encode(hv) : tanhf(0.5f * hv)};
         st_marg<MT, 1>(out + k, x);
     }
 }
@@ -450,8 +455,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_init_
     if (act) {
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             const size_t base = ((size_t)i * R + r) * Q;
+            const size_t sbase = (size_t)i * a.srow + (size_t)r * Q;   // h, m1, m2 rows
             float hv[Q];
-            ld_f32<Q>(a.h + base, hv);
+            ld_f32<Q>(a.h + sbase, hv);
             float mx = hv[0];
 #pragma unroll
             for (int s = 1; s < Q; ++s) mx = fmaxf(mx, hv[s]);
@@ -561,15 +567,16 @@ __global__ void colsum_combine_kernel(int R, int q, int n_inst, const long long*
 
 // ================================================ read-out & evaluation ===
 // sigma[i][r] = argmax_s h_i^r(s), ties to the lowest state; one logit: h > 0.
-__global__ void round_kernel(int kind, int32_t n, int32_t R, int32_t q, const float* __restrict__ h,
+__global__ void round_kernel(int kind, int32_t n, int32_t R, int32_t q, const float* __restrict__ h, int64_t srow,
                              uint8_t* __restrict__ sigma)
 {
     const size_t count = (size_t)n * R;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = k / R, r = k % R;
         if (kind != KIND_BMINCUT) {
-            sigma[k] = h[k] > 0.0f ? 1 : 0;
+            sigma[k] = h[i * srow + r] > 0.0f ? 1 : 0;
         } else {
-            const float* x = h + k * q;
+            const float* x = h + i * srow + r * q;
             int best = 0;
             float bv = x[0];
             for (int s = 1; s < q; ++s)
@@ -818,9 +825,11 @@ hipError_t launch_init_marginals(int kind, int dtype, const LaunchGeom& g, int w
     }
     if (count == 0) return hipSuccess;
     if (dtype == 1)
-        init_q1_kernel<uint16_t><<<grid_for(count), 256, 0, st>>>(kind, a.h, static_cast<uint16_t*>(a.marg_nxt), count);
+        init_q1_kernel<uint16_t><<<grid_for(count), 256, 0, st>>>(kind, a.h, a.R, a.srow,
+                                                                 static_cast<uint16_t*>(a.marg_nxt), count);
     else
-        init_q1_kernel<float><<<grid_for(count), 256, 0, st>>>(kind, a.h, static_cast<float*>(a.marg_nxt), count);
+        init_q1_kernel<float><<<grid_for(count), 256, 0, st>>>(kind, a.h, a.R, a.srow, static_cast<float*>(a.marg_nxt),
+                                                              count);
     return hipGetLastError();
 }
 
@@ -855,12 +864,13 @@ hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, 
     return hipGetLastError();
 }
 
-hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h, uint8_t* sigma, hipStream_t st)
+hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h, int64_t srow, uint8_t* sigma,
+                        hipStream_t st)
 {
     (void)hipGetLastError();   // drop stale errors of earlier calls
     const size_t count = (size_t)n * R;
     if (count == 0) return hipSuccess;
-    round_kernel<<<grid_for(count), 256, 0, st>>>(kind, n, R, q, h, sigma);
+    round_kernel<<<grid_for(count), 256, 0, st>>>(kind, n, R, q, h, srow, sigma);
     return hipGetLastError();
 }
 

@@ -50,10 +50,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_manip
         uint32_t bits = 0;
         if (act) {
             const size_t base = (size_t)i * R + rb;
+            const size_t sbase = (size_t)i * a.srow + rb;   // h, m1, m2 rows
             float hv[V], m1v[V], m2v[V], gv[V];
-            ld_state<V, NT>(a.h + base, hv);
-            ld_state<V, NT>(a.m1 + base, m1v);
-            ld_state<V, NT>(a.m2 + base, m2v);
+            ld_state<V, NT>(a.h + sbase, hv);
+            ld_state<V, NT>(a.m1 + sbase, m1v);
+            ld_state<V, NT>(a.m2 + sbase, m2v);
             double acc[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) acc[v] = 0.0;
@@ -96,9 +97,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_manip
                 hv[v] = nh;
                 bits |= (nh > 0.0f ? 1u : 0u) << v;
             }
-            st_state<V, NT>(a.h + base, hv);
-            st_state<V, NT>(a.m1 + base, m1v);
-            st_state<V, NT>(a.m2 + base, m2v);
+            st_state<V, NT>(a.h + sbase, hv);
+            st_state<V, NT>(a.m1 + sbase, m1v);
+            st_state<V, NT>(a.m2 + sbase, m2v);
             if (a.grad) st_f32<V>(a.grad + base, gv);
         }
         // assemble the word from the G lanes that share it (OR of disjoint
@@ -111,7 +112,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_manip
 
 // sign bits of the fields: each half-wave forms one 32-bit word from 32
 // coalesced loads and a ballot
-__global__ void sign_bits_kernel(const float* __restrict__ h, int32_t n, int32_t R, int32_t rw,
+__global__ void sign_bits_kernel(const float* __restrict__ h, int64_t srow, int32_t n, int32_t R, int32_t rw,
                                  uint32_t* __restrict__ out)
 {
     const size_t words = (size_t)n * rw;
@@ -124,7 +125,7 @@ __global__ void sign_bits_kernel(const float* __restrict__ h, int32_t n, int32_t
         if (k < words) {
             const size_t i = k / rw;
             const int r = 32 * (int)(k % rw) + (lane & 31);
-            bit = r < R && h[i * R + r] > 0.0f;
+            bit = r < R && h[i * srow + r] > 0.0f;
         }
         const uint64_t m = __ballot(bit);
         if (lane == 0) out[p] = (uint32_t)m;
@@ -165,10 +166,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_manip
         for (int s = 0; s < Q; ++s) ct[s] = a.ctil[((size_t)tile.inst * R + r) * Q + s];
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             const size_t base = ((size_t)i * R + r) * Q;
+            const size_t sbase = (size_t)i * a.srow + (size_t)r * Q;   // h, m1, m2 rows
             float hv[Q], m1v[Q], m2v[Q];
-            ld_state<Q, NT>(a.h + base, hv);
-            ld_state<Q, NT>(a.m1 + base, m1v);
-            ld_state<Q, NT>(a.m2 + base, m2v);
+            ld_state<Q, NT>(a.h + sbase, hv);
+            ld_state<Q, NT>(a.m1 + sbase, m1v);
+            ld_state<Q, NT>(a.m2 + sbase, m2v);
             AccT phi[Q];
 #pragma unroll
             for (int s = 0; s < Q; ++s) phi[s] = (AccT)0;
@@ -229,9 +231,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_manip
             const int nw = argmax_low<Q>(hv);
 #pragma unroll
             for (int s = 0; s < Q; ++s) cs[s] += (nw == s) ? 1 : 0;
-            st_state<Q, NT>(a.h + base, hv);
-            st_state<Q, NT>(a.m1 + base, m1v);
-            st_state<Q, NT>(a.m2 + base, m2v);
+            st_state<Q, NT>(a.h + sbase, hv);
+            st_state<Q, NT>(a.m1 + sbase, m1v);
+            st_state<Q, NT>(a.m2 + sbase, m2v);
             en[(size_t)i * R + r] = (uint8_t)nw;
             if (a.grad) st_f32<Q>(a.grad + base, gv);
         }
@@ -260,7 +262,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_manip
     if (r < R) {
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             float hv[Q];
-            ld_f32<Q>(a.h + ((size_t)i * R + r) * Q, hv);
+            ld_f32<Q>(a.h + (size_t)i * a.srow + (size_t)r * Q, hv);
             const int b = argmax_low<Q>(hv);
 #pragma unroll
             for (int s = 0; s < Q; ++s) cs[s] += (b == s) ? 1 : 0;
@@ -321,7 +323,7 @@ hipError_t launch_manip_init(int kind, const LaunchGeom& geo, int waves, const S
         if (count == 0) return hipSuccess;
         const size_t blocks = (count + 7) / 8;
         sign_bits_kernel<<<(unsigned)(blocks < 65536 ? blocks : 65536), 256, 0, st>>>(
-            a.h, a.n, a.R, a.rw, static_cast<uint32_t*>(a.marg_nxt));
+            a.h, a.srow, a.n, a.R, a.rw, static_cast<uint32_t*>(a.marg_nxt));
         return hipGetLastError();
     }
     if (kind != KIND_BMINCUT) return hipErrorInvalidValue;

@@ -24,6 +24,7 @@ MAXCUT, BMINCUT, MAXSAT = 0, 1, 2
 SCHED_LINEAR, SCHED_EXP, SCHED_INVPROP = 0, 1, 2
 OPT_ADAM, OPT_RMSPROP, OPT_SGD = 0, 1, 2
 GRAD_EXPLICIT, GRAD_MANIPULATED = 0, 1
+STATE_SEPARATE, STATE_INTERLEAVED = 0, 1
 F32, BF16 = 0, 1
 
 
@@ -44,7 +45,7 @@ class Params(C.Structure):
         ("marginal_dtype", C.c_int32), ("energy_every", C.c_int32),
         ("record_energies", C.c_int32), ("eval_every", C.c_int32), ("keep_grad", C.c_int32),
         ("optimizer", C.c_int32), ("momentum", C.c_double), ("rms_alpha", C.c_double), ("dampening", C.c_double),
-        ("gradient", C.c_int32), ("gamma_grad", C.c_double),
+        ("gradient", C.c_int32), ("gamma_grad", C.c_double), ("state_layout", C.c_int32),
     ]
 
 
