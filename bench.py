@@ -74,7 +74,7 @@ def kernel_sources_sha(gradient):
     return h.hexdigest()
 
 
-def measured_traffic(path, gradient, tile, marginals, layout="separate"):
+def measured_traffic(path, gradient, tile, marginals, layout="interleaved"):
     """Bytes per launch from a committed counter summary, or None when the
     summary is missing or was taken with other kernel sources / launch shape."""
     if not os.path.exists(path):
@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50, help="untimed warm-up steps W")
     ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32")
     ap.add_argument("--gradient", choices=["explicit", "manipulated"], default="explicit")
-    ap.add_argument("--state-layout", choices=["separate", "interleaved"], default="separate",
+    ap.add_argument("--state-layout", choices=["separate", "interleaved"], default="interleaved",
                     help="device layout of h and the Adam moments (no effect on results)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
@@ -316,7 +316,7 @@ def throughput(args):
         alg_bytes = sat_kernel_bytes(n, R, nnz, mbytes, n_tiles)
         kname, counters = "sat_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    if args.state_layout != "separate":
+    if args.state_layout != "interleaved":
         counters = counters.replace("_hbm_counters", f"_{args.state_layout}_hbm_counters")
     traffic = measured_traffic(os.path.join(ROOT, "profiles", counters), args.gradient, tile, args.dtype,
                                args.state_layout)

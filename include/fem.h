@@ -154,7 +154,8 @@ typedef struct {
  * no result, only how the step kernels stream it, and every getter and setter
  * keeps the [n][R] / [n][R][q] layout of each array.
  *  FEM_STATE_SEPARATE: three arrays.
- *  FEM_STATE_INTERLEAVED: the three rows of a node next to each other. */
+ *  FEM_STATE_INTERLEAVED (default): the three rows of a node next to each
+ *    other, one contiguous stream per node instead of three. */
 enum { FEM_STATE_SEPARATE = 0, FEM_STATE_INTERLEAVED = 1 };
 
 /* Gradient with respect to the fields (supplementary "The explicit gradient
@@ -184,7 +185,7 @@ enum { FEM_OPT_ADAM = 0, FEM_OPT_RMSPROP = 1, FEM_OPT_SGD = 2 };
 /* Adam 0.9 / 0.999 / 1e-8, lr 0.1, no weight decay, linear beta 0.01 -> 5,
  * R = 16, T = 500, F32 marginals, energies every step, no recording;
  * RMSprop alpha 0.99, no momentum or dampening; explicit gradients,
- * gamma_grad 1. */
+ * gamma_grad 1; interleaved state layout. */
 void fem_params_default(fem_params* p);
 
 /* hip_stream: a hipStream_t on the problem's device (NULL = the null stream).

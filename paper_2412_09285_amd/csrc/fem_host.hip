@@ -1037,7 +1037,7 @@ void fem_params_default(fem_params* p)
     p->dampening = 0.0;
     p->gradient = FEM_GRAD_EXPLICIT;
     p->gamma_grad = 1.0;
-    p->state_layout = FEM_STATE_SEPARATE;
+    p->state_layout = FEM_STATE_INTERLEAVED;
 }
 
 fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void* hip_stream, fem_solver** out)
@@ -1664,7 +1664,7 @@ static std::string tune_key(const fem_solver* s)
              (long long)s->prob->nnz, s->R, s->q, s->dtype, s->n_inst, s->prm.energy_every > 0 ? 1 : 0,
              s->manip ? 1 : 0);
     std::string key = buf;
-    if (s->prm.state_layout == FEM_STATE_INTERLEAVED) key += "_sl1";
+    if (s->prm.state_layout == FEM_STATE_SEPARATE) key += "_sl0";
     return key;
 }
 
