@@ -51,7 +51,7 @@ class _Problem(C.Structure):
         ("lr", C.c_double), ("b1", C.c_double), ("b2", C.c_double),
         ("eps", C.c_double), ("wd", C.c_double),
         ("opt", C.c_int32), ("momentum", C.c_double), ("rms_alpha", C.c_double), ("dampening", C.c_double),
-        ("manip", C.c_int32), ("gamma", C.c_double),
+        ("manip", C.c_int32), ("gamma", C.c_double), ("nw", C.c_void_p),
     ]
 
 
@@ -69,7 +69,7 @@ def lib():
         L.orc_maxcut_grad.restype = C.c_int
         L.orc_maxcut_grad.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, C.c_double, P, P, P]
         L.orc_bmincut_grad.restype = C.c_int
-        L.orc_bmincut_grad.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, C.c_double,
+        L.orc_bmincut_grad.argtypes = [C.c_int32, C.c_int64, P, P, P, P, C.c_int32, C.c_double,
                                        C.c_int32, P, C.c_double, P, P, P]
         L.orc_maxsat_grad.restype = C.c_int
         L.orc_maxsat_grad.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P, C.c_double, P, P, P]
@@ -77,7 +77,7 @@ def lib():
         L.orc_maxcut_grad_manip.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, C.c_double,
                                             C.c_double, P]
         L.orc_bmincut_grad_manip.restype = C.c_int
-        L.orc_bmincut_grad_manip.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, C.c_double,
+        L.orc_bmincut_grad_manip.argtypes = [C.c_int32, C.c_int64, P, P, P, P, C.c_int32, C.c_double,
                                              C.c_int32, P, C.c_double, C.c_double, P]
         L.orc_maxsat_grad_manip.restype = C.c_int
         L.orc_maxsat_grad_manip.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P, C.c_double,
@@ -95,7 +95,7 @@ def lib():
         L.orc_cut.restype = None
         L.orc_cut.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, P]
         L.orc_group_sizes.restype = None
-        L.orc_group_sizes.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P]
+        L.orc_group_sizes.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P]
         L.orc_unsat.restype = None
         L.orc_unsat.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P, P]
         L.orc_run.restype = C.c_int
@@ -148,15 +148,16 @@ def maxcut_grad(n, u, v, w, h, beta_, want_grad=True):
     return g, U, S
 
 
-def bmincut_grad(n, u, v, w, q, lam_, h, beta_, want_grad=True):
-    """h: [n][R][q] float64."""
+def bmincut_grad(n, u, v, w, q, lam_, h, beta_, want_grad=True, node_w=None):
+    """h: [n][R][q] float64; node_w: node weights V (None: all 1)."""
     h = _f64(h)
     R = h.shape[1]
     u, v, w = _i32(u), _i32(v), _f64(w)
+    V = None if node_w is None else _f64(node_w)
     g = np.zeros_like(h) if want_grad else None
     U = np.zeros(R)
     S = np.zeros(R)
-    rc = lib().orc_bmincut_grad(n, u.shape[0], _p(u), _p(v), _p(w), q, lam_, R, _p(h), beta_,
+    rc = lib().orc_bmincut_grad(n, u.shape[0], _p(u), _p(v), _p(w), _p(V), q, lam_, R, _p(h), beta_,
                                 _p(g), _p(U), _p(S))
     if rc:
         raise MemoryError(rc)
@@ -188,12 +189,13 @@ def maxcut_grad_manip(n, u, v, w, h, beta_, gamma=1.0):
     return g
 
 
-def bmincut_grad_manip(n, u, v, w, q, lam_, h, beta_, gamma=1.0):
+def bmincut_grad_manip(n, u, v, w, q, lam_, h, beta_, gamma=1.0, node_w=None):
     """Manipulated bMinCut gradient; h: [n][R][q] float64.  Returns g."""
     h = _f64(h)
     u, v, w = _i32(u), _i32(v), _f64(w)
+    V = None if node_w is None else _f64(node_w)
     g = np.zeros_like(h)
-    rc = lib().orc_bmincut_grad_manip(n, u.shape[0], _p(u), _p(v), _p(w), q, lam_, h.shape[1], _p(h), beta_,
+    rc = lib().orc_bmincut_grad_manip(n, u.shape[0], _p(u), _p(v), _p(w), _p(V), q, lam_, h.shape[1], _p(h), beta_,
                                       gamma, _p(g))
     if rc:
         raise MemoryError(rc)
@@ -256,11 +258,14 @@ def cut(n, u, v, w, sigma):
     return out
 
 
-def group_sizes(n, q, sigma):
+def group_sizes(n, q, sigma, node_w=None):
+    """Per replica and state, the summed node weight (the node count when
+    node_w is None) of the nodes in that state."""
     sigma = _i32(sigma)
     R = sigma.shape[0]
+    V = None if node_w is None else _i32(node_w)
     out = np.zeros((R, q), dtype=np.int64)
-    lib().orc_group_sizes(n, q, R, _p(sigma), _p(out))
+    lib().orc_group_sizes(n, q, R, _p(sigma), _p(V), _p(out))
     return out
 
 
@@ -301,7 +306,8 @@ class Params:
 class Run:
     """Holds one FP64 FEM run: h, m1, m2 and the step counter t."""
 
-    def __init__(self, kind, params: Params, h0, *, n, q=1, u=None, v=None, w=None, off=None, lits=None):
+    def __init__(self, kind, params: Params, h0, *, n, q=1, u=None, v=None, w=None, off=None, lits=None,
+                 node_w=None):
         self.kind, self.p, self.n, self.q = kind, params, n, q
         self.h = _f64(h0).copy()
         self.m1 = np.zeros_like(self.h)
@@ -326,6 +332,8 @@ class Run:
         pb.opt, pb.momentum, pb.rms_alpha, pb.dampening = params.opt, params.momentum, params.rms_alpha, \
             params.dampening
         pb.manip, pb.gamma = int(params.manip), params.gamma
+        self.node_w = None if node_w is None else _f64(node_w)
+        pb.nw = None if self.node_w is None else self.node_w.ctypes.data
         self._pb = pb
 
     def step(self, n_steps: int, record: bool = False):
@@ -361,7 +369,7 @@ class Run:
             if self.kind == KIND_BMINCUT:
                 u, v, w = self._keep
                 return bmincut_grad_manip(self.n, u, v, w, self.q, lam(p.lam_ramp, p.lam, p.T, t), h, b,
-                                          p.gamma), None, None
+                                          p.gamma, node_w=self.node_w), None, None
             off, lits = self._keep
             return maxsat_grad_manip(self.n, off, lits, h, b, p.gamma), None, None
         if self.kind == KIND_MAXCUT:
@@ -369,7 +377,7 @@ class Run:
             return maxcut_grad(self.n, u, v, w, h, b)
         if self.kind == KIND_BMINCUT:
             u, v, w = self._keep
-            return bmincut_grad(self.n, u, v, w, self.q, lam(p.lam_ramp, p.lam, p.T, t), h, b)
+            return bmincut_grad(self.n, u, v, w, self.q, lam(p.lam_ramp, p.lam, p.T, t), h, b, node_w=self.node_w)
         off, lits = self._keep
         return maxsat_grad(self.n, off, lits, h, b)
 
@@ -391,8 +399,8 @@ def maxcut_run(graph, params: Params, h0):
     return Run(KIND_MAXCUT, params, h0, n=graph.n, u=graph.u, v=graph.v, w=graph.w)
 
 
-def bmincut_run(graph, q, params: Params, h0):
-    return Run(KIND_BMINCUT, params, h0, n=graph.n, q=q, u=graph.u, v=graph.v, w=graph.w)
+def bmincut_run(graph, q, params: Params, h0, node_w=None):
+    return Run(KIND_BMINCUT, params, h0, n=graph.n, q=q, u=graph.u, v=graph.v, w=graph.w, node_w=node_w)
 
 
 def maxsat_run(cnf, params: Params, h0):

@@ -153,15 +153,17 @@ int orc_maxcut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
 /* ------------------------------------------------------------------------- */
 
 /*
- * For every replica r: P_i(s) = softmax_s h_i(s), C(s) = sum_j P_j(s);
+ * For every replica r: P_i(s) = softmax_s h_i(s), node weights V_i (1 when
+ * V is NULL; the supplementary chip-partitioning section, where coarsened
+ * nodes carry the number of nodes they group), C(s) = sum_j V_j P_j(s);
  *   U = sum_{ordered (i,j)} W_ij sum_s P_i(s)[1 - P_j(s)]
- *     + lam * sum_s [C(s)^2 - sum_i P_i(s)^2]
+ *     + lam * sum_s [C(s)^2 - sum_i V_i^2 P_i(s)^2]
  *   S = -sum_i sum_s P_i(s) ln P_i(s)
- *   g^p_i(s) = -2 sum_j W_ij P_j(s) + 2 lam [C(s) - P_i(s)] + (ln P_i(s) + 1)/beta
+ *   g^p_i(s) = -2 sum_j W_ij P_j(s) + 2 lam V_i [C(s) - V_i P_i(s)] + (ln P_i(s) + 1)/beta
  *   g^h_i(s) = [g^p_i(s) - sum_s' P_i(s') g^p_i(s')] P_i(s)
  */
 int orc_bmincut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
-                     const double* w, int32_t q, double lam, int32_t R,
+                     const double* w, const double* V, int32_t q, double lam, int32_t R,
                      const double* h, double beta, double* g, double* U, double* S)
 {
     size_t nq = (size_t)n * (size_t)q;
@@ -190,7 +192,7 @@ int orc_bmincut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev
         }
         for (int32_t s = 0; s < q; ++s) C[s] = 0.0;
         for (int32_t i = 0; i < n; ++i)
-            for (int32_t s = 0; s < q; ++s) C[s] += P[(size_t)i * q + s];
+            for (int32_t s = 0; s < q; ++s) C[s] += (V ? V[i] : 1.0) * P[(size_t)i * q + s];
         for (size_t k = 0; k < nq; ++k) Phi[k] = 0.0;
         double cut_acc = 0.0;
         for (int64_t e = 0; e < ne; ++e) {
@@ -208,7 +210,10 @@ int orc_bmincut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev
         double bal = 0.0;
         for (int32_t s = 0; s < q; ++s) {
             double self = 0.0;
-            for (int32_t i = 0; i < n; ++i) self += P[(size_t)i * q + s] * P[(size_t)i * q + s];
+            for (int32_t i = 0; i < n; ++i) {
+                double vp = (V ? V[i] : 1.0) * P[(size_t)i * q + s];
+                self += vp * vp;
+            }
             bal += C[s] * C[s] - self;
         }
         double s_acc = 0.0;
@@ -220,7 +225,8 @@ int orc_bmincut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev
                 double avg = 0.0;
                 for (int32_t s = 0; s < q; ++s) {
                     size_t k = (size_t)i * q + s;
-                    gp[s] = -2.0 * Phi[k] + 2.0 * lam * (C[s] - P[k]) + (lnP[k] + 1.0) / beta;
+                    double vi = V ? V[i] : 1.0;
+                    gp[s] = -2.0 * Phi[k] + 2.0 * lam * vi * (C[s] - vi * P[k]) + (lnP[k] + 1.0) / beta;
                     avg += P[k] * gp[s];
                 }
                 for (int32_t s = 0; s < q; ++s) {
@@ -380,15 +386,16 @@ int orc_maxcut_grad_manip(int32_t n, int64_t ne, const int32_t* eu, const int32_
 }
 
 /*
- * bMinCut, q states, P_i = softmax h_i, weights W_ij > 0, lam = lambda(t):
- *   ghat_i(s) = -c^f_i sum_j W_ij e_j(s) + lam c^a_i [sum_j e_j(s) - e_i(s)]
+ * bMinCut, q states, P_i = softmax h_i, weights W_ij > 0, lam = lambda(t),
+ * node weights V_i (1 when V is NULL):
+ *   ghat_i(s) = -c^f_i sum_j W_ij e_j(s) + lam c^a_i V_i [sum_j V_j e_j(s) - V_i e_i(s)]
  *               + (ln P_i(s) + 1) / beta,
  *   c^f_i = q / sum_j W_ij,  c^a_i = q / sqrt(sum_j W_ij),
- * where sum_j e_j(s) runs over all nodes (the size of group s in the
+ * where sum_j V_j e_j(s) runs over all nodes (the weight of group s in the
  * current read-out).
  */
 int orc_bmincut_grad_manip(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
-                           const double* w, int32_t q, double lam, int32_t R,
+                           const double* w, const double* V, int32_t q, double lam, int32_t R,
                            const double* h, double beta, double gamma, double* g)
 {
     size_t nq = (size_t)n * (size_t)q;
@@ -413,7 +420,7 @@ int orc_bmincut_grad_manip(int32_t n, int64_t ne, const int32_t* eu, const int32
             int32_t best = 0;
             for (int32_t s = 1; s < q; ++s) if (hi[s] > hi[best]) best = s;
             e1[i] = best;
-            cnt[best] += 1.0;
+            cnt[best] += V ? V[i] : 1.0;
         }
         for (size_t k = 0; k < nq; ++k) F[k] = 0.0;
         for (int64_t e = 0; e < ne; ++e) {
@@ -433,8 +440,9 @@ int orc_bmincut_grad_manip(int32_t n, int64_t ne, const int32_t* eu, const int32
             double ca = D[i] > 0.0 ? (double)q / sqrt(D[i]) : 0.0;
             double avg = 0.0;
             for (int32_t s = 0; s < q; ++s) {
-                double own = (e1[i] == s) ? 1.0 : 0.0;
-                gh[s] = -cf * F[(size_t)i * q + s] + lam * ca * (cnt[s] - own) + (lnP[s] + 1.0) / beta;
+                double vi = V ? V[i] : 1.0;
+                double own = (e1[i] == s) ? vi : 0.0;
+                gh[s] = -cf * F[(size_t)i * q + s] + lam * ca * vi * (cnt[s] - own) + (lnP[s] + 1.0) / beta;
                 avg += exp(lnP[s]) * gh[s];
             }
             for (int32_t s = 0; s < q; ++s)
@@ -548,11 +556,11 @@ void orc_cut(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev, const 
 }
 
 /* Group sizes |Pi_s| = #{i : sigma_i = s} per replica, [R][q]. */
-void orc_group_sizes(int32_t n, int32_t q, int32_t R, const int32_t* sigma, int64_t* sizes)
+void orc_group_sizes(int32_t n, int32_t q, int32_t R, const int32_t* sigma, const int32_t* V, int64_t* sizes)
 {
     for (int32_t r = 0; r < R; ++r) {
         for (int32_t s = 0; s < q; ++s) sizes[(size_t)r * q + s] = 0;
-        for (int32_t i = 0; i < n; ++i) sizes[(size_t)r * q + sigma[(size_t)r * n + i]] += 1;
+        for (int32_t i = 0; i < n; ++i) sizes[(size_t)r * q + sigma[(size_t)r * n + i]] += V ? V[i] : 1;
     }
 }
 
@@ -597,6 +605,7 @@ typedef struct {
     double momentum, rms_alpha, dampening;
     int32_t manip;          /* 1: manipulated gradients (no energies) */
     double gamma;           /* gamma_grad of the manipulated form */
+    const double* nw;       /* bMinCut node weights (NULL: all 1) */
 } orc_problem;
 
 int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, double* m1,
@@ -615,7 +624,7 @@ int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, doubl
         if (pb->manip && pb->kind == 0)
             rc = orc_maxcut_grad_manip(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->R, h, beta, pb->gamma, g);
         else if (pb->manip && pb->kind == 1)
-            rc = orc_bmincut_grad_manip(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->q,
+            rc = orc_bmincut_grad_manip(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->nw, pb->q,
                                         orc_lambda(pb->lam_ramp, pb->lam, pb->T, t), pb->R, h, beta,
                                         pb->gamma, g);
         else if (pb->manip)
@@ -623,7 +632,7 @@ int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, doubl
         else if (pb->kind == 0)
             rc = orc_maxcut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->R, h, beta, g, U, S);
         else if (pb->kind == 1)
-            rc = orc_bmincut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->q,
+            rc = orc_bmincut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->nw, pb->q,
                                   orc_lambda(pb->lam_ramp, pb->lam, pb->T, t), pb->R, h, beta, g, U, S);
         else
             rc = orc_maxsat_grad(pb->n, pb->ne, pb->off, pb->lits, pb->R, h, beta, g, U, S);
