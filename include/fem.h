@@ -90,6 +90,19 @@ fem_status fem_maxcut_create(int device, int32_t n, int64_t n_edges, const int32
 fem_status fem_bmincut_create(int device, int32_t n, int64_t n_edges, const int32_t* u,
                               const int32_t* v, const float* w, int32_t q, fem_problem** out);
 
+/* bMinCut with node weights V_i (the community sizes of a coarsened graph,
+ * Methods, multilevel bMinCut): the balance term becomes
+ * lambda * sum_s [W_s^2 - sum_i V_i^2 delta(sigma_i, s)] with W_s the summed
+ * weight of group s, and its mean-field form
+ * lambda * sum_s [(sum_i V_i P_i(s))^2 - sum_i V_i^2 P_i(s)^2].  node_weight:
+ * host, n entries, each >= 1 (FEM_E_INVAL otherwise, also for NULL); their
+ * sum must not exceed 2^22 (FEM_E_UNSUPPORTED).  All weights 1 is the same
+ * problem as fem_bmincut_create.  Group sizes reported by fem_eval_int are
+ * then group weights W_s. */
+fem_status fem_bmincut_create_weighted(int device, int32_t n, int64_t n_edges, const int32_t* u,
+                                       const int32_t* v, const float* w, int32_t q,
+                                       const int32_t* node_weight, fem_problem** out);
+
 /* Max-k-SAT (Results, "Application to the Max k-SAT problem"): energy = number
  * of unsatisfied clauses.  DIMACS-style literals +(x+1) / -(x+1) on host;
  * clause_off has n_clauses+1 nondecreasing entries starting at 0.  A repeated
@@ -239,19 +252,21 @@ fem_status fem_energy_history(fem_solver* s, int32_t first, int32_t count, doubl
 fem_status fem_round(fem_solver* s, int32_t* sigma);
 /* Integer evaluation of host configurations sigma [R][n]: value[B][R] is the
  * cut (MaxCut, bMinCut; each edge once) or the number of unsatisfied clauses
- * (Max-k-SAT); sizes[B][R][q] the group sizes for bMinCut (may be NULL).
+ * (Max-k-SAT); sizes[B][R][q] the group sizes for bMinCut, summed node weights
+ * for a weighted problem (may be NULL).
  * Exact for integral weights (|total| < 2^53). */
 fem_status fem_eval_int(const fem_problem* p, int32_t R, const int32_t* sigma, int64_t* value,
                         int64_t* sizes);
 /* Round the current fields, evaluate, and return per instance the best
  * replica (max cut; min unsat; min 2*cut + lambda*sum_s |Pi_s|(|Pi_s|-1) for
- * bMinCut; ties to the lowest replica index), its value, and (if sigma is not
+ * bMinCut, 2*cut + lambda*(sum_s W_s^2 - sum_i V_i^2) with node weights;
+ * ties to the lowest replica index), its value, and (if sigma is not
  * NULL) its configuration as int32 over all n nodes.  replica, value: [B]. */
 fem_status fem_best(fem_solver* s, int32_t* replica, int64_t* value, int32_t* sigma);
 /* Best value seen by the anytime read-out so far, [B][R] (eval_every > 0):
  * the cut (MaxCut; -inf before the first read-out), the number of unsatisfied
  * clauses (Max-k-SAT) or the integer energy 2*cut + lambda*sum_s
- * |Pi_s|(|Pi_s|-1) (bMinCut); +inf before the first read-out otherwise. */
+ * |Pi_s|(|Pi_s|-1) (bMinCut; with node weights as in fem_best); +inf before the first read-out otherwise. */
 fem_status fem_anytime_best(fem_solver* s, double* value);
 
 /* Checkpoint: bytes needed / write / restore (h, Adam moments, t).  Resuming

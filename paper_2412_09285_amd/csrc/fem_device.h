@@ -202,7 +202,7 @@ __device__ __forceinline__ long long to_fixed(double p) { return (long long)rint
 // over all nodes of float32 marginals would carry their rounding into the
 // global balance term.
 template <int Q>
-__device__ __forceinline__ void colsum_add(const float (&h)[Q], long long (&cs)[Q])
+__device__ __forceinline__ void colsum_add(const float (&h)[Q], long long (&cs)[Q], double vw = 1.0)
 {
     float mx = h[0];
 #pragma unroll
@@ -213,7 +213,7 @@ __device__ __forceinline__ void colsum_add(const float (&h)[Q], long long (&cs)[
         e[s] = exp((double)h[s] - (double)mx);
         Z += e[s];
     }
-    const double iz = 1.0 / Z;
+    const double iz = vw / Z;   // node weight times the normaliser
 #pragma unroll
     for (int s = 0; s < Q; ++s) cs[s] += to_fixed(e[s] * iz);
 }

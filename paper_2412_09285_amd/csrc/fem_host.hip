@@ -98,6 +98,9 @@ static void free_problem_device(Problem& p)
     dfree(p.inc4);
     dfree(p.wdeg);
     dfree(p.nrm);
+    dfree(p.nw);
+    dfree(p.v2);
+    dfree(p.dense_w);
 }
 
 static fem_status upload_problem(Problem& p)
@@ -125,6 +128,14 @@ static fem_status upload_problem(Problem& p)
         HIPCHK(dalloc(&p.nrm, p.h_nrm.size()));
         HIPCHK(hipMemcpy(p.nrm, p.h_nrm.data(), p.h_nrm.size() * sizeof(double), hipMemcpyHostToDevice));
     }
+    if (!p.h_nw.empty()) {
+        HIPCHK(dalloc(&p.nw, p.h_nw.size()));
+        HIPCHK(hipMemcpy(p.nw, p.h_nw.data(), p.h_nw.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    if (!p.inst_v2.empty()) {
+        HIPCHK(dalloc(&p.v2, p.inst_v2.size()));
+        HIPCHK(hipMemcpy(p.v2, p.inst_v2.data(), p.inst_v2.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     return FEM_OK;
 }
 
@@ -140,11 +151,25 @@ static fem_status check_device(int device)
 // Symmetric CSR of an undirected edge list: each edge {u,v} appears in row u
 // and row v; columns sorted within a row.
 static fem_status build_graph(int kind, int device, int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v,
-                              const float* w, int32_t q, fem_problem** out)
+                              const float* w, int32_t q, const int32_t* node_w, fem_problem** out)
 {
     if (!out) return fail(FEM_E_INVAL, "out is NULL");
     *out = nullptr;
     if (n < 1) return fail(FEM_E_INVAL, "n must be >= 1 (got %d)", n);
+    double v2 = (double)n;
+    if (node_w) {
+        // fixed-point column sums hold sum_i V_i P_i(s) * 2^40 in int64, and
+        // group weights are squared exactly in double: sum_i V_i <= 2^22
+        int64_t vsum = 0;
+        v2 = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            if (node_w[i] < 1) return fail(FEM_E_INVAL, "node %d: weight must be >= 1 (got %d)", i, node_w[i]);
+            vsum += node_w[i];
+            if (vsum > ((int64_t)1 << 22))
+                return fail(FEM_E_UNSUPPORTED, "sum of node weights exceeds 2^22");
+            v2 += (double)node_w[i] * (double)node_w[i];
+        }
+    }
     if (n_edges < 0) return fail(FEM_E_INVAL, "n_edges must be >= 0");
     if (n_edges > 0 && (!u || !v)) return fail(FEM_E_INVAL, "u and v must not be NULL");
     if (2 * n_edges > (int64_t)INT32_MAX * 8) return fail(FEM_E_UNSUPPORTED, "too many edges");
@@ -185,6 +210,10 @@ static fem_status build_graph(int kind, int device, int32_t n, int64_t n_edges, 
     p.integral = integral;
     p.inst_off = {0, n};
     p.inst_wtot = {wtot};
+    if (kind == KIND_BMINCUT) {
+        p.inst_v2 = {v2};
+        if (node_w) p.h_nw.assign(node_w, node_w + n);
+    }
     std::vector<int64_t>& ro = p.h_row_off;
     ro.assign((size_t)n + 1, 0);
     for (int64_t e = 0; e < n_edges; ++e) {
@@ -608,6 +637,7 @@ static StepArgs base_args(const fem_solver* s)
     a.inc4 = p.inc4;
     a.wdeg = p.wdeg;
     a.nrm = p.nrm;
+    a.nw = p.nw;
     a.tiles = s->d_tiles;
     a.h = s->h;
     a.m1 = s->m1;
@@ -665,7 +695,7 @@ static fem_status readout_eval(fem_solver* s, const uint8_t* sigma_in, bool upda
         HIPCHK(launch_sizes_widen((size_t)s->n_inst * s->R * s->q, s->sint, s->sout, s->stream));
     }
     if (update_best)
-        HIPCHK(launch_best_update(s->kind, s->R, s->n_inst, s->q, s->prm.lambda, s->vout, s->sout, s->best,
+        HIPCHK(launch_best_update(s->kind, s->R, s->n_inst, s->q, s->prm.lambda, s->vout, s->sout, p.v2, s->best,
                                   s->stream));
     return FEM_OK;
 }
@@ -803,7 +833,7 @@ int32_t fem_abi_version(void) { return 2; }
 fem_status fem_maxcut_create(int device, int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v,
                              const float* w, fem_problem** out)
 {
-    return build_graph(KIND_MAXCUT, device, n, n_edges, u, v, w, 2, out);
+    return build_graph(KIND_MAXCUT, device, n, n_edges, u, v, w, 2, nullptr, out);
 }
 
 fem_status fem_bmincut_create(int device, int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v,
@@ -812,7 +842,17 @@ fem_status fem_bmincut_create(int device, int32_t n, int64_t n_edges, const int3
     if (q < 2) return fail(FEM_E_INVAL, "q must be >= 2 (got %d)", q);
     if (q != 2 && q != 4 && q != 8 && q != 16 && q != 32)
         return fail(FEM_E_UNSUPPORTED, "q = %d: this build supports q in {2, 4, 8, 16, 32}", q);
-    return build_graph(KIND_BMINCUT, device, n, n_edges, u, v, w, q, out);
+    return build_graph(KIND_BMINCUT, device, n, n_edges, u, v, w, q, nullptr, out);
+}
+
+fem_status fem_bmincut_create_weighted(int device, int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v,
+                                       const float* w, int32_t q, const int32_t* node_weight, fem_problem** out)
+{
+    if (!node_weight) return fail(FEM_E_INVAL, "node_weight is NULL");
+    if (q < 2) return fail(FEM_E_INVAL, "q must be >= 2 (got %d)", q);
+    if (q != 2 && q != 4 && q != 8 && q != 16 && q != 32)
+        return fail(FEM_E_UNSUPPORTED, "q = %d: this build supports q in {2, 4, 8, 16, 32}", q);
+    return build_graph(KIND_BMINCUT, device, n, n_edges, u, v, w, q, node_weight, out);
 }
 
 fem_status fem_maxsat_create(int device, int32_t n_vars, int64_t n_clauses, const int64_t* clause_off,
@@ -847,11 +887,18 @@ fem_status fem_batch_create(int32_t nparts, fem_problem* const* parts, fem_probl
     for (int b = 0; b < nparts; ++b) p.sat_width = std::max(p.sat_width, parts[b]->p.sat_width);
     p.inst_off.assign(1, 0);
     p.h_row_off.assign(1, 0);
+    bool weighted = false;
+    for (int b = 0; b < nparts; ++b) weighted = weighted || !parts[b]->p.h_nw.empty();
     for (int b = 0; b < nparts; ++b) {
         const Problem& pb = parts[b]->p;
         for (size_t k = 0; k + 1 < pb.inst_off.size(); ++k) {
             p.inst_off.push_back(p.n + pb.inst_off[k + 1]);
             p.inst_wtot.push_back(pb.inst_wtot[k]);
+        }
+        p.inst_v2.insert(p.inst_v2.end(), pb.inst_v2.begin(), pb.inst_v2.end());
+        if (weighted) {   // unit weights for the parts that have none
+            if (pb.h_nw.empty()) p.h_nw.insert(p.h_nw.end(), (size_t)pb.n, 1);
+            else p.h_nw.insert(p.h_nw.end(), pb.h_nw.begin(), pb.h_nw.end());
         }
         const int64_t base = p.nnz;
         const int32_t noff = p.n;
@@ -1473,10 +1520,10 @@ fem_status fem_best(fem_solver* s, int32_t* replica, int64_t* value, int32_t* si
             if (s->kind == KIND_MAXCUT) score = -v[k];
             else if (s->kind == KIND_MAXSAT) score = v[k];
             else {
-                double pen = 0.0;
+                double pen = -s->prob->inst_v2[(size_t)b];
                 for (int c = 0; c < s->q; ++c) {
                     const double x = (double)sz[k * s->q + c];
-                    pen += x * (x - 1.0);
+                    pen += x * x;
                 }
                 score = v[k] + lamf * pen;
             }

@@ -37,6 +37,12 @@ struct Problem {
     int4* inc4 = nullptr;            // Max-k-SAT, <= 3 other literals per incidence
     float* wdeg = nullptr;           // bMinCut: sum_j W_ij per node
     double* nrm = nullptr;           // graphs: sum_j |W_ij| per node (normalisers of the manipulated gradients)
+    int32_t* nw = nullptr;           // bMinCut node weights V_i (null: all 1)
+    double* v2 = nullptr;            // bMinCut: [n_inst] sum_i V_i^2 per instance
+    // dense MaxCut: W as a zero-padded row-major float matrix [dense_ld][dense_ld]
+    // (the CSR above is still built, for read-out and evaluation)
+    float* dense_w = nullptr;
+    int32_t dense_ld = 0;
     // host copies kept for batching and validation
     std::vector<int64_t> h_row_off;
     std::vector<int2> h_adj;
@@ -44,6 +50,8 @@ struct Problem {
     std::vector<int4> h_inc4;
     std::vector<float> h_wdeg;
     std::vector<double> h_nrm;
+    std::vector<int32_t> h_nw;       // empty: unit node weights
+    std::vector<double> inst_v2;     // host [n_inst] sum_i V_i^2 (the node count for unit weights)
 };
 
 // Marginal-copy literal packing for Max-k-SAT incidence records:
@@ -102,6 +110,7 @@ struct StepArgs {
     const int4* inc4;
     const float* wdeg;
     const double* nrm;            // per-node sum_j |W_ij| (manipulated gradients)
+    const int32_t* nw;            // bMinCut node weights (null: all 1)
     const Tile* tiles;
     const void* marg_cur;
     void* marg_nxt;
@@ -157,8 +166,10 @@ hipError_t launch_eval(const Problem& p, const LaunchGeom& g, int waves, const T
                        int32_t R, const uint8_t* sigma, double* vpart, int* spart,
                        hipStream_t st);
 hipError_t launch_sizes_widen(size_t count, const int* in, long long* out, hipStream_t st);
+// v2: bMinCut per-instance sum_i V_i^2 (the constant that makes the balance
+// penalty vanish on a perfect split of unit weights)
 hipError_t launch_best_update(int kind, int R, int n_inst, int q, double lam, const double* vout,
-                              const long long* sout, double* best, hipStream_t st);
+                              const long long* sout, const double* v2, double* best, hipStream_t st);
 
 }  // namespace fem
 

@@ -220,9 +220,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             // The mean is normalised by the sum of the float32 marginals, so
             // their rounding perturbs only the weights, by a relative amount,
             // and the error scales with the spread of A, not its size.
-            const CT lam2 = (CT)2 * (CT)sc.lam_d, ib = (CT)sc.inv_beta_d;
+            // node weight V_i scales the balance term: 2 lam V_i [C~(s) - V_i P_i(s)]
+            const float vw = a.nw ? (float)a.nw[i] : 1.0f;
+            const CT lam2 = (CT)2 * (CT)sc.lam_d * (CT)vw, ib = (CT)sc.inv_beta_d;
             auto Aof = [&](int s) {
-                return (CT)-2 * (CT)phi[s] + lam2 * ((CT)ct[s] - (CT)P[s]) + ((CT)hv[s] - (CT)mx) * ib;
+                return (CT)-2 * (CT)phi[s] + lam2 * ((CT)ct[s] - (CT)vw * (CT)P[s]) + ((CT)hv[s] - (CT)mx) * ib;
             };
             CT avg = 0, psum = 0;
 #pragma unroll
@@ -241,7 +243,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
 #pragma unroll
                 for (int s = 0; s < Q; ++s) {
                     dot = fma((double)P[s], (double)phi[s], dot);
-                    sq = fmaf(P[s], P[s], sq);
+                    sq = fmaf(vw * P[s], vw * P[s], sq);
                     ent = fmaf(-P[s], hv[s] - mx - lz, ent);
                 }
                 eacc[0] += (double)a.wdeg[i] - dot;
@@ -265,10 +267,10 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             // into the balance term); the float softmax for bfloat16 ones,
             // whose own rounding is 2^-8
             if constexpr (sizeof(MT) == 4) {
-                colsum_add<Q>(hv, cs);
+                colsum_add<Q>(hv, cs, (double)vw);
             } else {
 #pragma unroll
-                for (int s = 0; s < Q; ++s) cs[s] += to_fixed((double)Pn[s]);
+                for (int s = 0; s < Q; ++s) cs[s] += to_fixed((double)vw * (double)Pn[s]);
             }
             st_state<Q, NT>(a.h + sbase, hv);
             st_state<Q, NT>(a.m1 + sbase, m1v);
@@ -467,7 +469,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_init_
             const float invZ = 1.0f / Z;
 #pragma unroll
             for (int s = 0; s < Q; ++s) P[s] *= invZ;
-            colsum_add<Q>(hv, cs);
+            colsum_add<Q>(hv, cs, a.nw ? (double)a.nw[i] : 1.0);
             st_marg<MT, Q>(mn + base, P);
         }
     }
@@ -597,13 +599,14 @@ __global__ void transpose_sigma_kernel(int32_t n, int32_t R, const int32_t* __re
 }
 
 // Ordered cut sum_{j in N(i)} W_ij [sigma_i != sigma_j] per replica (graphs),
-// group sizes (bMinCut), or unsatisfied clauses counted at owner incidences
-// (Max-k-SAT).  One lane per replica.
+// group sizes (bMinCut: sums of the node weights nw, 1 each when null), or
+// unsatisfied clauses counted at owner incidences (Max-k-SAT).  One lane per
+// replica.
 template <int Q>
 __global__ void __launch_bounds__(1024) eval_graph_kernel(const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
-                                                         const Tile* __restrict__ tiles, int32_t R, int lanes_log2,
-                                                         const uint8_t* __restrict__ sigma, double* __restrict__ vpart,
-                                                         int* __restrict__ spart)
+                                                         const int32_t* __restrict__ nw, const Tile* __restrict__ tiles,
+                                                         int32_t R, int lanes_log2, const uint8_t* __restrict__ sigma,
+                                                         double* __restrict__ vpart, int* __restrict__ spart)
 {
     const Tile tile = tiles[blockIdx.x];
     const TeamIdx ti = team_idx(lanes_log2);
@@ -617,8 +620,9 @@ __global__ void __launch_bounds__(1024) eval_graph_kernel(const int64_t* __restr
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             const uint8_t si = sigma[(size_t)i * R + r];
             if constexpr (Q > 1) {
+                const int vi = nw ? nw[i] : 1;
 #pragma unroll
-                for (int s = 0; s < Q; ++s) cnt[s] += (si == s) ? 1 : 0;
+                for (int s = 0; s < Q; ++s) cnt[s] += (si == s) ? vi : 0;
             }
             for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
                 const int2 e = adj[k];
@@ -698,9 +702,12 @@ __global__ void sizes_widen_kernel(size_t count, const int* __restrict__ in, lon
 
 // anytime best: best[inst][r] <- better of best and the value just evaluated.
 // MaxCut: cut = ordered / 2, larger is better; Max-k-SAT: fewer unsat;
-// bMinCut: integer energy 2 cut + lam sum_s |Pi_s| (|Pi_s| - 1), lower.
+// bMinCut: integer energy 2 cut + lam (sum_s W_s^2 - sum_i V_i^2), lower, with
+// W_s the summed node weight of group s (|Pi_s| (|Pi_s| - 1) summed over s for
+// unit weights).
 __global__ void best_update_kernel(int kind, int R, int n_inst, int q, double lam, const double* __restrict__ v,
-                                   const long long* __restrict__ sz, double* __restrict__ best)
+                                   const long long* __restrict__ sz, const double* __restrict__ v2,
+                                   double* __restrict__ best)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_inst * R) return;
@@ -710,10 +717,10 @@ __global__ void best_update_kernel(int kind, int R, int n_inst, int q, double la
     } else if (kind == KIND_MAXSAT) {
         score = v[idx];
     } else {
-        double pen = 0.0;
+        double pen = -v2[idx / R];
         for (int s = 0; s < q; ++s) {
             const double c = (double)sz[(size_t)idx * q + s];
-            pen += c * (c - 1.0);
+            pen += c * c;   // exact: group weights are below 2^22
         }
         score = v[idx] + lam * pen;   // ordered cut = 2 cut
     }
@@ -898,16 +905,16 @@ hipError_t launch_eval(const Problem& p, const LaunchGeom& geo, int waves, const
         else
             eval_sat_kernel<3><<<g, b, lds, st>>>(p.row_off, (const void*)p.inc4, tiles, R, lanes_log2, sigma, vpart);
     } else if (p.kind == KIND_MAXCUT) {
-        eval_graph_kernel<1><<<g, b, lds_bytes(waves, L, 1), st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma,
-                                                                    vpart, spart);
+        eval_graph_kernel<1><<<g, b, lds_bytes(waves, L, 1), st>>>(p.row_off, p.adj, nullptr, tiles, R, lanes_log2,
+                                                                    sigma, vpart, spart);
     } else {
         const size_t lds = lds_bytes(waves, L, p.q);
         switch (p.q) {
-        case 2: eval_graph_kernel<2><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
-        case 4: eval_graph_kernel<4><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
-        case 8: eval_graph_kernel<8><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
-        case 16: eval_graph_kernel<16><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
-        case 32: eval_graph_kernel<32><<<g, b, lds, st>>>(p.row_off, p.adj, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        case 2: eval_graph_kernel<2><<<g, b, lds, st>>>(p.row_off, p.adj, p.nw, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        case 4: eval_graph_kernel<4><<<g, b, lds, st>>>(p.row_off, p.adj, p.nw, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        case 8: eval_graph_kernel<8><<<g, b, lds, st>>>(p.row_off, p.adj, p.nw, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        case 16: eval_graph_kernel<16><<<g, b, lds, st>>>(p.row_off, p.adj, p.nw, tiles, R, lanes_log2, sigma, vpart, spart); break;
+        case 32: eval_graph_kernel<32><<<g, b, lds, st>>>(p.row_off, p.adj, p.nw, tiles, R, lanes_log2, sigma, vpart, spart); break;
         default: return hipErrorInvalidValue;
         }
     }
@@ -923,11 +930,12 @@ hipError_t launch_sizes_widen(size_t count, const int* in, long long* out, hipSt
 }
 
 hipError_t launch_best_update(int kind, int R, int n_inst, int q, double lam, const double* vout,
-                              const long long* sout, double* best, hipStream_t st)
+                              const long long* sout, const double* v2, double* best, hipStream_t st)
 {
     (void)hipGetLastError();   // drop stale errors of earlier calls
+    if (kind == KIND_BMINCUT && !v2) return hipErrorInvalidValue;
     const int n = n_inst * R;
-    best_update_kernel<<<(n + 255) / 256, 256, 0, st>>>(kind, R, n_inst, q, lam, vout, sout, best);
+    best_update_kernel<<<(n + 255) / 256, 256, 0, st>>>(kind, R, n_inst, q, lam, vout, sout, v2, best);
     return hipGetLastError();
 }
 

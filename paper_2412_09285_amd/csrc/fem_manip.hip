@@ -198,6 +198,10 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_manip
                 for (int s = 0; s < Q; ++s) phi[s] += (s0 == s) ? w0 : (AccT)0;
             }
             const int own = argmax_low<Q>(hv);
+            // node weight: lam c^a V_i [sum_j V_j e_j(s) - V_i e_i(s)]; the
+            // state counts become summed weights
+            const int ivw = a.nw ? a.nw[i] : 1;
+            const double vw = (double)ivw;
             const double D = a.nrm[i];
             const double cf = D > 0.0 ? (double)Q / D : 0.0;
             const double ca = D > 0.0 ? (double)Q / sqrt(D) : 0.0;
@@ -213,7 +217,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_manip
             // mean normalised by the sum of the float32 marginals (their
             // rounding then perturbs only the weights)
             auto Aof = [&](int s) {
-                return -cf * (double)phi[s] + sc.lam_d * ca * (ct[s] - (own == s ? 1.0 : 0.0)) +
+                return -cf * (double)phi[s] + sc.lam_d * ca * vw * (ct[s] - (own == s ? vw : 0.0)) +
                        ((double)hv[s] - (double)mx) * sc.inv_beta_d;
             };
             double avg = 0.0, psum = 0.0;
@@ -230,7 +234,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_manip
             for (int s = 0; s < Q; ++s) hv[s] = adam_update(hv[s], gv[s], m1v[s], m2v[s], sc);
             const int nw = argmax_low<Q>(hv);
 #pragma unroll
-            for (int s = 0; s < Q; ++s) cs[s] += (nw == s) ? 1 : 0;
+            for (int s = 0; s < Q; ++s) cs[s] += (nw == s) ? ivw : 0;
             st_state<Q, NT>(a.h + sbase, hv);
             st_state<Q, NT>(a.m1 + sbase, m1v);
             st_state<Q, NT>(a.m2 + sbase, m2v);
@@ -265,7 +269,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_manip
             ld_f32<Q>(a.h + (size_t)i * a.srow + (size_t)r * Q, hv);
             const int b = argmax_low<Q>(hv);
 #pragma unroll
-            for (int s = 0; s < Q; ++s) cs[s] += (b == s) ? 1 : 0;
+            for (int s = 0; s < Q; ++s) cs[s] += (b == s) ? (a.nw ? a.nw[i] : 1) : 0;
             en[(size_t)i * R + r] = (uint8_t)b;
         }
     }

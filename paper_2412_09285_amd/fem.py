@@ -65,6 +65,7 @@ _SIGS = {
     "fem_abi_version": (C.c_int32, []),
     "fem_maxcut_create": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _P, _PP]),
     "fem_bmincut_create": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _P, C.c_int32, _PP]),
+    "fem_bmincut_create_weighted": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _P, C.c_int32, _P, _PP]),
     "fem_maxsat_create": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _PP]),
     "fem_batch_create": (C.c_int, [C.c_int32, _P, _PP]),
     "fem_graph_order": (C.c_int, [C.c_int32, C.c_int64, _P, _P, _P]),
@@ -211,14 +212,22 @@ class Problem:
         return cls(out)
 
     @classmethod
-    def bmincut(cls, n, u, v, w, q, device=0):
+    def bmincut(cls, n, u, v, w, q, device=0, node_weight=None):
+        """node_weight: optional positive integer weight per node (community
+        sizes); the balance term then counts summed weights per group."""
         u, pu = _host(u, np.int32)
         v, pv = _host(v, np.int32)
         pw = None
         if w is not None:
             w, pw = _host(w, np.float32)
         out = C.c_void_p()
-        _check(lib().fem_bmincut_create(device, n, u.shape[0], pu, pv, pw, q, C.byref(out)))
+        if node_weight is None:
+            _check(lib().fem_bmincut_create(device, n, u.shape[0], pu, pv, pw, q, C.byref(out)))
+        else:
+            nw, pn = _host(node_weight, np.int32)
+            if nw.shape != (n,):
+                raise ValueError(f"node_weight must have shape ({n},), got {nw.shape}")
+            _check(lib().fem_bmincut_create_weighted(device, n, u.shape[0], pu, pv, pw, q, pn, C.byref(out)))
         return cls(out)
 
     @classmethod

@@ -327,3 +327,11 @@ def batch_instance(b: int, seed0: int = 50_000, n_range=(1_000, 50_000), n_overr
         g = random_sparse_graph(n, 5 * n, seed=seed + 7_000_000, weights="pm1")
     g.meta.update({"instance": b, "seed": seed})
     return g
+
+
+def community_sizes(n: int, seed: int, mean: float = 4.0) -> np.ndarray:
+    """Node weights of a coarsened graph (each coarse node stands for a
+    community of original nodes): V_i >= 1, geometric with the given mean,
+    int32."""
+    rng = rng_for(seed)
+    return rng.geometric(1.0 / mean, size=n).astype(np.int32)
