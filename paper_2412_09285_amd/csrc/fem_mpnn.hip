@@ -120,9 +120,9 @@ __global__ void feat_kernel(int32_t n, const int64_t* __restrict__ row_off, cons
 
 // A wave takes L1_NB = 8 nodes at a time.  Gather: lane 8q + c aggregates
 // feature c of node q (four neighbour rows in flight); the nodes' [x | a(x)]
-// are staged in the wave's LDS slice.  Dense part (only when pre1 is kept,
-// for training): lane j owns hidden unit j (its 16 weights in registers) and
-// reads the staged inputs as broadcasts.
+// are staged in the wave's LDS slice.  Dense part (skipped when pre1 is
+// null): lane j owns hidden unit j (its 16 weights in registers) and reads the
+// staged inputs as broadcasts; layer 2 gathers the pre1 rows.
 constexpr int L1_NB = 8;
 __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* __restrict__ row_off,
                                                      const int2* __restrict__ adj, const float* __restrict__ X,
@@ -186,37 +186,13 @@ __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* _
     }
 }
 
-// H1 of node j, hidden units 4l..4l+3, from its 16 layer-1 inputs
-// [x_j | a(x)_j], in the same operation order as layer1_kernel (bit-identical)
-__device__ __forceinline__ void h1_units4(const float* __restrict__ X, const float* __restrict__ A1agg, int64_t j,
-                                          const float (&cA)[4][D_IN], const float (&cB)[4][D_IN],
-                                          const float (&b1)[4], float (&out)[4])
-{
-    const float4 x0 = reinterpret_cast<const float4*>(X + j * D_IN)[0];
-    const float4 x1 = reinterpret_cast<const float4*>(X + j * D_IN)[1];
-    const float4 a0 = reinterpret_cast<const float4*>(A1agg + j * D_IN)[0];
-    const float4 a1 = reinterpret_cast<const float4*>(A1agg + j * D_IN)[1];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        float acc = b1[u];
-        acc = fmaf(x0.x, cA[u][0], acc); acc = fmaf(x0.y, cA[u][1], acc);
-        acc = fmaf(x0.z, cA[u][2], acc); acc = fmaf(x0.w, cA[u][3], acc);
-        acc = fmaf(x1.x, cA[u][4], acc); acc = fmaf(x1.y, cA[u][5], acc);
-        acc = fmaf(x1.z, cA[u][6], acc); acc = fmaf(x1.w, cA[u][7], acc);
-        acc = fmaf(a0.x, cB[u][0], acc); acc = fmaf(a0.y, cB[u][1], acc);
-        acc = fmaf(a0.z, cB[u][2], acc); acc = fmaf(a0.w, cB[u][3], acc);
-        acc = fmaf(a1.x, cB[u][4], acc); acc = fmaf(a1.y, cB[u][5], acc);
-        acc = fmaf(a1.z, cB[u][6], acc); acc = fmaf(a1.w, cB[u][7], acc);
-        out[u] = fmaxf(acc, 0.0f);
-    }
-}
-
 // Layer 2, four nodes per wave at a time.
-// Gather: team t (16 lanes) takes node i0 + t; lane l of the team owns hidden
-// units 4l..4l+3 (their layer-1 weights in registers) and forms a(H1) from
-// the neighbours' 16 layer-1 inputs [x | a(x)] (64 bytes, the same for the
-// team's lanes) with H1 recomputed per neighbour, instead of gathering
-// 256-byte H1 rows; the four nodes' dependency chains run side by side.
+// Gather: team t (16 lanes) takes node i0 + t; lane l of the team reads hidden
+// units 4l..4l+3 of each neighbour's layer-1 pre-activation row (one float4 of
+// a 256-byte row, ReLU applied on load), four neighbours in flight, so the
+// four nodes' dependency chains run side by side.  (Recomputing H1 from the
+// neighbours' 16 layer-1 inputs instead reads 64 bytes per neighbour but costs
+// 64 FMAs per lane per neighbour; measured slower end to end.)
 // Dense: [A2; B2] (128 x 64, float) sits in LDS, shared by the workgroup; the
 // four nodes' [H1 | a(H1)] are staged in the wave's LDS slice and lane j (=
 // output unit) reads one weight per k (a conflict-free 256-byte row) and the
@@ -226,9 +202,9 @@ __device__ __forceinline__ void h1_units4(const float* __restrict__ X, const flo
 constexpr int L2_NB = 4;
 __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* __restrict__ row_off,
                                                      const int2* __restrict__ adj, const float* __restrict__ inv_deg,
-                                                     const uint16_t* __restrict__ w, const float* __restrict__ X,
-                                                     const float* __restrict__ A1agg, float* __restrict__ a2out,
-                                                     float* __restrict__ pre2out, float* __restrict__ z)
+                                                     const uint16_t* __restrict__ w, const float* __restrict__ pre1,
+                                                     float* __restrict__ a2out, float* __restrict__ pre2out,
+                                                     float* __restrict__ z)
 {
     __shared__ float sW[2 * HID * HID];                // [k][j], k < 64: A2, k >= 64: B2
     __shared__ float4 sx[4][L2_NB][2 * HID / 4];       // per wave: L2_NB nodes x [H1 | a2]
@@ -242,52 +218,42 @@ __global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* _
     const int team = lane >> 4, tl = lane & 15;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
-    float cA[4][D_IN], cB[4][D_IN], b1[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-        for (int c = 0; c < D_IN; ++c) {
-            cA[u][c] = bf(w[OFF_A1 + c * HID + 4 * tl + u]);
-            cB[u][c] = bf(w[OFF_B1 + c * HID + 4 * tl + u]);
-        }
-        b1[u] = bf(w[OFF_b1 + 4 * tl + u]);
-    }
     const float bias = bf(w[OFF_b2 + lane]);
     const float cl = bf(w[OFF_c + lane]);
     const float dd = bf(w[OFF_d]);
+    auto relu4 = [](float4 v) { return make_float4(fmaxf(v.x, 0.0f), fmaxf(v.y, 0.0f), fmaxf(v.z, 0.0f), fmaxf(v.w, 0.0f)); };
     for (int i0 = wave * L2_NB; i0 < n; i0 += nw * L2_NB) {
         const int cnt = (n - i0) < L2_NB ? (n - i0) : L2_NB;
         const int i = i0 + team;
         if (i < n) {
-            float h[4], a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            h1_units4(X, A1agg, i, cA, cB, b1, h);
+            const float4 h = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)i * HID)[tl]);
+            float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
             int64_t k = row_off[i];
             const int64_t kend = row_off[i + 1];
-            for (; k + 2 <= kend; k += 2) {
-                const int2 e0 = adj[k], e1 = adj[k + 1];
-                float v0[4], v1[4];
-                h1_units4(X, A1agg, e0.x, cA, cB, b1, v0);
-                h1_units4(X, A1agg, e1.x, cA, cB, b1, v1);
+            for (; k + 4 <= kend; k += 4) {
+                const int2 e0 = adj[k], e1 = adj[k + 1], e2 = adj[k + 2], e3 = adj[k + 3];
+                const float4 v0 = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e0.x * HID)[tl]);
+                const float4 v1 = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e1.x * HID)[tl]);
+                const float4 v2 = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e2.x * HID)[tl]);
+                const float4 v3 = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e3.x * HID)[tl]);
                 const float w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    a[u] = fmaf(w0, v0[u], a[u]);
-                    a[u] = fmaf(w1, v1[u], a[u]);
-                }
+                const float w2 = __int_as_float(e2.y), w3 = __int_as_float(e3.y);
+                a0 = fmaf(w0, v0.x, a0); a1 = fmaf(w0, v0.y, a1); a2 = fmaf(w0, v0.z, a2); a3 = fmaf(w0, v0.w, a3);
+                a0 = fmaf(w1, v1.x, a0); a1 = fmaf(w1, v1.y, a1); a2 = fmaf(w1, v1.z, a2); a3 = fmaf(w1, v1.w, a3);
+                a0 = fmaf(w2, v2.x, a0); a1 = fmaf(w2, v2.y, a1); a2 = fmaf(w2, v2.z, a2); a3 = fmaf(w2, v2.w, a3);
+                a0 = fmaf(w3, v3.x, a0); a1 = fmaf(w3, v3.y, a1); a2 = fmaf(w3, v3.z, a2); a3 = fmaf(w3, v3.w, a3);
             }
             for (; k < kend; ++k) {
                 const int2 e = adj[k];
-                float v0[4];
-                h1_units4(X, A1agg, e.x, cA, cB, b1, v0);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) a[u] = fmaf(__int_as_float(e.y), v0[u], a[u]);
+                const float4 v = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e.x * HID)[tl]);
+                const float ww = __int_as_float(e.y);
+                a0 = fmaf(ww, v.x, a0); a1 = fmaf(ww, v.y, a1); a2 = fmaf(ww, v.z, a2); a3 = fmaf(ww, v.w, a3);
             }
             const float id = inv_deg[i];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] *= id;
-            sx[wl][team][tl] = make_float4(h[0], h[1], h[2], h[3]);
-            sx[wl][team][HID / 4 + tl] = make_float4(a[0], a[1], a[2], a[3]);
-            if (a2out) reinterpret_cast<float4*>(a2out + (size_t)i * HID)[tl] = make_float4(a[0], a[1], a[2], a[3]);
+            const float4 av = make_float4(a0 * id, a1 * id, a2 * id, a3 * id);
+            sx[wl][team][tl] = h;
+            sx[wl][team][HID / 4 + tl] = av;
+            if (a2out) reinterpret_cast<float4*>(a2out + (size_t)i * HID)[tl] = av;
         }
         __builtin_amdgcn_wave_barrier();
         float acc[L2_NB];
@@ -636,10 +602,9 @@ static fem_status forward(fem_mpnn* m, const Problem& p, const float* state, int
     feat_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, p.row_off, p.adj, state, stride, k0, k1, (uint32_t)draw, m->X,
                                                  m->inv_deg);
     layer1_kernel<<<grid_rows((n + L1_NB - 1) / L1_NB, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->X, m->inv_deg, m->wbf,
-                                                                         m->A1agg, train ? m->pre1 : nullptr);
+                                                                         m->A1agg, m->pre1);
     layer2_kernel<<<grid_rows((n + L2_NB - 1) / L2_NB, 4), 256, 0, st>>>(
-        n, p.row_off, p.adj, m->inv_deg, m->wbf, m->X, m->A1agg, train ? m->a2 : nullptr, train ? m->pre2 : nullptr,
-        m->z);
+        n, p.row_off, p.adj, m->inv_deg, m->wbf, m->pre1, train ? m->a2 : nullptr, train ? m->pre2 : nullptr, m->z);
     MCHK(hipGetLastError());
     return FEM_OK;
 }
