@@ -16,6 +16,11 @@ inputs resident in HBM.  Prints one JSON line.
 gradients (one-hot neighbour read-outs, 1/sum|W| normalisation): the gather
 then reads sign bits, and no energies are formed.
 
+--workload k2000dense is the dense-W path: MaxCut on a complete graph of
+2,000 nodes with +/-1 weights (the shape of the paper's K2000 benchmark),
+R = 1,000, RMSprop with the paper's K2000 settings; the field product runs on
+the FP64 matrix cores, so its roofline is the FP64 MFMA peak.
+
 roofline.traffic is the HBM traffic of one step-kernel launch measured with
 the FETCH_SIZE and WRITE_SIZE counters (scaled by a plain copy of known
 size), read from the committed counter summary of this workload; it is null
@@ -35,6 +40,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_F64_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -63,6 +69,7 @@ def manip_kernel_bytes(n, R, nnz):
 KERNEL_SOURCES = {
     "explicit": ["fem_kernels.hip", "fem_device.h", "fem_internal.h"],
     "manipulated": ["fem_manip.hip", "fem_device.h", "fem_internal.h"],
+    "dense": ["fem_dense.hip", "fem_dense.h", "fem_device.h", "fem_internal.h"],
 }
 
 
@@ -124,10 +131,11 @@ def main():
     ap.add_argument("--retune", action="store_true", help="time every launch shape even if one is cached")
     ap.add_argument("--cpu-replicas", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=150)
-    ap.add_argument("--workload", choices=["maxcut1e5", "bmincut1e6", "max3sat1e5", "batch512", "copy"],
+    ap.add_argument("--workload", choices=["maxcut1e5", "bmincut1e6", "max3sat1e5", "k2000dense", "batch512", "copy"],
                     default="maxcut1e5",
                     help="maxcut1e5: the throughput line; bmincut1e6 / max3sat1e5: the Potts and Max-3-SAT "
-                         "kernels at full size; batch512: time to target on 512 uneven MaxCut instances; "
+                         "kernels at full size; k2000dense: the dense-W (matrix-core) path on a complete "
+                         "2000-node graph; batch512: time to target on 512 uneven MaxCut instances; "
                          "copy: a plain device copy (calibrates HBM counters)")
     ap.add_argument("--order", choices=["draw", "rcm"], default="rcm",
                     help="bmincut1e6: node order of the graph (rcm: relabelled by fem_graph_order before the "
@@ -200,7 +208,21 @@ WORKLOADS = {
     "max3sat1e5": dict(kind="maxsat", recipe=4, R=64, seed=104, T=2000,
                        name="max3sat_n100000_m800000", counters="max3sat_1e5_R64",
                        data="random 3-SAT, distinct variables, fair signs, ratio 8"),
+    "k2000dense": dict(kind="maxcut_dense", n=2000, R=1000, seed=105, T=1000,
+                       name="maxcut_complete_n2000_pm1_dense", counters="maxcut_dense_k2000_R1000",
+                       data="complete graph K_2000, +/-1 weights"),
 }
+
+# the paper's K2000 optimiser: RMSprop (alpha 0.56, momentum 0.63, weight
+# decay 0.013, lr 0.03), inverse-proportional schedule T 1.16 -> 6e-5
+K2000_PARAMS = dict(optimizer=1, rms_alpha=0.56, momentum=0.63, weight_decay=0.013, lr=0.03, schedule=2,
+                    beta_min=1 / 1.16, beta_max=1 / 6e-5)
+
+
+def dense_kernel_bytes(n, R):
+    """Algorithmic bytes of one dense step launch: W once (4 n^2), the marginal
+    copy read and written, h, m1, m2 read and written, the energy partials."""
+    return 4 * n * n + n * R * (24 + 8) + 16 * R * (-(-n // 64))
 
 
 def potts_kernel_bytes(n, R, q, nnz, mbytes, n_tiles):
@@ -235,7 +257,12 @@ def throughput(args):
         raise SystemExit("--gradient manipulated is measured on the MaxCut workload")
     log("generating the workload ...")
     order_s = None
-    if kind == "maxsat":
+    if kind == "maxcut_dense":
+        g = W.complete_pm1(wl["n"], seed=wl["seed"])
+        n, nnz, q = g.n, g.nnz, 1
+        prob = fem.Problem.maxcut_dense(W.dense_matrix(g), device=0)
+        h0 = W.initial_fields(n, R, seed=wl["seed"])
+    elif kind == "maxsat":
         cnf = W.config_cnf(wl["recipe"])
         n, nnz, q = cnf.n_vars, int(cnf.clause_off[-1]), 1
         prob = fem.Problem.maxsat(cnf.n_vars, cnf.clause_off, cnf.lits, device=0)
@@ -263,6 +290,8 @@ def throughput(args):
     extra["state_layout"] = fem.STATE_INTERLEAVED if args.state_layout == "interleaved" else fem.STATE_SEPARATE
     if kind == "bmincut":
         extra["lam"] = wl["lam"]
+    if kind == "maxcut_dense":
+        extra.update(K2000_PARAMS)
     s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, marginal_dtype=dtype, **extra), stream=stream)
     s.set_fields(h0)
     tile = s.tile()
@@ -305,6 +334,9 @@ def throughput(args):
     if manip:
         alg_bytes = manip_kernel_bytes(n, R, nnz)
         kname, counters = "maxcut_manip_kernel", "maxcut_manip_n1e5_R256_hbm_counters.md"
+    elif kind == "maxcut_dense":
+        alg_bytes = dense_kernel_bytes(n, R)
+        kname, counters = "maxcut_dense_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
     elif kind == "maxcut":
         alg_bytes = step_kernel_bytes(n, R, nnz, mbytes, n_tiles)
         kname, counters = "maxcut_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
@@ -318,13 +350,25 @@ def throughput(args):
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     if args.state_layout != "interleaved":
         counters = counters.replace("_hbm_counters", f"_{args.state_layout}_hbm_counters")
-    traffic = measured_traffic(os.path.join(ROOT, "profiles", counters), args.gradient, tile, args.dtype,
+    src = "dense" if kind == "maxcut_dense" else args.gradient
+    traffic = measured_traffic(os.path.join(ROOT, "profiles", counters), src, tile, args.dtype,
                                args.state_layout)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kname, "kernel_avg_ms": round(kern_ms, 5), "kernel_launches": n_k,
-            "alg_bytes_per_launch": int(alg_bytes), "kernel_sources_sha256": kernel_sources_sha(args.gradient)}
-    label = {"maxcut": "cut", "bmincut": "2 cut + lambda sum |Pi|(|Pi|-1)", "maxsat": "unsatisfied clauses"}[kind]
+            "alg_bytes_per_launch": int(alg_bytes), "kernel_sources_sha256": kernel_sources_sha(src)}
+    if kind == "maxcut_dense":
+        # a dense contraction in FP64: the FP64 matrix-core peak bounds it;
+        # the HBM figures stay alongside
+        flops = 2.0 * n * n * R
+        tfs = flops / (kern_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfs / MFMA_F64_PEAK_TFLOPS, 4), "traffic": traffic, "flops_per_launch": flops,
+                "hbm_achieved_GBps": round(achieved, 1), "kernel": kname, "kernel_avg_ms": round(kern_ms, 5),
+                "kernel_launches": n_k, "alg_bytes_per_launch": int(alg_bytes),
+                "kernel_sources_sha256": kernel_sources_sha(src)}
+    label = {"maxcut": "cut", "maxcut_dense": "cut", "bmincut": "2 cut + lambda sum |Pi|(|Pi|-1)",
+             "maxsat": "unsatisfied clauses"}[kind]
     out = {
         "metric": "replica-edge updates/s (nnz*R*steps/s)",
         "value": value,
@@ -336,13 +380,16 @@ def throughput(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f32+sign-bit-readouts" if manip else "f32" if dtype == fem.F32 else "f32+bf16-marginals"),
+        "dtype": ("f32+sign-bit-readouts" if manip else "f32 state, f64 field product" if kind == "maxcut_dense"
+                  else "f32" if dtype == fem.F32 else "f32+bf16-marginals"),
         "data": f"synthetic (seeded generator: {wl['data']})",
         "config": {"workload": wl["name"] + ("_rcm" if kind == "bmincut" and args.order == "rcm" else ""),
                    "n": n, "nnz": nnz, "q": q if kind == "bmincut" else 2,
                    "replicas": R, "anneal_steps": K, "marginals": args.dtype, "gradient": args.gradient,
                    "state_layout": args.state_layout,
-                   "schedule": "linear beta 0.01->5, Adam lr 0.1", "tile": list(tile),
+                   "schedule": ("inverse-proportional T 1.16->6e-5, RMSprop lr 0.03 alpha 0.56 momentum 0.63 "
+                                "weight decay 0.013" if kind == "maxcut_dense" else "linear beta 0.01->5, Adam lr 0.1"),
+                   "tile": list(tile),
                    "parallelism": "single GPU",
                    "node_order": args.order if kind == "bmincut" else "as generated",
                    "order_seconds": order_s if kind == "bmincut" else None},
@@ -350,7 +397,7 @@ def throughput(args):
                    "U_mean_final": float(np.mean(U)) if U is not None else None},
         "roofline": roof,
     }
-    if kind == "maxcut" and not args.no_cpu and not manip:
+    if kind in ("maxcut", "maxcut_dense") and not args.no_cpu and not manip:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_replicas, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -83,6 +83,19 @@ typedef struct fem_solver fem_solver;     /* R replicas: h, Adam moments, margin
 fem_status fem_maxcut_create(int device, int32_t n, int64_t n_edges, const int32_t* u,
                              const int32_t* v, const float* w, fem_problem** out);
 
+/* MaxCut on a dense weight matrix: complete or near-complete graphs such as
+ * the all-to-all K2000 benchmark (Results, "Applications to the Maximum-Cut
+ * problem").  W: host, n x n row-major float, symmetric with zero diagonal
+ * and finite entries (FEM_E_INVAL otherwise); n <= 32768 (FEM_E_UNSUPPORTED).
+ * With explicit gradients the step forms the field product W m on the
+ * matrix cores (float32 marginals; a bfloat16 marginal copy gives
+ * FEM_E_UNSUPPORTED at solver creation); read-out, evaluation and the
+ * manipulated gradients use the sparse structure of W's nonzeros, which the
+ * problem also holds.  Device memory: W zero-padded to a multiple of 64 rows
+ * and columns (float) plus that structure.  Dense problems are not batched
+ * (fem_batch_create gives FEM_E_UNSUPPORTED). */
+fem_status fem_maxcut_create_dense(int device, int32_t n, const float* W, fem_problem** out);
+
 /* q-way balanced min-cut (Results, the bMinCut energy with the soft balance
  * term lambda * sum_i sum_{j != i} delta(sigma_i, sigma_j)).  Same edge rules
  * as MaxCut; weights must be > 0.  q must be one of 2, 4, 8, 16, 32 (other

@@ -23,6 +23,7 @@
 
 #include "../../include/fem.h"
 #include "fem_internal.h"
+#include "fem_dense.h"
 
 using namespace fem;
 
@@ -374,6 +375,7 @@ struct fem_solver {
     int32_t t = 0;
     bool fields_set = false;
     bool manip = false;   // manipulated gradients on a graph kind: read-out marginal copy
+    bool dense = false;   // dense MaxCut problem, explicit gradients: matrix-core step kernel
     int32_t rw = 0;       // MaxCut manipulated: 32-bit words per row of sign bits
     // state: one allocation of 3 vals floats holding h, m1, m2; rows of each
     // are srow floats apart (RQ: three separate arrays; 3RQ: the three rows
@@ -528,7 +530,8 @@ static fem_status setup_tiling(fem_solver* s, const TileShape& shape)
         (s->geo.nseg > 1 && count_tiles(s, s->geo.teams_per_block * shape.rows) <= GRID_Y_MAX) ? 1 : 0;
     s->lanes_log2 = 0;
     while ((1 << s->lanes_log2) < s->geo.lanes) ++s->lanes_log2;
-    const int tile_rows = s->geo.teams_per_block * shape.rows;
+    // the dense step kernel owns fixed row blocks (the padding of W)
+    const int tile_rows = s->dense ? DENSE_ROWS : s->geo.teams_per_block * shape.rows;
     std::vector<Tile> tiles;
     std::vector<int32_t> chunk_off{0}, inst_chunk_off{0};
     for (int b = 0; b < s->n_inst; ++b) {
@@ -724,6 +727,8 @@ static fem_status do_step(fem_solver* s)
     }
     if (s->manip)
         HIPCHK(launch_manip_step(s->kind, s->shape.vec, s->shape.nt != 0, s->geo, s->shape.waves, a, s->stream));
+    else if (s->dense)
+        HIPCHK(launch_dense_step(*s->prob, s->dtype, en, s->shape.nt != 0, s->n_tiles, a, s->stream));
     else
         HIPCHK(launch_step(s->kind, s->dtype, s->shape.vec, s->shape.nt != 0, s->geo, s->shape.waves, a, s->stream));
     if (e1) HIPCHK(hipEventRecord(e1, s->stream));
@@ -836,6 +841,48 @@ fem_status fem_maxcut_create(int device, int32_t n, int64_t n_edges, const int32
     return build_graph(KIND_MAXCUT, device, n, n_edges, u, v, w, 2, nullptr, out);
 }
 
+fem_status fem_maxcut_create_dense(int device, int32_t n, const float* W, fem_problem** out)
+{
+    if (!out) return fail(FEM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!W) return fail(FEM_E_INVAL, "W is NULL");
+    if (n < 1) return fail(FEM_E_INVAL, "n must be >= 1 (got %d)", n);
+    if (n > 32768) return fail(FEM_E_UNSUPPORTED, "dense problems hold n <= 32768 (got %d)", n);
+    std::vector<int32_t> eu, ev;
+    std::vector<float> ew;
+    for (int32_t i = 0; i < n; ++i) {
+        if (W[(size_t)i * n + i] != 0.0f) return fail(FEM_E_INVAL, "W[%d][%d] != 0: self-loop", i, i);
+        for (int32_t j = i + 1; j < n; ++j) {
+            const float a = W[(size_t)i * n + j];
+            if (!std::isfinite(a)) return fail(FEM_E_INVAL, "W[%d][%d] is not finite", i, j);
+            if (a != W[(size_t)j * n + i]) return fail(FEM_E_INVAL, "W is not symmetric at (%d, %d)", i, j);
+            if (a != 0.0f) {
+                eu.push_back(i);
+                ev.push_back(j);
+                ew.push_back(a);
+            }
+        }
+    }
+    // the CSR of the nonzeros serves read-out, evaluation and the manipulated
+    // gradients; the padded matrix the explicit step
+    STCHK(build_graph(KIND_MAXCUT, device, n, (int64_t)eu.size(), eu.data(), ev.data(), ew.data(), 2, nullptr, out));
+    Problem& p = (*out)->p;
+    const int32_t ld = (n + DENSE_ROWS - 1) / DENSE_ROWS * DENSE_ROWS;
+    std::vector<float> pad((size_t)ld * ld, 0.0f);
+    for (int32_t i = 0; i < n; ++i) std::memcpy(&pad[(size_t)i * ld], &W[(size_t)i * n], (size_t)n * 4);
+    hipError_t e = hipSetDevice(p.device);
+    if (e == hipSuccess) e = dalloc(&p.dense_w, pad.size());
+    if (e == hipSuccess) e = hipMemcpy(p.dense_w, pad.data(), pad.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_problem_device(p);
+        delete *out;
+        *out = nullptr;
+        return fail(FEM_E_NOMEM, "dense matrix upload: %s", hipGetErrorString(e));
+    }
+    p.dense_ld = ld;
+    return FEM_OK;
+}
+
 fem_status fem_bmincut_create(int device, int32_t n, int64_t n_edges, const int32_t* u, const int32_t* v,
                               const float* w, int32_t q, fem_problem** out)
 {
@@ -873,6 +920,7 @@ fem_status fem_batch_create(int32_t nparts, fem_problem* const* parts, fem_probl
         const Problem& pb = parts[b]->p;
         if (pb.kind != p0.kind || pb.q != p0.q || pb.device != p0.device)
             return fail(FEM_E_INVAL, "part %d differs in kind, q or device", b);
+        if (pb.dense_w) return fail(FEM_E_UNSUPPORTED, "part %d is a dense problem: dense problems are not batched", b);
         ntot += pb.n;
     }
     if (ntot > INT32_MAX / 2) return fail(FEM_E_UNSUPPORTED, "batch too large");
@@ -1115,6 +1163,8 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     if (P.gradient == FEM_GRAD_MANIPULATED && P.energy_every != 0)
         return fail(FEM_E_UNSUPPORTED, "manipulated gradients form no energies: set energy_every = 0");
     const Problem& p = fp->p;
+    if (p.dense_w && P.gradient == FEM_GRAD_EXPLICIT && P.marginal_dtype != FEM_F32)
+        return fail(FEM_E_UNSUPPORTED, "dense problems take float32 marginals with explicit gradients");
     if ((int64_t)p.n * P.replicas * (p.kind == KIND_BMINCUT ? p.q : 1) > ((int64_t)1 << 40))
         return fail(FEM_E_NOMEM, "state of %lld values does not fit", (long long)p.n * P.replicas);
     auto* s = new (std::nothrow) fem_solver;
@@ -1134,6 +1184,7 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     s->vals = (size_t)s->n * s->R * s->Q;
     s->NE = (p.kind == KIND_BMINCUT) ? 3 : 2;
     s->manip = P.gradient == FEM_GRAD_MANIPULATED && p.kind != KIND_MAXSAT;
+    s->dense = p.dense_w != nullptr && !s->manip;
     s->rw = (s->R + 31) / 32;
     s->beta.resize((size_t)P.steps);
     s->lam.resize((size_t)P.steps);
@@ -1220,11 +1271,30 @@ void fem_solver_destroy(fem_solver* s) { destroy_solver(s); }
 
 // copy n rows of RQ floats between a dense [n][RQ] array and one of the
 // solver's state arrays (rows srow floats apart)
+// A strided copy between host and device memory moves every row as a
+// transfer of its own, so host copies of interleaved rows go through a dense
+// device buffer (one contiguous transfer plus a device-side strided copy).
 static hipError_t copy_state_rows(const fem_solver* s, float* dst, bool dst_state, const float* src, hipMemcpyKind kd)
 {
     const size_t w = (size_t)s->R * s->Q * 4;
     const size_t sp = (size_t)s->srow * 4;
-    return hipMemcpy2DAsync(dst, dst_state ? sp : w, src, dst_state ? w : sp, w, (size_t)s->n, kd, s->stream);
+    const size_t n = (size_t)s->n;
+    if (sp == w) return hipMemcpyAsync(dst, src, w * n, kd, s->stream);
+    if (kd == hipMemcpyDeviceToDevice)
+        return hipMemcpy2DAsync(dst, dst_state ? sp : w, src, dst_state ? w : sp, w, n, kd, s->stream);
+    void* tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, w * n);
+    if (e != hipSuccess) return e;
+    if (kd == hipMemcpyHostToDevice) {
+        e = hipMemcpyAsync(tmp, src, w * n, kd, s->stream);
+        if (e == hipSuccess) e = hipMemcpy2DAsync(dst, sp, tmp, w, w, n, hipMemcpyDeviceToDevice, s->stream);
+    } else {
+        e = hipMemcpy2DAsync(tmp, w, src, sp, w, n, hipMemcpyDeviceToDevice, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dst, tmp, w * n, kd, s->stream);
+    }
+    const hipError_t e2 = hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    return e != hipSuccess ? e : e2;
 }
 
 static hipError_t zero_state_rows(const fem_solver* s, float* dst)
@@ -1712,6 +1782,7 @@ static std::string tune_key(const fem_solver* s)
              s->manip ? 1 : 0);
     std::string key = buf;
     if (s->prm.state_layout == FEM_STATE_SEPARATE) key += "_sl0";
+    if (s->dense) key += "_dense";
     return key;
 }
 
@@ -1763,7 +1834,14 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
     const int wavess[4] = {2, 4, 8, 16};
     const int rowss[4] = {1, 2, 4, 8};
     const int laness[4] = {0, 32, 16, 8};
-    for (int vi = 0; vi < (s->kind == KIND_BMINCUT ? 1 : 4); ++vi)
+    // the dense step kernel has a fixed shape: only the non-temporal flag is
+    // tried (the rest of the shape serves the read-out)
+    for (int ntf = 0; s->dense && ntf < 2; ++ntf) {
+        TileShape sh = s->shape;
+        sh.nt = ntf;
+        cands.push_back(sh);
+    }
+    for (int vi = 0; !s->dense && vi < (s->kind == KIND_BMINCUT ? 1 : 4); ++vi)
         for (int ln : laness) {
             // a lane cap only matters where it splits the replicas
             const int per_lane = s->kind == KIND_BMINCUT ? 1 : vecs[vi];

@@ -65,6 +65,7 @@ _SIGS = {
     "fem_abi_version": (C.c_int32, []),
     "fem_maxcut_create": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _P, _PP]),
     "fem_bmincut_create": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _P, C.c_int32, _PP]),
+    "fem_maxcut_create_dense": (C.c_int, [C.c_int, C.c_int32, _P, _PP]),
     "fem_bmincut_create_weighted": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _P, C.c_int32, _P, _PP]),
     "fem_maxsat_create": (C.c_int, [C.c_int, C.c_int32, C.c_int64, _P, _P, _PP]),
     "fem_batch_create": (C.c_int, [C.c_int32, _P, _PP]),
@@ -228,6 +229,17 @@ class Problem:
             if nw.shape != (n,):
                 raise ValueError(f"node_weight must have shape ({n},), got {nw.shape}")
             _check(lib().fem_bmincut_create_weighted(device, n, u.shape[0], pu, pv, pw, q, pn, C.byref(out)))
+        return cls(out)
+
+    @classmethod
+    def maxcut_dense(cls, W, device=0):
+        """MaxCut on a dense symmetric weight matrix W [n][n] (zero diagonal);
+        the explicit-gradient step runs on the matrix cores."""
+        W = np.ascontiguousarray(W, dtype=np.float32)
+        if W.ndim != 2 or W.shape[0] != W.shape[1]:
+            raise ValueError(f"W must be square, got shape {W.shape}")
+        out = C.c_void_p()
+        _check(lib().fem_maxcut_create_dense(device, W.shape[0], W.ctypes.data_as(C.c_void_p), C.byref(out)))
         return cls(out)
 
     @classmethod

@@ -335,3 +335,20 @@ def community_sizes(n: int, seed: int, mean: float = 4.0) -> np.ndarray:
     int32."""
     rng = rng_for(seed)
     return rng.geometric(1.0 / mean, size=n).astype(np.int32)
+
+
+def complete_pm1(n: int, seed: int) -> Graph:
+    """Complete graph K_n with independent +1/-1 weights of equal probability
+    (the shape of the K2000 MaxCut benchmark: all-to-all, unit magnitudes)."""
+    rng = rng_for(seed)
+    iu, ju = np.triu_indices(n, k=1)
+    w = _draw_weights(rng, iu.shape[0], "pm1")
+    return Graph(n, iu.astype(np.int32), ju.astype(np.int32), w, {"kind": "complete_pm1", "seed": seed})
+
+
+def dense_matrix(g: Graph) -> np.ndarray:
+    """Symmetric float32 [n][n] weight matrix of an edge list (zero diagonal)."""
+    W = np.zeros((g.n, g.n), dtype=np.float32)
+    W[g.u, g.v] = g.w
+    W[g.v, g.u] = g.w
+    return W
