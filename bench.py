@@ -18,8 +18,10 @@ then reads sign bits, and no energies are formed.
 
 --workload k2000dense is the dense-W path: MaxCut on a complete graph of
 2,000 nodes with +/-1 weights (the shape of the paper's K2000 benchmark),
-R = 1,000, RMSprop with the paper's K2000 settings; the field product runs on
-the FP64 matrix cores, so its roofline is the FP64 MFMA peak.
+R = 1,000, RMSprop with the paper's K2000 settings.  With integral weights the
+field product is formed exactly from int8 digit planes of the fixed-point
+marginals on the int8 matrix cores (four int8 products per step), so its
+roofline is the int8 MFMA peak; other weights run on the FP64 matrix cores.
 
 roofline.traffic is the HBM traffic of one step-kernel launch measured with
 the FETCH_SIZE and WRITE_SIZE counters (scaled by a plain copy of known
@@ -41,6 +43,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 MFMA_F64_PEAK_TFLOPS = 78.6
+MFMA_I8_PEAK_TOPS = 5000.0
 
 
 def log(msg):
@@ -219,10 +222,12 @@ K2000_PARAMS = dict(optimizer=1, rms_alpha=0.56, momentum=0.63, weight_decay=0.0
                     beta_min=1 / 1.16, beta_max=1 / 6e-5)
 
 
-def dense_kernel_bytes(n, R):
-    """Algorithmic bytes of one dense step launch: W once (4 n^2), the marginal
-    copy read and written, h, m1, m2 read and written, the energy partials."""
-    return 4 * n * n + n * R * (24 + 8) + 16 * R * (-(-n // 64))
+def dense_kernel_bytes(n, R, w_bytes):
+    """Algorithmic bytes of one dense step launch: W once (w_bytes per entry:
+    4 float, 1 int8), the marginal copy read and written (4 B per value as
+    float or as four int8 digits), h, m1, m2 read and written, the energy
+    partials."""
+    return w_bytes * n * n + n * R * (24 + 8) + 16 * R * (-(-n // 64))
 
 
 def potts_kernel_bytes(n, R, q, nnz, mbytes, n_tiles):
@@ -257,10 +262,13 @@ def throughput(args):
         raise SystemExit("--gradient manipulated is measured on the MaxCut workload")
     log("generating the workload ...")
     order_s = None
+    dense_i8 = False
     if kind == "maxcut_dense":
         g = W.complete_pm1(wl["n"], seed=wl["seed"])
         n, nnz, q = g.n, g.nnz, 1
-        prob = fem.Problem.maxcut_dense(W.dense_matrix(g), device=0)
+        Wd = W.dense_matrix(g)
+        dense_i8 = bool(np.all(Wd == np.rint(Wd)) and np.abs(Wd).max() <= 127)
+        prob = fem.Problem.maxcut_dense(Wd, device=0)
         h0 = W.initial_fields(n, R, seed=wl["seed"])
     elif kind == "maxsat":
         cnf = W.config_cnf(wl["recipe"])
@@ -335,8 +343,9 @@ def throughput(args):
         alg_bytes = manip_kernel_bytes(n, R, nnz)
         kname, counters = "maxcut_manip_kernel", "maxcut_manip_n1e5_R256_hbm_counters.md"
     elif kind == "maxcut_dense":
-        alg_bytes = dense_kernel_bytes(n, R)
-        kname, counters = "maxcut_dense_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
+        alg_bytes = dense_kernel_bytes(n, R, 1 if dense_i8 else 4)
+        kname = "maxcut_dense_i8_step_kernel" if dense_i8 else "maxcut_dense_step_kernel"
+        counters = f"{wl['counters']}_{'i8' if dense_i8 else 'f64'}_hbm_counters.md"
     elif kind == "maxcut":
         alg_bytes = step_kernel_bytes(n, R, nnz, mbytes, n_tiles)
         kname, counters = "maxcut_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
@@ -358,12 +367,14 @@ def throughput(args):
             "kernel": kname, "kernel_avg_ms": round(kern_ms, 5), "kernel_launches": n_k,
             "alg_bytes_per_launch": int(alg_bytes), "kernel_sources_sha256": kernel_sources_sha(src)}
     if kind == "maxcut_dense":
-        # a dense contraction in FP64: the FP64 matrix-core peak bounds it;
+        # a dense contraction: the matrix-core peak of the type it runs in
+        # bounds it (int8: four digit-plane products per step; FP64: one);
         # the HBM figures stay alongside
-        flops = 2.0 * n * n * R
+        flops = (4.0 if dense_i8 else 1.0) * 2.0 * n * n * R
+        peak = MFMA_I8_PEAK_TOPS if dense_i8 else MFMA_F64_PEAK_TFLOPS
         tfs = flops / (kern_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tfs / MFMA_F64_PEAK_TFLOPS, 4), "traffic": traffic, "flops_per_launch": flops,
+        roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": peak, "unit": "TOP/s" if dense_i8 else "TFLOP/s",
+                "frac": round(tfs / peak, 4), "traffic": traffic, "ops_per_launch": flops,
                 "hbm_achieved_GBps": round(achieved, 1), "kernel": kname, "kernel_avg_ms": round(kern_ms, 5),
                 "kernel_launches": n_k, "alg_bytes_per_launch": int(alg_bytes),
                 "kernel_sources_sha256": kernel_sources_sha(src)}
@@ -380,7 +391,9 @@ def throughput(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f32+sign-bit-readouts" if manip else "f32 state, f64 field product" if kind == "maxcut_dense"
+        "dtype": ("f32+sign-bit-readouts" if manip
+                  else ("f32 state, exact int8 x fixed-point field product" if dense_i8 else
+                        "f32 state, f64 field product") if kind == "maxcut_dense"
                   else "f32" if dtype == fem.F32 else "f32+bf16-marginals"),
         "data": f"synthetic (seeded generator: {wl['data']})",
         "config": {"workload": wl["name"] + ("_rcm" if kind == "bmincut" and args.order == "rcm" else ""),

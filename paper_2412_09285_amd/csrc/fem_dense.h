@@ -12,11 +12,17 @@ constexpr int DENSE_ROWS = 64;
 // replicas per workgroup
 constexpr int DENSE_COLS = 64;
 
+// replica rows of each int8 digit plane of the marginal copy
+inline int dense_rows_padded(int R) { return (R + DENSE_COLS - 1) / DENSE_COLS * DENSE_COLS; }
+
 // One explicit-gradient MaxCut step with phi = W m formed by matrix-core
-// products: float32 marginals use the float32 MFMA, bfloat16 marginals the
-// bfloat16 MFMA on a bfloat16 copy of W (exact by construction, see
-// fem_maxcut_create_dense).  Grid: (n_tiles, ceil(R / DENSE_COLS)).
+// products: exact int32 products of int8 weights and the four int8 digit
+// planes of the fixed-point marginals when the problem holds dense_w8 (W
+// integral, |W| <= 127), FP64 products of the float32 W and marginals
+// otherwise.  Float32 marginal type only.  Grid: (n_tiles, ceil(R / 64)).
 hipError_t launch_dense_step(const Problem& p, int dtype, bool en, bool nt, int n_tiles, const StepArgs& a,
                              hipStream_t st);
+// the digit planes of the marginals of a.h into a.marg_nxt (int8 path)
+hipError_t launch_dense_i8_init(const Problem& p, const StepArgs& a, hipStream_t st);
 
 }  // namespace fem

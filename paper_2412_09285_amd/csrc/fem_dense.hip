@@ -26,11 +26,56 @@
 #include "fem_device.h"
 #include "fem_dense.h"
 
+#include <algorithm>
+
 namespace fem {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int DK = 32;   // K block
+constexpr int DK = 32;   // K block of the FP64 kernel
+
+// The step of one (node i, replica r) given its field phi: gradient, the
+// optimiser update of h, m1, m2, energy terms; returns the new marginal and
+// stores the gradient when it is kept.
+template <bool EN, bool NT>
+__device__ __forceinline__ float dense_update(const StepArgs& a, const StepScalars& sc, int i, int r, double phi,
+                                              double& e_mphi, double& e_h2)
+{
+    const size_t sbase = (size_t)i * a.srow + r;
+    float x, m1v, m2v;
+    if constexpr (NT) {
+        x = __builtin_nontemporal_load(a.h + sbase);
+        m1v = __builtin_nontemporal_load(a.m1 + sbase);
+        m2v = __builtin_nontemporal_load(a.m2 + sbase);
+    } else {
+        x = a.h[sbase];
+        m1v = a.m1[sbase];
+        m2v = a.m2[sbase];
+    }
+    const float ax = fabsf(x);
+    const float e = expf(-ax);
+    const float ope = 1.0f + e;
+    const float pq = e / (ope * ope);   // P(1-P) without cancellation
+    const float g = (float)((double)pq * (2.0 * phi + (double)x * sc.inv_beta_d));
+    if constexpr (EN) {
+        e_mphi += (double)tanhf(0.5f * x) * phi;
+        e_h2 += (double)(log1pf(e) + ax * (e / ope));
+    }
+    const float nh = adam_update(x, g, m1v, m2v, sc);
+    if constexpr (NT) {
+        __builtin_nontemporal_store(nh, a.h + sbase);
+        __builtin_nontemporal_store(m1v, a.m1 + sbase);
+        __builtin_nontemporal_store(m2v, a.m2 + sbase);
+    } else {
+        a.h[sbase] = nh;
+        a.m1[sbase] = m1v;
+        a.m2[sbase] = m2v;
+    }
+    if (a.grad) a.grad[(size_t)i * a.R + r] = g;
+    return tanhf(0.5f * nh);
+}
 
 template <bool EN, bool NT>
 __global__ void __launch_bounds__(256) maxcut_dense_step_kernel(StepArgs a, const float* __restrict__ W, int32_t ld)
@@ -115,40 +160,7 @@ __global__ void __launch_bounds__(256) maxcut_dense_step_kernel(StepArgs a, cons
             const int bm = q >> 2, v = q & 3;
             const int i = i0 + wm * 32 + 16 * bm + kq + 4 * v;
             if (i >= tile.row_end) continue;
-            const size_t sbase = (size_t)i * a.srow + r;
-            float x, m1v, m2v;
-            if constexpr (NT) {
-                x = __builtin_nontemporal_load(a.h + sbase);
-                m1v = __builtin_nontemporal_load(a.m1 + sbase);
-                m2v = __builtin_nontemporal_load(a.m2 + sbase);
-            } else {
-                x = a.h[sbase];
-                m1v = a.m1[sbase];
-                m2v = a.m2[sbase];
-            }
-            const double phi = acc[bm][bn][v];
-            const float ax = fabsf(x);
-            const float e = expf(-ax);
-            const float ope = 1.0f + e;
-            const float pq = e / (ope * ope);   // P(1-P) without cancellation
-            const float g = (float)((double)pq * (2.0 * phi + (double)x * sc.inv_beta_d));
-            if constexpr (EN) {
-                e_mphi[bn] += (double)tanhf(0.5f * x) * phi;
-                e_h2[bn] += (double)(log1pf(e) + ax * (e / ope));
-            }
-            const float nh = adam_update(x, g, m1v, m2v, sc);
-            if constexpr (NT) {
-                __builtin_nontemporal_store(nh, a.h + sbase);
-                __builtin_nontemporal_store(m1v, a.m1 + sbase);
-                __builtin_nontemporal_store(m2v, a.m2 + sbase);
-            } else {
-                a.h[sbase] = nh;
-                a.m1[sbase] = m1v;
-                a.m2[sbase] = m2v;
-            }
-            const size_t base = (size_t)i * R + r;
-            mn[base] = tanhf(0.5f * nh);
-            if (a.grad) a.grad[base] = g;
+            mn[(size_t)i * R + r] = dense_update<EN, NT>(a, sc, i, r, acc[bm][bn][v], e_mphi[bn], e_h2[bn]);
         }
     }
     if constexpr (EN) {
@@ -183,13 +195,184 @@ __global__ void __launch_bounds__(256) maxcut_dense_step_kernel(StepArgs a, cons
     }
 }
 
+// ------------------------------------------------ integer weights: int8 ---
+// For integral W with |W_ij| <= 127 the marginal copy is kept in fixed point,
+// m_fx = rint(m 2^30) (|m| <= 1, so |m_fx| <= 2^30), written as four signed
+// base-256 digits m_fx = d0 + 2^8 d1 + 2^16 d2 + 2^24 d3 (d0..d2 in
+// [-128, 127], |d3| <= 65).  Each digit plane is an int8 matrix, and
+// S_d = W d_d is an exact int32 product on the int8 matrix cores
+// (v_mfma_i32_32x32x32_i8; |S_d| <= 127 * 128 * n < 2^31 for n <= 32768), so
+// phi = 2^-30 sum_d 2^(8d) S_d is the field of the fixed-point marginals
+// without any rounding (all terms are integers below 2^53).  Against the
+// float32 copy the only difference is the quantisation of m to 2^-30.
+// Planes are replica-major, q[d][r][j] with rows of ld bytes and Rp (R
+// rounded up to 64) rows per plane, so that an MFMA lane's 16 consecutive k
+// values are 16 contiguous bytes of one row; rows j >= n and replicas r >= R
+// hold zeros.
+constexpr int QK = 64;        // K block (bytes of a row per block)
+constexpr int QP = QK + 16;   // LDS row pitch: 16-byte reads of 32 rows stay conflict-free
+
+__device__ __forceinline__ void to_digits(float m, int (&d)[4])
+{
+    int x = (int)rintf(m * 1073741824.0f);   // exact scaling by 2^30
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        d[k] = ((x & 0xff) ^ 0x80) - 0x80;   // low byte as a signed digit
+        x = (x - d[k]) >> 8;                  // exact: x - d[k] is a multiple of 256
+    }
+    d[3] = x;
+}
+
+template <bool EN, bool NT>
+__global__ void __launch_bounds__(256) maxcut_dense_i8_step_kernel(StepArgs a, const int8_t* __restrict__ W8,
+                                                                   int32_t ld, int32_t Rp)
+{
+    constexpr int DM = DENSE_ROWS, DN = DENSE_COLS;
+    const Tile tile = a.tiles[blockIdx.x];
+    const int i0 = tile.row_begin;   // a multiple of DM
+    const int r0 = blockIdx.y * DN;
+    const int R = a.R;
+    const size_t plane = (size_t)Rp * ld;
+    const int8_t* __restrict__ qc = static_cast<const int8_t*>(a.marg_cur);
+    int8_t* __restrict__ qn = static_cast<int8_t*>(a.marg_nxt);
+    __shared__ __attribute__((aligned(16))) int8_t sA[2][DM][QP];      // W[i0 + m][j0 + k]
+    __shared__ __attribute__((aligned(16))) int8_t sB[2][4][DN][QP];   // q[d][r0 + c][j0 + k]
+    __shared__ double sE[2][2][32];                                    // energy partials of waves wm = 1
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;   // the wave's 32 x 32 quarter
+    const int kh = lane >> 5, c32 = lane & 31;
+    // staging: thread t moves the 16-byte chunk (t & 3) of row t >> 2 of the
+    // W block and of each digit plane's block
+    const int srow_ = tid >> 2, sch = (tid & 3) * 16;
+    i32x4 ra, rb[4];
+    auto gload = [&](int j0) {
+        ra = *reinterpret_cast<const i32x4*>(W8 + (size_t)(i0 + srow_) * ld + j0 + sch);
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            rb[d] = *reinterpret_cast<const i32x4*>(qc + d * plane + (size_t)(r0 + srow_) * ld + j0 + sch);
+    };
+    auto sstore = [&](int buf) {
+        *reinterpret_cast<i32x4*>(&sA[buf][srow_][sch]) = ra;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) *reinterpret_cast<i32x4*>(&sB[buf][d][srow_][sch]) = rb[d];
+    };
+    i32x16 acc[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[d][v] = 0;
+    const int nk = ld / QK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kb = 0; kb < nk; ++kb) {
+        const int buf = kb & 1;
+        if (kb + 1 < nk) gload((kb + 1) * QK);
+#pragma unroll
+        for (int kk = 0; kk < QK / 32; ++kk) {
+            // lane (kh, c32) supplies k = 32 kk + 16 kh + e, e = 0..15, of row
+            // c32 of A and of column c32 of B (the same pairing on both sides)
+            const i32x4 av = *reinterpret_cast<const i32x4*>(&sA[buf][wm * 32 + c32][32 * kk + 16 * kh]);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const i32x4 bv = *reinterpret_cast<const i32x4*>(&sB[buf][d][wn * 32 + c32][32 * kk + 16 * kh]);
+                acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc[d], 0, 0, 0);
+            }
+        }
+        if (kb + 1 < nk) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: register v of this lane is (row 8 (v / 4) + 4 kh + v % 4 of
+    // the quarter, replica c32); new marginals go to LDS as digits,
+    // transposed to [d][replica][row], then out as 64-byte rows
+    int8_t (*sT)[DN][QP] = reinterpret_cast<int8_t (*)[DN][QP]>(&sB[0][0][0][0]);   // [4][DN][QP]
+    const StepScalars sc = a.sc;
+    const int r = r0 + wn * 32 + c32;
+    double e_mphi = 0.0, e_h2 = 0.0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int il = wm * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
+        const int i = i0 + il;
+        float mnew = 0.0f;   // rows past n and replicas past R keep zero digits
+        if (r < R && i < tile.row_end) {
+            const double phi = ((double)acc[3][v] * 16777216.0 + (double)acc[2][v] * 65536.0 +
+                                (double)acc[1][v] * 256.0 + (double)acc[0][v]) * (1.0 / 1073741824.0);
+            mnew = dense_update<EN, NT>(a, sc, i, r, phi, e_mphi, e_h2);
+        }
+        int dg[4];
+        to_digits(mnew, dg);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) sT[d][wn * 32 + c32][il] = (int8_t)dg[d];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int c = tid + 256 * u;   // chunk: plane d, replica row rl, 16-byte piece
+        const int d = c >> 8, rl = (c >> 2) & 63, ch = (c & 3) * 16;
+        if (r0 + rl < R)
+            *reinterpret_cast<i32x4*>(qn + d * plane + (size_t)(r0 + rl) * ld + i0 + ch) =
+                *reinterpret_cast<const i32x4*>(&sT[d][rl][ch]);
+    }
+    if constexpr (EN) {
+        e_mphi += __shfl_xor(e_mphi, 32, 64);
+        e_h2 += __shfl_xor(e_h2, 32, 64);
+        if (wm == 1 && kh == 0) {
+            sE[wn][0][c32] = e_mphi;
+            sE[wn][1][c32] = e_h2;
+        }
+        __syncthreads();
+        if (wm == 0 && kh == 0 && r < R) {
+            a.epart[((size_t)tile.slot * 2 + 0) * R + r] = e_mphi + sE[wn][0][c32];
+            a.epart[((size_t)tile.slot * 2 + 1) * R + r] = e_h2 + sE[wn][1][c32];
+        }
+    }
+}
+
+// digit planes of the marginals of h (rows j < n, replicas r < R)
+__global__ void dense_i8_init_kernel(const float* __restrict__ h, int64_t srow, int32_t n, int32_t R, int32_t ld,
+                                     size_t plane, int8_t* __restrict__ q)
+{
+    const size_t total = (size_t)n * R;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(k / n), j = (int)(k % n);
+        int dg[4];
+        to_digits(tanhf(0.5f * h[(size_t)j * srow + r]), dg);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) q[d * plane + (size_t)r * ld + j] = (int8_t)dg[d];
+    }
+}
+
+hipError_t launch_dense_i8_init(const Problem& p, const StepArgs& a, hipStream_t st)
+{
+    (void)hipGetLastError();   // drop stale errors of earlier calls
+    if (!p.dense_w8 || p.dense_ld % QK != 0) return hipErrorInvalidValue;
+    const int Rp = dense_rows_padded(a.R);
+    const size_t total = (size_t)a.n * a.R;
+    const size_t blocks = std::min<size_t>((total + 255) / 256, 65536);
+    dense_i8_init_kernel<<<(unsigned)std::max<size_t>(blocks, 1), 256, 0, st>>>(
+        a.h, a.srow, a.n, a.R, p.dense_ld, (size_t)Rp * p.dense_ld, static_cast<int8_t*>(a.marg_nxt));
+    return hipGetLastError();
+}
+
 hipError_t launch_dense_step(const Problem& p, int dtype, bool en, bool nt, int n_tiles, const StepArgs& a,
                              hipStream_t st)
 {
     (void)hipGetLastError();   // drop stale errors of earlier calls
-    if (!p.dense_w || p.kind != KIND_MAXCUT || dtype != 0 || p.dense_ld % DK != 0 || p.dense_ld % DENSE_ROWS != 0)
+    if (!p.dense_w || p.kind != KIND_MAXCUT || dtype != 0 || p.dense_ld % QK != 0 || p.dense_ld % DENSE_ROWS != 0)
         return hipErrorInvalidValue;
     const dim3 g(n_tiles, (a.R + DENSE_COLS - 1) / DENSE_COLS), b(256);
+    if (p.dense_w8) {
+        const int Rp = dense_rows_padded(a.R);
+        if (en) {
+            if (nt) maxcut_dense_i8_step_kernel<true, true><<<g, b, 0, st>>>(a, p.dense_w8, p.dense_ld, Rp);
+            else maxcut_dense_i8_step_kernel<true, false><<<g, b, 0, st>>>(a, p.dense_w8, p.dense_ld, Rp);
+        } else {
+            if (nt) maxcut_dense_i8_step_kernel<false, true><<<g, b, 0, st>>>(a, p.dense_w8, p.dense_ld, Rp);
+            else maxcut_dense_i8_step_kernel<false, false><<<g, b, 0, st>>>(a, p.dense_w8, p.dense_ld, Rp);
+        }
+        return hipGetLastError();
+    }
     if (en) {
         if (nt) maxcut_dense_step_kernel<true, true><<<g, b, 0, st>>>(a, p.dense_w, p.dense_ld);
         else maxcut_dense_step_kernel<true, false><<<g, b, 0, st>>>(a, p.dense_w, p.dense_ld);

@@ -102,6 +102,7 @@ static void free_problem_device(Problem& p)
     dfree(p.nw);
     dfree(p.v2);
     dfree(p.dense_w);
+    dfree(p.dense_w8);
 }
 
 static fem_status upload_problem(Problem& p)
@@ -376,6 +377,7 @@ struct fem_solver {
     bool fields_set = false;
     bool manip = false;   // manipulated gradients on a graph kind: read-out marginal copy
     bool dense = false;   // dense MaxCut problem, explicit gradients: matrix-core step kernel
+    bool dense_i8 = false;   // ... with integral weights: int8 digit planes as the marginal copy
     int32_t rw = 0;       // MaxCut manipulated: 32-bit words per row of sign bits
     // state: one allocation of 3 vals floats holding h, m1, m2; rows of each
     // are srow floats apart (RQ: three separate arrays; 3RQ: the three rows
@@ -752,6 +754,8 @@ static fem_status init_marginals(fem_solver* s)
     a.marg_nxt = s->marg[s->t & 1];
     if (s->manip)
         HIPCHK(launch_manip_init(s->kind, s->geo, s->shape.waves, a, s->stream));
+    else if (s->dense_i8)
+        HIPCHK(launch_dense_i8_init(*s->prob, a, s->stream));
     else
         HIPCHK(launch_init_marginals(s->kind, s->dtype, s->geo, s->shape.waves, a, s->vals, s->stream));
     if (s->kind == KIND_BMINCUT) STCHK(finish_colsums(s));
@@ -870,9 +874,20 @@ fem_status fem_maxcut_create_dense(int device, int32_t n, const float* W, fem_pr
     const int32_t ld = (n + DENSE_ROWS - 1) / DENSE_ROWS * DENSE_ROWS;
     std::vector<float> pad((size_t)ld * ld, 0.0f);
     for (int32_t i = 0; i < n; ++i) std::memcpy(&pad[(size_t)i * ld], &W[(size_t)i * n], (size_t)n * 4);
+    // integral weights of magnitude <= 127 also get the int8 image that the
+    // exact fixed-point step multiplies
+    bool small_int = true;
+    for (size_t k = 0; k < pad.size() && small_int; ++k)
+        small_int = pad[k] == std::rint(pad[k]) && std::fabs(pad[k]) <= 127.0f;
     hipError_t e = hipSetDevice(p.device);
     if (e == hipSuccess) e = dalloc(&p.dense_w, pad.size());
     if (e == hipSuccess) e = hipMemcpy(p.dense_w, pad.data(), pad.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && small_int) {
+        std::vector<int8_t> w8(pad.size());
+        for (size_t k = 0; k < pad.size(); ++k) w8[k] = (int8_t)pad[k];
+        e = dalloc(&p.dense_w8, w8.size());
+        if (e == hipSuccess) e = hipMemcpy(p.dense_w8, w8.data(), w8.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         free_problem_device(p);
         delete *out;
@@ -1185,6 +1200,7 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     s->NE = (p.kind == KIND_BMINCUT) ? 3 : 2;
     s->manip = P.gradient == FEM_GRAD_MANIPULATED && p.kind != KIND_MAXSAT;
     s->dense = p.dense_w != nullptr && !s->manip;
+    s->dense_i8 = s->dense && p.dense_w8 != nullptr;
     s->rw = (s->R + 31) / 32;
     s->beta.resize((size_t)P.steps);
     s->lam.resize((size_t)P.steps);
@@ -1202,7 +1218,8 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     if (e != hipSuccess) return bail(fail(FEM_E_HIP, "hipSetDevice: %s", hipGetErrorString(e)));
     const size_t msz = s->dtype == FEM_BF16 ? 2 : 4;
     // bytes of one marginal-copy buffer
-    const size_t mbytes = !s->manip ? s->vals * msz
+    const size_t mbytes = s->dense_i8 ? 4 * (size_t)dense_rows_padded(s->R) * p.dense_ld
+                          : !s->manip ? s->vals * msz
                           : s->kind == KIND_MAXCUT ? (size_t)s->n * s->rw * 4 : (size_t)s->n * s->R;
     const size_t IR = (size_t)s->n_inst * s->R;
     {
@@ -1234,6 +1251,9 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     for (int k = 0; k < 2; ++k) {
         e = hipMalloc(&s->marg[k], mbytes ? mbytes : 4);
         if (e != hipSuccess) return bail(fail(FEM_E_NOMEM, "device allocation of the marginal copy: %s", hipGetErrorString(e)));
+        // digit planes: padding rows and replicas are read and must stay zero
+        if (s->dense_i8) e = hipMemset(s->marg[k], 0, mbytes);
+        if (e != hipSuccess) return bail(fail(FEM_E_HIP, "clearing the marginal copy: %s", hipGetErrorString(e)));
     }
     ALLOC(s->eraw, IR * s->NE);
     ALLOC(s->eout, IR * 3);

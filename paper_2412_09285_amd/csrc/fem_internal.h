@@ -43,6 +43,7 @@ struct Problem {
     // (the CSR above is still built, for read-out and evaluation)
     float* dense_w = nullptr;
     int32_t dense_ld = 0;
+    int8_t* dense_w8 = nullptr;      // the same as int8 when W is integral with |W| <= 127
     // host copies kept for batching and validation
     std::vector<int64_t> h_row_off;
     std::vector<int2> h_adj;

@@ -1,14 +1,16 @@
 """GPU parity of the dense-W MaxCut path (matrix-core field product) against
 the FP64 oracle, through the C ABI.
 
-The oracle runs MaxCut on the same complete graph given as an edge list; the
-dense path forms phi = W m with float32 matrix-core products (the sparse
-kernel accumulates in double), so the same 1e-5 lockstep tolerances apply to
-gradients, energies and the propagated fields.  Also: ragged row and replica
-blocks, the paper's K2000 optimiser setting (RMSprop with momentum, inverse-
-proportional schedule), the full 2000-node size on sampled replicas, the
-manipulated gradients (which run on the nonzero structure), captured graphs,
-and argument checks.
+The oracle runs MaxCut on the same complete graph given as an edge list.  The
+dense path forms phi = W m either exactly from int8 digit planes of the
+fixed-point marginals (integral |W| <= 127, e.g. the +/-1 complete graphs
+here) or with FP64 matrix-core products (any other W); both reproduce the
+sparse kernel's FP64 accumulation, so the same 1e-5 lockstep tolerances
+apply to gradients, energies and the propagated fields.  Also: ragged row and
+replica blocks, the paper's K2000 optimiser setting (RMSprop with momentum,
+inverse-proportional schedule), the full 2000-node size on sampled replicas,
+the manipulated gradients (which run on the nonzero structure), captured
+graphs, and argument checks.
 """
 import numpy as np
 import pytest
@@ -57,6 +59,23 @@ def test_edge_sizes(n, R):
     g = W.complete_pm1(n, seed=n) if n > 1 else W.Graph(1, np.zeros(0, np.int32), np.zeros(0, np.int32),
                                                         np.zeros(0, np.float32))
     lockstep_dense(g, R=R, T=100, n_steps=10, seed=n + R, tag=f"dense n{n} R{R}")
+
+
+def test_fp64_path_complete_real_weights():
+    """Non-integral weights take the FP64 matrix-core product: K_300, R = 70."""
+    g = W.complete_pm1(300, seed=21)
+    g.w = (g.w * np.random.default_rng(21).uniform(0.5, 1.5, size=g.n_edges)).astype(np.float32)
+    lockstep_dense(g, R=70, T=500, n_steps=60, seed=22, tag="dense fp64 K300")
+
+
+@pytest.mark.parametrize("wmax", [127, 128])
+def test_integer_weight_range(wmax):
+    """Integral weights up to 127 take the int8 digit path, 128 the FP64 one."""
+    g = W.complete_pm1(200, seed=23)
+    rng = np.random.default_rng(wmax)
+    g.w = rng.integers(-wmax, wmax + 1, size=g.n_edges).astype(np.float32)
+    g.w[0] = wmax
+    lockstep_dense(g, R=40, T=300, n_steps=30, seed=24, tag=f"dense |W| <= {wmax}")
 
 
 def test_weighted_near_complete():
