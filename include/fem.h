@@ -91,7 +91,7 @@ fem_status fem_maxcut_create(int device, int32_t n, int64_t n_edges, const int32
  * matrix cores (float32 marginals; a bfloat16 marginal copy gives
  * FEM_E_UNSUPPORTED at solver creation); read-out, evaluation and the
  * manipulated gradients use the sparse structure of W's nonzeros, which the
- * problem also holds.  Device memory: W zero-padded to a multiple of 64 rows
+ * problem also holds.  Device memory: W zero-padded to a multiple of 128 rows
  * and columns (float) plus that structure.  Dense problems are not batched
  * (fem_batch_create gives FEM_E_UNSUPPORTED). */
 fem_status fem_maxcut_create_dense(int device, int32_t n, const float* W, fem_problem** out);

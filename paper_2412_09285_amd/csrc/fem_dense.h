@@ -7,10 +7,13 @@
 namespace fem {
 
 // rows of W (and of the state) per workgroup; a dense problem's tiles are
-// exactly these row blocks, and its matrix is zero-padded to a multiple
+// exactly these row blocks
 constexpr int DENSE_ROWS = 64;
 // replicas per workgroup
 constexpr int DENSE_COLS = 64;
+// W and the int8 digit planes are zero-padded to a multiple of this many
+// columns (the K block of the int8 kernel)
+constexpr int DENSE_LD_ALIGN = 128;
 
 // replica rows of each int8 digit plane of the marginal copy
 inline int dense_rows_padded(int R) { return (R + DENSE_COLS - 1) / DENSE_COLS * DENSE_COLS; }

@@ -36,15 +36,14 @@ typedef int i32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int DK = 32;   // K block of the FP64 kernel
 
-// The step of one (node i, replica r) given its field phi: gradient, the
-// optimiser update of h, m1, m2, energy terms; returns the new marginal and
-// stores the gradient when it is kept.
-template <bool EN, bool NT>
-__device__ __forceinline__ float dense_update(const StepArgs& a, const StepScalars& sc, int i, int r, double phi,
-                                              double& e_mphi, double& e_h2)
+// h, m1, m2 of (node i, replica r).  The kernels load every entry of the
+// lane before the K loop, so that these loads are in flight while the
+// matrix cores run (issued after the first store they would wait for it:
+// the state arrays may alias as far as the compiler knows).
+template <bool NT>
+__device__ __forceinline__ void dense_load(const StepArgs& a, int i, int r, float& x, float& m1v, float& m2v)
 {
     const size_t sbase = (size_t)i * a.srow + r;
-    float x, m1v, m2v;
     if constexpr (NT) {
         x = __builtin_nontemporal_load(a.h + sbase);
         m1v = __builtin_nontemporal_load(a.m1 + sbase);
@@ -54,6 +53,16 @@ __device__ __forceinline__ float dense_update(const StepArgs& a, const StepScala
         m1v = a.m1[sbase];
         m2v = a.m2[sbase];
     }
+}
+
+// The step of one (node i, replica r) given its field phi and loaded state:
+// gradient, the optimiser update of h, m1, m2, energy terms; returns the new
+// marginal and stores the gradient when it is kept.
+template <bool EN, bool NT>
+__device__ __forceinline__ float dense_update(const StepArgs& a, const StepScalars& sc, int i, int r, double phi,
+                                              float x, float m1v, float m2v, double& e_mphi, double& e_h2)
+{
+    const size_t sbase = (size_t)i * a.srow + r;
     const float ax = fabsf(x);
     const float e = expf(-ax);
     const float ope = 1.0f + e;
@@ -110,6 +119,21 @@ __global__ void __launch_bounds__(256) maxcut_dense_step_kernel(StepArgs a, cons
             sB[buf][wave + 4 * u][lane] = rb[u];
         }
     };
+    // this lane's 16 outputs: tile (bm, bn), register v -> row
+    // 16 bm + kq + 4 v of the quarter, replica 16 bn + c16 (the output layout
+    // of the f64 16x16x4 MFMA: lane group kq holds rows kq, kq + 4, kq + 8,
+    // kq + 12 of column c16); their state is loaded up front
+    float xs[2][8], m1s[2][8], m2s[2][8];
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) {
+        const int r = r0 + wn * 32 + 16 * bn + c16;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = i0 + wm * 32 + 16 * (q >> 2) + kq + 4 * (q & 3);
+            xs[bn][q] = m1s[bn][q] = m2s[bn][q] = 0.0f;
+            if (r < R && i < tile.row_end) dense_load<NT>(a, i, r, xs[bn][q], m1s[bn][q], m2s[bn][q]);
+        }
+    }
     f64x4 acc[2][2];   // [16-row tile][16-column tile]
 #pragma unroll
     for (int bm = 0; bm < 2; ++bm)
@@ -145,10 +169,7 @@ __global__ void __launch_bounds__(256) maxcut_dense_step_kernel(StepArgs a, cons
         __syncthreads();
     }
 
-    // epilogue: accumulator v of tile (bm, bn) is phi[row][r] with
-    // row = 16 bm + kq + 4 v within the quarter, r = 16 bn + c16 (the
-    // output layout of the f64 16x16x4 MFMA: lane group kq holds rows
-    // kq, kq + 4, kq + 8, kq + 12 of column c16)
+    // epilogue
     const StepScalars sc = a.sc;
     double e_mphi[2] = {0.0, 0.0}, e_h2[2] = {0.0, 0.0};
 #pragma unroll
@@ -160,7 +181,8 @@ __global__ void __launch_bounds__(256) maxcut_dense_step_kernel(StepArgs a, cons
             const int bm = q >> 2, v = q & 3;
             const int i = i0 + wm * 32 + 16 * bm + kq + 4 * v;
             if (i >= tile.row_end) continue;
-            mn[(size_t)i * R + r] = dense_update<EN, NT>(a, sc, i, r, acc[bm][bn][v], e_mphi[bn], e_h2[bn]);
+            mn[(size_t)i * R + r] = dense_update<EN, NT>(a, sc, i, r, acc[bm][bn][v], xs[bn][q], m1s[bn][q],
+                                                         m2s[bn][q], e_mphi[bn], e_h2[bn]);
         }
     }
     if constexpr (EN) {
@@ -209,8 +231,8 @@ __global__ void __launch_bounds__(256) maxcut_dense_step_kernel(StepArgs a, cons
 // rounded up to 64) rows per plane, so that an MFMA lane's 16 consecutive k
 // values are 16 contiguous bytes of one row; rows j >= n and replicas r >= R
 // hold zeros.
-constexpr int QK = 64;        // K block (bytes of a row per block)
-constexpr int QP = QK + 16;   // LDS row pitch: 16-byte reads of 32 rows stay conflict-free
+constexpr int QK = DENSE_LD_ALIGN;   // K block (bytes of a row per block)
+constexpr int QP = QK + 16;          // LDS row pitch: 16-byte reads of 32 rows stay conflict-free
 
 __device__ __forceinline__ void to_digits(float m, int (&d)[4])
 {
@@ -235,27 +257,52 @@ __global__ void __launch_bounds__(256) maxcut_dense_i8_step_kernel(StepArgs a, c
     const size_t plane = (size_t)Rp * ld;
     const int8_t* __restrict__ qc = static_cast<const int8_t*>(a.marg_cur);
     int8_t* __restrict__ qn = static_cast<int8_t*>(a.marg_nxt);
-    __shared__ __attribute__((aligned(16))) int8_t sA[2][DM][QP];      // W[i0 + m][j0 + k]
-    __shared__ __attribute__((aligned(16))) int8_t sB[2][4][DN][QP];   // q[d][r0 + c][j0 + k]
+    __shared__ __attribute__((aligned(16))) int8_t sA[1][DM][QP];      // W[i0 + m][j0 + k]
+    __shared__ __attribute__((aligned(16))) int8_t sB[1][4][DN][QP];   // q[d][r0 + c][j0 + k]
     __shared__ double sE[2][2][32];                                    // energy partials of waves wm = 1
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;   // the wave's 32 x 32 quarter
     const int kh = lane >> 5, c32 = lane & 31;
-    // staging: thread t moves the 16-byte chunk (t & 3) of row t >> 2 of the
-    // W block and of each digit plane's block
-    const int srow_ = tid >> 2, sch = (tid & 3) * 16;
-    i32x4 ra, rb[4];
+    // staging: 16-byte chunks ck = t + 256 c; chunk ck is piece ck % 8 of row
+    // ck / 8 of the W block (2 per thread), and of row (ck / 8) % 64 of digit
+    // plane ck / 512 (8 per thread).  One LDS buffer: the next block's loads
+    // are in registers while the MFMAs read the current one (a second buffer
+    // at half the block measured slower).
+    i32x4 ra[2], rb[8];
     auto gload = [&](int j0) {
-        ra = *reinterpret_cast<const i32x4*>(W8 + (size_t)(i0 + srow_) * ld + j0 + sch);
 #pragma unroll
-        for (int d = 0; d < 4; ++d)
-            rb[d] = *reinterpret_cast<const i32x4*>(qc + d * plane + (size_t)(r0 + srow_) * ld + j0 + sch);
-    };
-    auto sstore = [&](int buf) {
-        *reinterpret_cast<i32x4*>(&sA[buf][srow_][sch]) = ra;
+        for (int c = 0; c < 2; ++c) {
+            const int ck = tid + 256 * c, row = ck >> 3, ch = (ck & 7) * 16;
+            ra[c] = *reinterpret_cast<const i32x4*>(W8 + (size_t)(i0 + row) * ld + j0 + ch);
+        }
 #pragma unroll
-        for (int d = 0; d < 4; ++d) *reinterpret_cast<i32x4*>(&sB[buf][d][srow_][sch]) = rb[d];
+        for (int c = 0; c < 8; ++c) {
+            const int ck = tid + 256 * c, d = ck >> 9, row = (ck >> 3) & 63, ch = (ck & 7) * 16;
+            rb[c] = *reinterpret_cast<const i32x4*>(qc + d * plane + (size_t)(r0 + row) * ld + j0 + ch);
+        }
     };
+    auto sstore = [&](int) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int ck = tid + 256 * c, row = ck >> 3, ch = (ck & 7) * 16;
+            *reinterpret_cast<i32x4*>(&sA[0][row][ch]) = ra[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int ck = tid + 256 * c, d = ck >> 9, row = (ck >> 3) & 63, ch = (ck & 7) * 16;
+            *reinterpret_cast<i32x4*>(&sB[0][d][row][ch]) = rb[c];
+        }
+    };
+    // this lane's 16 outputs: register v -> row 8 (v / 4) + 4 kh + v % 4 of
+    // the quarter, replica c32; their state is loaded up front
+    const int r = r0 + wn * 32 + c32;
+    float xs[16], m1s[16], m2s[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = i0 + wm * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
+        xs[v] = m1s[v] = m2s[v] = 0.0f;
+        if (r < R && i < tile.row_end) dense_load<NT>(a, i, r, xs[v], m1s[v], m2s[v]);
+    }
     i32x16 acc[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d)
@@ -263,10 +310,10 @@ __global__ void __launch_bounds__(256) maxcut_dense_i8_step_kernel(StepArgs a, c
         for (int v = 0; v < 16; ++v) acc[d][v] = 0;
     const int nk = ld / QK;
     gload(0);
-    sstore(0);
-    __syncthreads();
     for (int kb = 0; kb < nk; ++kb) {
-        const int buf = kb & 1;
+        const int buf = 0;
+        sstore(buf);
+        __syncthreads();
         if (kb + 1 < nk) gload((kb + 1) * QK);
 #pragma unroll
         for (int kk = 0; kk < QK / 32; ++kk) {
@@ -279,16 +326,13 @@ __global__ void __launch_bounds__(256) maxcut_dense_i8_step_kernel(StepArgs a, c
                 acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc[d], 0, 0, 0);
             }
         }
-        if (kb + 1 < nk) sstore(buf ^ 1);
         __syncthreads();
     }
 
-    // epilogue: register v of this lane is (row 8 (v / 4) + 4 kh + v % 4 of
-    // the quarter, replica c32); new marginals go to LDS as digits,
-    // transposed to [d][replica][row], then out as 64-byte rows
+    // epilogue: new marginals go to LDS as digits, transposed to
+    // [d][replica][row], then out as 64-byte rows
     int8_t (*sT)[DN][QP] = reinterpret_cast<int8_t (*)[DN][QP]>(&sB[0][0][0][0]);   // [4][DN][QP]
     const StepScalars sc = a.sc;
-    const int r = r0 + wn * 32 + c32;
     double e_mphi = 0.0, e_h2 = 0.0;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -298,7 +342,7 @@ __global__ void __launch_bounds__(256) maxcut_dense_i8_step_kernel(StepArgs a, c
         if (r < R && i < tile.row_end) {
             const double phi = ((double)acc[3][v] * 16777216.0 + (double)acc[2][v] * 65536.0 +
                                 (double)acc[1][v] * 256.0 + (double)acc[0][v]) * (1.0 / 1073741824.0);
-            mnew = dense_update<EN, NT>(a, sc, i, r, phi, e_mphi, e_h2);
+            mnew = dense_update<EN, NT>(a, sc, i, r, phi, xs[v], m1s[v], m2s[v], e_mphi, e_h2);
         }
         int dg[4];
         to_digits(mnew, dg);

@@ -871,7 +871,7 @@ fem_status fem_maxcut_create_dense(int device, int32_t n, const float* W, fem_pr
     // gradients; the padded matrix the explicit step
     STCHK(build_graph(KIND_MAXCUT, device, n, (int64_t)eu.size(), eu.data(), ev.data(), ew.data(), 2, nullptr, out));
     Problem& p = (*out)->p;
-    const int32_t ld = (n + DENSE_ROWS - 1) / DENSE_ROWS * DENSE_ROWS;
+    const int32_t ld = (n + DENSE_LD_ALIGN - 1) / DENSE_LD_ALIGN * DENSE_LD_ALIGN;
     std::vector<float> pad((size_t)ld * ld, 0.0f);
     for (int32_t i = 0; i < n; ++i) std::memcpy(&pad[(size_t)i * ld], &W[(size_t)i * n], (size_t)n * 4);
     // integral weights of magnitude <= 127 also get the int8 image that the

@@ -184,6 +184,23 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             for (int s = 0; s < Q; ++s) phi[s] = (AccT)0;
             int64_t k = a.row_off[i];
             const int64_t kend = a.row_off[i + 1];
+            for (; k + 4 <= kend; k += 4) {
+                const int2 e0 = a.adj[k], e1 = a.adj[k + 1], e2 = a.adj[k + 2], e3 = a.adj[k + 3];
+                float x0[Q], x1[Q], x2[Q], x3[Q];
+                ld_marg<MT, Q>(mc + (size_t)e0.x * RQ + (size_t)r * Q, x0);
+                ld_marg<MT, Q>(mc + (size_t)e1.x * RQ + (size_t)r * Q, x1);
+                ld_marg<MT, Q>(mc + (size_t)e2.x * RQ + (size_t)r * Q, x2);
+                ld_marg<MT, Q>(mc + (size_t)e3.x * RQ + (size_t)r * Q, x3);
+                const AccT w0 = (AccT)__int_as_float(e0.y), w1 = (AccT)__int_as_float(e1.y);
+                const AccT w2 = (AccT)__int_as_float(e2.y), w3 = (AccT)__int_as_float(e3.y);
+#pragma unroll
+                for (int s = 0; s < Q; ++s) {
+                    phi[s] = fma(w0, (AccT)x0[s], phi[s]);
+                    phi[s] = fma(w1, (AccT)x1[s], phi[s]);
+                    phi[s] = fma(w2, (AccT)x2[s], phi[s]);
+                    phi[s] = fma(w3, (AccT)x3[s], phi[s]);
+                }
+            }
             for (; k + 2 <= kend; k += 2) {
                 const int2 e0 = a.adj[k], e1 = a.adj[k + 1];
                 float x0[Q], x1[Q];
@@ -352,11 +369,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
             CT d[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) d[v] = (CT)0;
-            const int64_t kend = a.row_off[i + 1];
-            for (int64_t k = a.row_off[i]; k < kend; ++k) {
-                const Rec rec = inc[k];
-                uint32_t lit[W];
-                bool own_pos, owner;
+            // literals of an incidence record: the other variables with their
+            // signs, the own sign, and whether this is the clause's owner
+            auto decode = [&](const Rec& rec, uint32_t (&lit)[W], bool& own_pos, bool& owner) {
                 if constexpr (W == 2) {
                     lit[0] = (uint32_t)rec.x; lit[1] = (uint32_t)rec.y;
                     own_pos = (lit[0] & SAT_FLAG) != 0;
@@ -366,18 +381,19 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                     own_pos = (rec.w & 1) != 0;
                     owner = (rec.w & 2) != 0;
                 }
+            };
+            // the cavity product of one incidence from its gathered rows, added
+            // to d (and to the energy at the owner) in incidence order
+            auto combine = [&](const uint32_t (&lit)[W], bool own_pos, bool owner, const float (&x)[W][V]) {
                 float c[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) c[v] = 1.0f;
 #pragma unroll
                 for (int s = 0; s < W; ++s) {
-                    const uint32_t var = lit[s] & SAT_VAR_MASK;
-                    if (var != SAT_NONE) {
-                        float x[V];
-                        ld_marg<MT, V>(mc + (size_t)var * R + rb, x);
+                    if ((lit[s] & SAT_VAR_MASK) != SAT_NONE) {
                         const bool pos = (lit[s] & SAT_POS) != 0;
 #pragma unroll
-                        for (int v = 0; v < V; ++v) c[v] *= sat_u(x[v], pos);
+                        for (int v = 0; v < V; ++v) c[v] *= sat_u(x[s][v], pos);
                     }
                 }
 #pragma unroll
@@ -390,6 +406,37 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                         }
                     }
                 }
+            };
+            auto gather = [&](const uint32_t (&lit)[W], float (&x)[W][V]) {
+#pragma unroll
+                for (int s = 0; s < W; ++s) {
+                    const uint32_t var = lit[s] & SAT_VAR_MASK;
+                    if (var != SAT_NONE) ld_marg<MT, V>(mc + (size_t)var * R + rb, x[s]);
+                }
+            };
+            int64_t k = a.row_off[i];
+            const int64_t kend = a.row_off[i + 1];
+            // two incidences per round: their records, then all their rows, are
+            // in flight together
+            for (; k + 2 <= kend; k += 2) {
+                const Rec r0 = inc[k], r1 = inc[k + 1];
+                uint32_t l0[W], l1[W];
+                bool p0, o0, p1, o1;
+                decode(r0, l0, p0, o0);
+                decode(r1, l1, p1, o1);
+                float x0[W][V], x1[W][V];
+                gather(l0, x0);
+                gather(l1, x1);
+                combine(l0, p0, o0, x0);
+                combine(l1, p1, o1, x1);
+            }
+            for (; k < kend; ++k) {
+                uint32_t l0[W];
+                bool p0, o0;
+                decode(inc[k], l0, p0, o0);
+                float x0[W][V];
+                gather(l0, x0);
+                combine(l0, p0, o0, x0);
             }
             float gv[V], snew[V];
 #pragma unroll
