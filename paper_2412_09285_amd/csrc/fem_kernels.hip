@@ -184,6 +184,20 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             for (int s = 0; s < Q; ++s) phi[s] = (AccT)0;
             int64_t k = a.row_off[i];
             const int64_t kend = a.row_off[i + 1];
+            for (; k + 8 <= kend; k += 8) {
+                int2 e[8];
+                float x[8][Q];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) e[u] = a.adj[k + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) ld_marg<MT, Q>(mc + (size_t)e[u].x * RQ + (size_t)r * Q, x[u]);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const AccT w = (AccT)__int_as_float(e[u].y);
+#pragma unroll
+                    for (int s = 0; s < Q; ++s) phi[s] = fma(w, (AccT)x[u][s], phi[s]);
+                }
+            }
             for (; k + 4 <= kend; k += 4) {
                 const int2 e0 = a.adj[k], e1 = a.adj[k + 1], e2 = a.adj[k + 2], e3 = a.adj[k + 3];
                 float x0[Q], x1[Q], x2[Q], x3[Q];
