@@ -134,10 +134,12 @@ def main():
     ap.add_argument("--retune", action="store_true", help="time every launch shape even if one is cached")
     ap.add_argument("--cpu-replicas", type=int, default=8)
     ap.add_argument("--cpu-steps", type=int, default=150)
-    ap.add_argument("--workload", choices=["maxcut1e5", "bmincut1e6", "max3sat1e5", "k2000dense", "batch512", "copy"],
+    ap.add_argument("--workload", choices=["maxcut1e5", "bmincut1e6", "max3sat1e5", "k2000dense", "er800", "batch512",
+                                           "copy"],
                     default="maxcut1e5",
                     help="maxcut1e5: the throughput line; bmincut1e6 / max3sat1e5: the Potts and Max-3-SAT "
-                         "kernels at full size; k2000dense: the dense-W (matrix-core) path on a complete "
+                         "kernels at full size; er800: a G-set-sized instance (800 nodes, R = 16), launch-bound; "
+                         "k2000dense: the dense-W (matrix-core) path on a complete "
                          "2000-node graph; batch512: time to target on 512 uneven MaxCut instances; "
                          "copy: a plain device copy (calibrates HBM counters)")
     ap.add_argument("--order", choices=["draw", "rcm"], default="rcm",
@@ -211,6 +213,9 @@ WORKLOADS = {
     "max3sat1e5": dict(kind="maxsat", recipe=4, R=64, seed=104, T=2000,
                        name="max3sat_n100000_m800000", counters="max3sat_1e5_R64",
                        data="random 3-SAT, distinct variables, fair signs, ratio 8"),
+    "er800": dict(kind="maxcut", recipe=1, R=16, seed=101, T=500,
+                  name="maxcut_er_n800_e19176", counters="maxcut_er800_R16",
+                  data="Erdos-Renyi G(800, 19176), unit weights"),
     "k2000dense": dict(kind="maxcut_dense", n=2000, R=1000, seed=105, T=1000,
                        name="maxcut_complete_n2000_pm1_dense", counters="maxcut_dense_k2000_R1000",
                        data="complete graph K_2000, +/-1 weights"),
