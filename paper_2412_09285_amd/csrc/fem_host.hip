@@ -408,6 +408,9 @@ struct fem_solver {
     int n_records = 0;
     int last_energy_step = -1;
     double* d_wtot = nullptr;
+    // most tiles of one instance: up to ENERGY_FINISH_TILES the energies are
+    // reduced in one launch, beyond in two stages plus the combination
+    int max_inst_tiles = 0;
     // bMinCut column sums
     long long* cpart = nullptr;
     long long* ctmp = nullptr;
@@ -520,6 +523,10 @@ static void drop_graphs(fem_solver* s)
 // tiles an XCD receives form one contiguous row range; with several segments
 // the grid is segment-major (consecutive blocks = segments of one tile; while
 // the tile count fits grid.y) and the tiles keep their natural order.
+// instances of at most this many tiles take the one-launch energy reduction
+// (one workgroup per instance and 32 replicas reads all their partials)
+constexpr int ENERGY_FINISH_TILES = 256;
+
 static fem_status setup_tiling(fem_solver* s, const TileShape& shape)
 {
     const Problem& p = *s->prob;
@@ -556,6 +563,10 @@ static fem_status setup_tiling(fem_solver* s, const TileShape& shape)
     }
     s->n_tiles = (int)tiles.size();
     s->n_chunks = (int)chunk_off.size() - 1;
+    s->max_inst_tiles = 0;
+    for (int b = 0; b < s->n_inst; ++b)
+        s->max_inst_tiles = std::max(s->max_inst_tiles, chunk_off[(size_t)inst_chunk_off[(size_t)b + 1]] -
+                                                            chunk_off[(size_t)inst_chunk_off[(size_t)b]]);
     // XCD-aware dispatch order: position pos runs on XCD pos % 8; XCD x gets
     // the contiguous tile range [start_x, start_x + cnt_x), cnt_x differing by
     // at most one between XCDs, so every position holds exactly one tile.
@@ -736,10 +747,16 @@ static fem_status do_step(fem_solver* s)
     if (e1) HIPCHK(hipEventRecord(e1, s->stream));
     if (en) {
         double* slot = energy_slot(s, t);
-        HIPCHK(launch_seg_reduce<double>(s->epart, s->NE * s->R, s->d_chunk_off, s->n_chunks, s->d_inst_chunk_off,
-                                         s->n_inst, s->etmp, s->eraw, s->stream));
-        HIPCHK(launch_energy_combine(s->kind, s->R, s->q, s->n_inst, s->eraw, s->d_wtot, s->csum, s->lam[(size_t)t],
-                                     s->beta[(size_t)t], slot, s->stream));
+        if (s->max_inst_tiles <= ENERGY_FINISH_TILES) {
+            HIPCHK(launch_energy_finish(s->kind, s->R, s->q, s->NE, s->n_inst, s->epart, s->d_chunk_off,
+                                        s->d_inst_chunk_off, s->d_wtot, s->csum, s->lam[(size_t)t],
+                                        s->beta[(size_t)t], slot, s->stream));
+        } else {
+            HIPCHK(launch_seg_reduce<double>(s->epart, s->NE * s->R, s->d_chunk_off, s->n_chunks,
+                                             s->d_inst_chunk_off, s->n_inst, s->etmp, s->eraw, s->stream));
+            HIPCHK(launch_energy_combine(s->kind, s->R, s->q, s->n_inst, s->eraw, s->d_wtot, s->csum,
+                                         s->lam[(size_t)t], s->beta[(size_t)t], slot, s->stream));
+        }
         s->last_energy_step = t;
     }
     if (s->kind == KIND_BMINCUT) STCHK(finish_colsums(s));

@@ -147,6 +147,12 @@ template <typename T>
 hipError_t launch_seg_reduce(const T* part, int cols, const int32_t* chunk_off, int n_chunks,
                              const int32_t* inst_chunk_off, int n_inst, T* tmp, T* out,
                              hipStream_t st);
+// the same energies from the per-tile partials in one launch (instances of
+// few tiles): part [tile][NE][R], tiles of instance b from chunk
+// inst_chunk_off[b] to inst_chunk_off[b + 1]
+hipError_t launch_energy_finish(int kind, int R, int q, int NE, int n_inst, const double* part,
+                                const int32_t* chunk_off, const int32_t* inst_chunk_off, const double* wtot,
+                                const double* csum, double lam, double beta, double* eout, hipStream_t st);
 hipError_t launch_energy_combine(int kind, int R, int q, int n_inst, const double* raw,
                                  const double* wtot, const double* csum, double lam, double beta,
                                  double* eout, hipStream_t st);

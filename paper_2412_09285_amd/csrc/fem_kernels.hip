@@ -580,6 +580,64 @@ static hipError_t seg_reduce2(const T* part, int cols, const int32_t* chunk_off,
     return hipGetLastError();
 }
 
+// Energies straight from the per-tile partials [tile][NE][R], one launch:
+// block (inst, replica group of 32) sums the instance's tiles in 8 strided
+// sub-sums added in fixed order, then forms U, S, F.  For instances of few
+// tiles, where the two-stage reduction and the combination cost three
+// launches for a few thousand values.
+template <int NE>
+__global__ void __launch_bounds__(256) energy_finish_kernel(int kind, int R, int q, const double* __restrict__ part,
+                                                            const int32_t* __restrict__ chunk_off,
+                                                            const int32_t* __restrict__ inst_chunk_off,
+                                                            const double* __restrict__ wtot,
+                                                            const double* __restrict__ csum, double lam,
+                                                            double beta, double* __restrict__ eout)
+{
+    __shared__ double lds[NE][256];
+    const int inst = blockIdx.x;
+    const int r = blockIdx.y * 32 + (threadIdx.x & 31);
+    const int sub = threadIdx.x >> 5;
+    const int t0 = chunk_off[inst_chunk_off[inst]], t1 = chunk_off[inst_chunk_off[inst + 1]];
+    double acc[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) acc[k] = 0.0;
+    if (r < R)
+        for (int t = t0 + sub; t < t1; t += 8)
+#pragma unroll
+            for (int k = 0; k < NE; ++k) acc[k] += part[((size_t)t * NE + k) * R + r];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) lds[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    if (sub == 0 && r < R) {
+        double x[NE];
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            double v = lds[k][threadIdx.x];
+            for (int s = 1; s < 8; ++s) v += lds[k][s * 32 + threadIdx.x];
+            x[k] = v;
+        }
+        // U, S, F as energy_combine_kernel forms them
+        double U, S;
+        if (kind == KIND_MAXCUT) {
+            U = -wtot[inst] + 0.5 * x[0];
+            S = x[1];
+        } else if (kind == KIND_MAXSAT) {
+            U = x[0];
+            S = x[1];
+        } else {
+            const double* C = csum + ((size_t)inst * R + r) * q;
+            double c2 = 0.0;
+            for (int s = 0; s < q; ++s) c2 += C[s] * C[s];
+            U = x[0] + lam * (c2 - x[1]);
+            S = x[NE - 1];
+        }
+        double* o = eout + (size_t)inst * 3 * R;
+        o[r] = U;
+        o[R + r] = S;
+        o[2 * R + r] = U - S / beta;
+    }
+}
+
 // energies: raw[inst][NE][R] -> eout[inst][3][R] = U, S, F
 __global__ void energy_combine_kernel(int kind, int R, int q, int n_inst, const double* __restrict__ raw,
                                       const double* __restrict__ wtot, const double* __restrict__ csum,
@@ -913,6 +971,23 @@ template hipError_t launch_seg_reduce<long long>(const long long*, int, const in
                                                  long long*, long long*, hipStream_t);
 template hipError_t launch_seg_reduce<int>(const int*, int, const int32_t*, int, const int32_t*, int, int*, int*,
                                            hipStream_t);
+
+hipError_t launch_energy_finish(int kind, int R, int q, int NE, int n_inst, const double* part,
+                                const int32_t* chunk_off, const int32_t* inst_chunk_off, const double* wtot,
+                                const double* csum, double lam, double beta, double* eout, hipStream_t st)
+{
+    (void)hipGetLastError();   // drop stale errors of earlier calls
+    const dim3 g(n_inst, (R + 31) / 32);
+    if (NE == 2)
+        energy_finish_kernel<2><<<g, 256, 0, st>>>(kind, R, q, part, chunk_off, inst_chunk_off, wtot, csum, lam, beta,
+                                                   eout);
+    else if (NE == 3)
+        energy_finish_kernel<3><<<g, 256, 0, st>>>(kind, R, q, part, chunk_off, inst_chunk_off, wtot, csum, lam, beta,
+                                                   eout);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 hipError_t launch_energy_combine(int kind, int R, int q, int n_inst, const double* raw, const double* wtot,
                                  const double* csum, double lam, double beta, double* eout, hipStream_t st)
