@@ -126,7 +126,7 @@ def main():
     log(f"trained in {time.time() - t2:.1f} s")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     net.save(args.out)
-    print(json.dumps({"params": args.out, "instances": len(graphs), "loss_per_epoch": hist,
+    print(json.dumps({"params": os.path.basename(args.out), "instances": len(graphs), "loss_per_epoch": hist,
                       "label_seconds": time.time() - t1, "train_seconds": time.time() - t2}))
 
 
