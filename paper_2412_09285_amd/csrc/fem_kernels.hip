@@ -90,7 +90,20 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                     acc[v] = fma(w3, (CT)x3[v], acc[v]);
                 }
             }
-            for (; k < kend; ++k) {
+            if (k + 2 <= kend) {   // a remaining pair in one round
+                const int2 e0 = a.adj[k], e1 = a.adj[k + 1];
+                float x0[V], x1[V];
+                ld_marg<MT, V>(mc + (size_t)e0.x * R + rb, x0);
+                ld_marg<MT, V>(mc + (size_t)e1.x * R + rb, x1);
+                const CT w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    acc[v] = fma(w0, (CT)x0[v], acc[v]);
+                    acc[v] = fma(w1, (CT)x1[v], acc[v]);
+                }
+                k += 2;
+            }
+            if (k < kend) {
                 const int2 e0 = a.adj[k];
                 float x0[V];
                 ld_marg<MT, V>(mc + (size_t)e0.x * R + rb, x0);

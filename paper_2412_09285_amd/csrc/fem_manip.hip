@@ -76,7 +76,19 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_manip
                     acc[v] += ((b3 >> v) & 1u) ? w3 : -w3;
                 }
             }
-            for (; k < kend; ++k) {
+            if (k + 2 <= kend) {   // a remaining pair in one round
+                const int2 e0 = a.adj[k], e1 = a.adj[k + 1];
+                const uint32_t b0 = bc[(size_t)e0.x * a.rw + word] >> shift;
+                const uint32_t b1 = bc[(size_t)e1.x * a.rw + word] >> shift;
+                const double w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    acc[v] += ((b0 >> v) & 1u) ? w0 : -w0;
+                    acc[v] += ((b1 >> v) & 1u) ? w1 : -w1;
+                }
+                k += 2;
+            }
+            if (k < kend) {
                 const int2 e0 = a.adj[k];
                 const uint32_t b0 = bc[(size_t)e0.x * a.rw + word] >> shift;
                 const double w0 = __int_as_float(e0.y);
