@@ -133,7 +133,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--retune", action="store_true", help="time every launch shape even if one is cached")
     ap.add_argument("--cpu-replicas", type=int, default=8)
-    ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--cpu-steps", type=int, default=400,
+                    help="oracle steps of the CPU baseline sample (8 replicas by default): 10-20 s of CPU work")
     ap.add_argument("--workload", choices=["maxcut1e5", "bmincut1e6", "max3sat1e5", "k2000dense", "er800", "batch512",
                                            "copy"],
                     default="maxcut1e5",
