@@ -1,9 +1,14 @@
 // Dense-W MaxCut step for complete or near-complete graphs on gfx950 matrix
 // cores.
 //
-// On a complete graph the field product phi = W m (m = tanh(h/2), the stored
-// marginal copy, node-major [n][R]) is a dense matrix product n x n x R, so
-// it runs on MFMA instead of the gather of the sparse kernel: a workgroup of
+// On a complete graph the field product phi = W m (m = tanh(h/2)) is a dense
+// matrix product n x n x R, so it runs on MFMA instead of the gather of the
+// sparse kernel.  Two kernels, both as exact as the sparse kernel's FP64
+// accumulation: for integral weights (|W| <= 127) int8 products of the
+// fixed-point marginals' digit planes (maxcut_dense_i8_step_kernel, second
+// half of this file); for any other W the FP64 kernel below.
+//
+// FP64 kernel: the marginal copy is float, node-major [n][R]; a workgroup of
 // four waves owns a 64-row x 64-replica block of phi, each wave a 32 x 32
 // quarter held as 2 x 2 tiles of v_mfma_f64_16x16x4_f64 accumulators.  The
 // products and sums are formed in double, as the sparse kernel accumulates:
@@ -257,8 +262,8 @@ __global__ void __launch_bounds__(256) maxcut_dense_i8_step_kernel(StepArgs a, c
     const size_t plane = (size_t)Rp * ld;
     const int8_t* __restrict__ qc = static_cast<const int8_t*>(a.marg_cur);
     int8_t* __restrict__ qn = static_cast<int8_t*>(a.marg_nxt);
-    __shared__ __attribute__((aligned(16))) int8_t sA[1][DM][QP];      // W[i0 + m][j0 + k]
-    __shared__ __attribute__((aligned(16))) int8_t sB[1][4][DN][QP];   // q[d][r0 + c][j0 + k]
+    __shared__ __attribute__((aligned(16))) int8_t sA[DM][QP];      // W[i0 + m][j0 + k]
+    __shared__ __attribute__((aligned(16))) int8_t sB[4][DN][QP];   // q[d][r0 + c][j0 + k]
     __shared__ double sE[2][2][32];                                    // energy partials of waves wm = 1
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;   // the wave's 32 x 32 quarter
@@ -281,16 +286,16 @@ __global__ void __launch_bounds__(256) maxcut_dense_i8_step_kernel(StepArgs a, c
             rb[c] = *reinterpret_cast<const i32x4*>(qc + d * plane + (size_t)(r0 + row) * ld + j0 + ch);
         }
     };
-    auto sstore = [&](int) {
+    auto sstore = [&]() {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const int ck = tid + 256 * c, row = ck >> 3, ch = (ck & 7) * 16;
-            *reinterpret_cast<i32x4*>(&sA[0][row][ch]) = ra[c];
+            *reinterpret_cast<i32x4*>(&sA[row][ch]) = ra[c];
         }
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int ck = tid + 256 * c, d = ck >> 9, row = (ck >> 3) & 63, ch = (ck & 7) * 16;
-            *reinterpret_cast<i32x4*>(&sB[0][d][row][ch]) = rb[c];
+            *reinterpret_cast<i32x4*>(&sB[d][row][ch]) = rb[c];
         }
     };
     // this lane's 16 outputs: register v -> row 8 (v / 4) + 4 kh + v % 4 of
@@ -311,18 +316,17 @@ __global__ void __launch_bounds__(256) maxcut_dense_i8_step_kernel(StepArgs a, c
     const int nk = ld / QK;
     gload(0);
     for (int kb = 0; kb < nk; ++kb) {
-        const int buf = 0;
-        sstore(buf);
+        sstore();
         __syncthreads();
         if (kb + 1 < nk) gload((kb + 1) * QK);
 #pragma unroll
         for (int kk = 0; kk < QK / 32; ++kk) {
             // lane (kh, c32) supplies k = 32 kk + 16 kh + e, e = 0..15, of row
             // c32 of A and of column c32 of B (the same pairing on both sides)
-            const i32x4 av = *reinterpret_cast<const i32x4*>(&sA[buf][wm * 32 + c32][32 * kk + 16 * kh]);
+            const i32x4 av = *reinterpret_cast<const i32x4*>(&sA[wm * 32 + c32][32 * kk + 16 * kh]);
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
-                const i32x4 bv = *reinterpret_cast<const i32x4*>(&sB[buf][d][wn * 32 + c32][32 * kk + 16 * kh]);
+                const i32x4 bv = *reinterpret_cast<const i32x4*>(&sB[d][wn * 32 + c32][32 * kk + 16 * kh]);
                 acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc[d], 0, 0, 0);
             }
         }
@@ -331,7 +335,7 @@ __global__ void __launch_bounds__(256) maxcut_dense_i8_step_kernel(StepArgs a, c
 
     // epilogue: new marginals go to LDS as digits, transposed to
     // [d][replica][row], then out as 64-byte rows
-    int8_t (*sT)[DN][QP] = reinterpret_cast<int8_t (*)[DN][QP]>(&sB[0][0][0][0]);   // [4][DN][QP]
+    int8_t (*sT)[DN][QP] = sB;   // [4][DN][QP]: the staging buffer, free after the K loop
     const StepScalars sc = a.sc;
     double e_mphi = 0.0, e_h2 = 0.0;
 #pragma unroll
