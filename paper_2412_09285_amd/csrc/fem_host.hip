@@ -492,6 +492,7 @@ static bool valid_shape(const fem_solver* s, const TileShape& t)
     const int k_step = (s->kind == KIND_BMINCUT) ? std::max(s->q, 3) : 2 * t.vec;
     const int k_eval = (s->kind == KIND_BMINCUT) ? s->q : 1;
     if ((size_t)t.waves * g.lanes * k_step * 8 > LDS_LIMIT) return false;
+    if (s->kind == KIND_BMINCUT && potts_step_lds(64 * t.waves, g.lanes, s->q) > LDS_LIMIT) return false;
     if ((size_t)t.waves * ge.lanes * k_eval * 8 > LDS_LIMIT) return false;
     return true;
 }

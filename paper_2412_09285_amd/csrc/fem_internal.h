@@ -74,6 +74,16 @@ __host__ __device__ constexpr int step_max_threads(int kind, int per_lane)
                                 : (per_lane >= 8 ? 512 : 1024);
 }
 
+// bMinCut step kernel: per-lane running sums in LDS up to q = 16 (q + 3
+// doubles per thread); the block reduction reuses that space
+__host__ __device__ constexpr bool potts_lds_acc(int q) { return q <= 16; }
+inline size_t potts_step_lds(int threads, int lanes, int q)
+{
+    const size_t red = (size_t)(threads / 64) * lanes * (q > 3 ? q : 3) * 8;
+    const size_t acc = potts_lds_acc(q) ? (size_t)threads * (q + 3) * 8 : 0;
+    return red > acc ? red : acc;
+}
+
 struct TileShape {
     int vec = 1, waves = 4, rows = 4;
     int nt = 0;      // non-temporal access to h, m1, m2

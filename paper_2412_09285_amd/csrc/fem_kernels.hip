@@ -159,6 +159,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
 // Energies per replica: [sum_i (sum_j W_ij - P_i.Phi_i), sum_i |P_i|^2,
 // -sum_i P_i.ln P_i].  Column sums of the new marginals go out as 2^-40
 // fixed point.
+// Up to q = 16 each lane keeps its running column sums and energies in its
+// own LDS slots (potts_acc_doubles per thread), and a row's h, m1, m2 are
+// loaded after its gather: the registers go to the neighbour rows in flight
+// (at q = 8: 121 VGPRs, 4 waves per SIMD, instead of 164 and 3).  The sums
+// are formed in the same order either way.
 template <int Q, typename MT, bool EN, bool NT>
 __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_kernel(StepArgs a)
 {
@@ -177,21 +182,38 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
     // 8 bits, so float is exact enough there
     using AccT = typename std::conditional<(Q <= 8 && sizeof(MT) == 4), double, float>::type;
     using CT = typename std::conditional<sizeof(MT) == 4, double, float>::type;
-    AccT ct[Q];
+    constexpr bool LA = potts_lds_acc(Q);
+    extern __shared__ double lds_d[];
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    // LA: slot [s][tid] of cs_l holds column sum s, slot [k][tid] of ea_l energy k
+    long long* cs_l = reinterpret_cast<long long*>(lds_d);
+    double* ea_l = lds_d + (size_t)Q * nthr;
+    AccT ctr[LA ? 1 : Q];
     double eacc[3] = {0.0, 0.0, 0.0};
     long long cs[Q];
 #pragma unroll
     for (int s = 0; s < Q; ++s) cs[s] = 0;
-    if (act) {
+    if constexpr (LA) {
 #pragma unroll
-        for (int s = 0; s < Q; ++s) ct[s] = (AccT)a.ctil[((size_t)tile.inst * R + r) * Q + s];
+        for (int s = 0; s < Q; ++s) cs_l[s * nthr + tid] = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ea_l[k * nthr + tid] = 0.0;
+    }
+    if (act) {
+        const double* ctp = a.ctil + ((size_t)tile.inst * R + r) * Q;
+        if constexpr (!LA) {
+#pragma unroll
+            for (int s = 0; s < Q; ++s) ctr[s] = (AccT)ctp[s];
+        }
         for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
             const size_t base = ((size_t)i * R + r) * Q;
             const size_t sbase = (size_t)i * a.srow + (size_t)r * Q;   // h, m1, m2 rows
             float hv[Q], m1v[Q], m2v[Q];
-            ld_state<Q, NT>(a.h + sbase, hv);
-            ld_state<Q, NT>(a.m1 + sbase, m1v);
-            ld_state<Q, NT>(a.m2 + sbase, m2v);
+            if constexpr (!LA) {
+                ld_state<Q, NT>(a.h + sbase, hv);
+                ld_state<Q, NT>(a.m1 + sbase, m1v);
+                ld_state<Q, NT>(a.m2 + sbase, m2v);
+            }
             AccT phi[Q];
 #pragma unroll
             for (int s = 0; s < Q; ++s) phi[s] = (AccT)0;
@@ -248,6 +270,17 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
 #pragma unroll
                 for (int s = 0; s < Q; ++s) phi[s] = fma(w0, (AccT)x0[s], phi[s]);
             }
+            AccT ct[Q];
+            if constexpr (LA) {
+                ld_state<Q, NT>(a.h + sbase, hv);
+                ld_state<Q, NT>(a.m1 + sbase, m1v);
+                ld_state<Q, NT>(a.m2 + sbase, m2v);
+#pragma unroll
+                for (int s = 0; s < Q; ++s) ct[s] = (AccT)ctp[s];
+            } else {
+#pragma unroll
+                for (int s = 0; s < Q; ++s) ct[s] = ctr[LA ? 0 : s];
+            }
             // softmax of the current fields
             float mx = hv[0];
 #pragma unroll
@@ -290,9 +323,12 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
                     sq = fmaf(vw * P[s], vw * P[s], sq);
                     ent = fmaf(-P[s], hv[s] - mx - lz, ent);
                 }
-                eacc[0] += (double)a.wdeg[i] - dot;
-                eacc[1] += (double)sq;
-                eacc[2] += (double)ent;
+                const double e3[3] = {(double)a.wdeg[i] - dot, (double)sq, (double)ent};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    if constexpr (LA) ea_l[k * nthr + tid] += e3[k];
+                    else eacc[k] += e3[k];
+                }
             }
             // Adam, then the softmax of the new fields
 #pragma unroll
@@ -310,11 +346,19 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             // marginals (their rounding, summed over all nodes, would carry
             // into the balance term); the float softmax for bfloat16 ones,
             // whose own rounding is 2^-8
+            if constexpr (LA) {
+#pragma unroll
+                for (int s = 0; s < Q; ++s) cs[s] = 0;
+            }
             if constexpr (sizeof(MT) == 4) {
                 colsum_add<Q>(hv, cs, (double)vw);
             } else {
 #pragma unroll
                 for (int s = 0; s < Q; ++s) cs[s] += to_fixed((double)vw * (double)Pn[s]);
+            }
+            if constexpr (LA) {
+#pragma unroll
+                for (int s = 0; s < Q; ++s) cs_l[s * nthr + tid] += cs[s];
             }
             st_state<Q, NT>(a.h + sbase, hv);
             st_state<Q, NT>(a.m1 + sbase, m1v);
@@ -323,7 +367,14 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             if (a.grad) st_f32<Q>(a.grad + base, gv);
         }
     }
-    extern __shared__ double lds_d[];
+    if constexpr (LA) {
+        // every lane reads its own slots before the reduction reuses the LDS
+#pragma unroll
+        for (int s = 0; s < Q; ++s) cs[s] = cs_l[s * nthr + tid];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) eacc[k] = ea_l[k * nthr + tid];
+        __syncthreads();
+    }
     block_reduce_store<long long, Q>(cs, ti, a.lanes_log2, reinterpret_cast<long long*>(lds_d),
                                      [&](int s, int l, long long v) {
                                          const int rr = seg * ti.L + l;
@@ -877,7 +928,7 @@ static void launch_sat(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStr
 template <int Q, typename MT, bool NT>
 static void launch_potts(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStream_t st)
 {
-    const size_t lds = lds_bytes(b.x / 64, L, Q > 3 ? Q : 3);
+    const size_t lds = potts_step_lds(b.x, L, Q);
     if (en) potts_step_kernel<Q, MT, true, NT><<<g, b, lds, st>>>(a);
     else potts_step_kernel<Q, MT, false, NT><<<g, b, lds, st>>>(a);
 }
