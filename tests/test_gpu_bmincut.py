@@ -68,6 +68,14 @@ def test_tile_shapes(waves, rows, lanes):
                    tag=f"tile{waves}x{rows}L{lanes}")
 
 
+@pytest.mark.parametrize("q,waves", [(2, 16), (4, 16), (16, 4)])
+def test_largest_workgroups(q, waves):
+    """The largest workgroup each q allows: the step kernel's per-lane LDS sums
+    (q + 3 doubles per thread) are largest here (q = 4: 57 KB)."""
+    lockstep_potts(W.rgg_3d(400, 12.0, seed=9), q, R=16, T=80, n_steps=8, seed=11, tile=(8, waves, 2, 0, 0),
+                   tag=f"q{q}_waves{waves}")
+
+
 def test_integer_eval_sizes_bitexact():
     rng = np.random.default_rng(1)
     g = W.rgg_3d(800, 12.0, seed=9)
