@@ -160,10 +160,10 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
 // -sum_i P_i.ln P_i].  Column sums of the new marginals go out as 2^-40
 // fixed point.
 // Up to q = 16 each lane keeps its running column sums and energies in its
-// own LDS slots (potts_acc_doubles per thread), and a row's h, m1, m2 are
-// loaded after its gather: the registers go to the neighbour rows in flight
-// (at q = 8: 121 VGPRs, 4 waves per SIMD, instead of 164 and 3).  The sums
-// are formed in the same order either way.
+// own LDS slots (q + 3 doubles per thread, potts_step_lds), and a row's h,
+// m1, m2 are loaded after its gather: the registers go to the neighbour rows
+// in flight (at q = 8: 121 VGPRs, 4 waves per SIMD, instead of 164 and 3).
+// The sums are formed in the same order either way.
 template <int Q, typename MT, bool EN, bool NT>
 __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_kernel(StepArgs a)
 {
@@ -178,8 +178,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
     // Phi accumulates and the gradient terms combine in double for float32
-    // marginals up to q = 8 (register budget above); bfloat16 marginals carry
-    // 8 bits, so float is exact enough there
+    // marginals up to q = 8 (at larger q the registers would not hold it);
+    // bfloat16 marginals carry 8 bits, so float is exact enough there
     using AccT = typename std::conditional<(Q <= 8 && sizeof(MT) == 4), double, float>::type;
     using CT = typename std::conditional<sizeof(MT) == 4, double, float>::type;
     constexpr bool LA = potts_lds_acc(Q);
