@@ -22,8 +22,9 @@
 // [-1, 1) is the top 24 bits of a word times 2^-23, minus one (exact).
 //
 // Determinism: every sum runs in a fixed order (neighbour order of the CSR,
-// butterfly within a wave, rows in order within a workgroup, workgroups in
-// order in the final reduction).
+// the matrix-core steps of layer 2 in a fixed sequence, butterflies within a
+// wave, rows in order within a workgroup, workgroups in order in the final
+// reduction).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -45,6 +46,8 @@ constexpr int OFF_A1 = 0, OFF_B1 = 512, OFF_b1 = 1024, OFF_A2 = 1088, OFF_B2 = 5
               OFF_d = 9408;
 constexpr int NP = 9409;
 constexpr int WG_BLOCKS = 512;   // workgroups of the weight-gradient reduction
+
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
@@ -84,12 +87,6 @@ __device__ __forceinline__ float upm1(uint32_t w) { return (float)(w >> 8) * 0x1
 __device__ __forceinline__ float lane_val(float x, int k)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
-}
-
-__device__ __forceinline__ float wave_sum(float v)
-{
-    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-    return v;
 }
 
 // ------------------------------------------------------------- forward ----
@@ -186,98 +183,152 @@ __global__ void __launch_bounds__(256) layer1_kernel(int32_t n, const int64_t* _
     }
 }
 
-// Layer 2, four nodes per wave at a time.
-// Gather: team t (16 lanes) takes node i0 + t; lane l of the team reads hidden
-// units 4l..4l+3 of each neighbour's layer-1 pre-activation row (one float4 of
-// a 256-byte row, ReLU applied on load), four neighbours in flight, so the
-// four nodes' dependency chains run side by side.  (Recomputing H1 from the
-// neighbours' 16 layer-1 inputs instead reads 64 bytes per neighbour but costs
-// 64 FMAs per lane per neighbour; measured slower end to end.)
-// Dense: [A2; B2] (128 x 64, float) sits in LDS, shared by the workgroup; the
-// four nodes' [H1 | a(H1)] are staged in the wave's LDS slice and lane j (=
-// output unit) reads one weight per k (a conflict-free 256-byte row) and the
-// nodes' inputs as broadcasts, so each weight read feeds four FMAs.  Every sum
-// runs in the order of a single-node evaluation (CSR order for a(H1); k =
-// 0..63 of H1, then 0..63 of a(H1), for pre2).
-constexpr int L2_NB = 4;
-__global__ void __launch_bounds__(256) layer2_kernel(int32_t n, const int64_t* __restrict__ row_off,
+// Layer 2 on the matrix cores, sixteen nodes per wave at a time.
+// Gather: lane l = 16 g + i takes node i0 + i and hidden units 16 g .. 16 g +
+// 15 of its own and its neighbours' layer-1 pre-activation rows (four float4
+// of a 256-byte row, ReLU applied on load, two neighbours in flight); every
+// a(H1) sum runs in CSR order, as in a single-node evaluation.
+// Dense: pre2 for the 16 nodes is four 16 x 16 output tiles (16 units each),
+// each 32 steps of v_mfma_f32_16x16x4_f32 (A: nodes x 4 inputs, B: 4 inputs x
+// units).  Step s of the H1 half takes the inputs 16 g' + s (g' = 0..3), so a
+// lane supplies its own s-th gathered value as its A element and nothing is
+// staged; the a(H1) half follows.  [A2; B2] (128 x 64, float) sits in LDS
+// with rows padded to W2_LD = 65 floats, which puts the four input rows of a
+// step in distinct banks.  Output element (node 4 g + v, unit 16 t + i) is
+// register v of lane l in tile t.  Each output depends on its own node's
+// inputs only, in a fixed order.
+constexpr int L2_NB = 16;
+constexpr int W2_LD = 65;
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) layer2_kernel(int32_t n, const int64_t* __restrict__ row_off,
                                                      const int2* __restrict__ adj, const float* __restrict__ inv_deg,
                                                      const uint16_t* __restrict__ w, const float* __restrict__ pre1,
                                                      float* __restrict__ a2out, float* __restrict__ pre2out,
                                                      float* __restrict__ z)
 {
-    __shared__ float sW[2 * HID * HID];                // [k][j], k < 64: A2, k >= 64: B2
-    __shared__ float4 sx[4][L2_NB][2 * HID / 4];       // per wave: L2_NB nodes x [H1 | a2]
+    __shared__ float sW[2 * HID * W2_LD];   // row k < 64: A2[k][:], row 64 + k: B2[k][:]
     for (int t = threadIdx.x; t < HID * HID; t += blockDim.x) {
-        sW[t] = bf(w[OFF_A2 + t]);
-        sW[HID * HID + t] = bf(w[OFF_B2 + t]);
+        const int k = t / HID, j = t % HID;
+        sW[k * W2_LD + j] = bf(w[OFF_A2 + t]);
+        sW[(HID + k) * W2_LD + j] = bf(w[OFF_B2 + t]);
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int wl = threadIdx.x >> 6;
-    const int team = lane >> 4, tl = lane & 15;
+    const int g = lane >> 4, li = lane & 15;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
-    const float bias = bf(w[OFF_b2 + lane]);
-    const float cl = bf(w[OFF_c + lane]);
+    float bias[4], cl[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        bias[t] = bf(w[OFF_b2 + 16 * t + li]);
+        cl[t] = bf(w[OFF_c + 16 * t + li]);
+    }
     const float dd = bf(w[OFF_d]);
-    auto relu4 = [](float4 v) { return make_float4(fmaxf(v.x, 0.0f), fmaxf(v.y, 0.0f), fmaxf(v.z, 0.0f), fmaxf(v.w, 0.0f)); };
+    auto relu = [](float x) { return fmaxf(x, 0.0f); };
     for (int i0 = wave * L2_NB; i0 < n; i0 += nw * L2_NB) {
-        const int cnt = (n - i0) < L2_NB ? (n - i0) : L2_NB;
-        const int i = i0 + team;
+        const int i = i0 + li;
+        float hs[16], ag[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            hs[u] = 0.0f;
+            ag[u] = 0.0f;
+        }
         if (i < n) {
-            const float4 h = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)i * HID)[tl]);
-            float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+            const float4* hp = reinterpret_cast<const float4*>(pre1 + (size_t)i * HID + 16 * g);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float4 v = hp[c];
+                hs[4 * c] = relu(v.x); hs[4 * c + 1] = relu(v.y); hs[4 * c + 2] = relu(v.z); hs[4 * c + 3] = relu(v.w);
+            }
             int64_t k = row_off[i];
             const int64_t kend = row_off[i + 1];
-            for (; k + 4 <= kend; k += 4) {
-                const int2 e0 = adj[k], e1 = adj[k + 1], e2 = adj[k + 2], e3 = adj[k + 3];
-                const float4 v0 = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e0.x * HID)[tl]);
-                const float4 v1 = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e1.x * HID)[tl]);
-                const float4 v2 = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e2.x * HID)[tl]);
-                const float4 v3 = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e3.x * HID)[tl]);
+            for (; k + 2 <= kend; k += 2) {
+                const int2 e0 = adj[k], e1 = adj[k + 1];
+                const float4* p0 = reinterpret_cast<const float4*>(pre1 + (size_t)e0.x * HID + 16 * g);
+                const float4* p1 = reinterpret_cast<const float4*>(pre1 + (size_t)e1.x * HID + 16 * g);
+                float4 v0[4], v1[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    v0[c] = p0[c];
+                    v1[c] = p1[c];
+                }
                 const float w0 = __int_as_float(e0.y), w1 = __int_as_float(e1.y);
-                const float w2 = __int_as_float(e2.y), w3 = __int_as_float(e3.y);
-                a0 = fmaf(w0, v0.x, a0); a1 = fmaf(w0, v0.y, a1); a2 = fmaf(w0, v0.z, a2); a3 = fmaf(w0, v0.w, a3);
-                a0 = fmaf(w1, v1.x, a0); a1 = fmaf(w1, v1.y, a1); a2 = fmaf(w1, v1.z, a2); a3 = fmaf(w1, v1.w, a3);
-                a0 = fmaf(w2, v2.x, a0); a1 = fmaf(w2, v2.y, a1); a2 = fmaf(w2, v2.z, a2); a3 = fmaf(w2, v2.w, a3);
-                a0 = fmaf(w3, v3.x, a0); a1 = fmaf(w3, v3.y, a1); a2 = fmaf(w3, v3.z, a2); a3 = fmaf(w3, v3.w, a3);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    ag[4 * c] = fmaf(w0, relu(v0[c].x), ag[4 * c]);
+                    ag[4 * c + 1] = fmaf(w0, relu(v0[c].y), ag[4 * c + 1]);
+                    ag[4 * c + 2] = fmaf(w0, relu(v0[c].z), ag[4 * c + 2]);
+                    ag[4 * c + 3] = fmaf(w0, relu(v0[c].w), ag[4 * c + 3]);
+                    ag[4 * c] = fmaf(w1, relu(v1[c].x), ag[4 * c]);
+                    ag[4 * c + 1] = fmaf(w1, relu(v1[c].y), ag[4 * c + 1]);
+                    ag[4 * c + 2] = fmaf(w1, relu(v1[c].z), ag[4 * c + 2]);
+                    ag[4 * c + 3] = fmaf(w1, relu(v1[c].w), ag[4 * c + 3]);
+                }
             }
-            for (; k < kend; ++k) {
-                const int2 e = adj[k];
-                const float4 v = relu4(reinterpret_cast<const float4*>(pre1 + (size_t)e.x * HID)[tl]);
-                const float ww = __int_as_float(e.y);
-                a0 = fmaf(ww, v.x, a0); a1 = fmaf(ww, v.y, a1); a2 = fmaf(ww, v.z, a2); a3 = fmaf(ww, v.w, a3);
+            if (k < kend) {
+                const int2 e0 = adj[k];
+                const float4* p0 = reinterpret_cast<const float4*>(pre1 + (size_t)e0.x * HID + 16 * g);
+                const float w0 = __int_as_float(e0.y);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float4 v = p0[c];
+                    ag[4 * c] = fmaf(w0, relu(v.x), ag[4 * c]);
+                    ag[4 * c + 1] = fmaf(w0, relu(v.y), ag[4 * c + 1]);
+                    ag[4 * c + 2] = fmaf(w0, relu(v.z), ag[4 * c + 2]);
+                    ag[4 * c + 3] = fmaf(w0, relu(v.w), ag[4 * c + 3]);
+                }
             }
             const float id = inv_deg[i];
-            const float4 av = make_float4(a0 * id, a1 * id, a2 * id, a3 * id);
-            sx[wl][team][tl] = h;
-            sx[wl][team][HID / 4 + tl] = av;
-            if (a2out) reinterpret_cast<float4*>(a2out + (size_t)i * HID)[tl] = av;
-        }
-        __builtin_amdgcn_wave_barrier();
-        float acc[L2_NB];
 #pragma unroll
-        for (int q = 0; q < L2_NB; ++q) acc[q] = bias;
-#pragma unroll 2
-        for (int k4 = 0; k4 < 2 * HID / 4; ++k4) {
-            const float w0 = sW[(4 * k4) * HID + lane], w1 = sW[(4 * k4 + 1) * HID + lane];
-            const float w2 = sW[(4 * k4 + 2) * HID + lane], w3 = sW[(4 * k4 + 3) * HID + lane];
+            for (int u = 0; u < 16; ++u) ag[u] *= id;
+            if (a2out) {
+                float4* ap = reinterpret_cast<float4*>(a2out + (size_t)i * HID + 16 * g);
 #pragma unroll
-            for (int q = 0; q < L2_NB; ++q) {
-                const float4 v = sx[wl][q][k4];
-                acc[q] = fmaf(v.x, w0, acc[q]);
-                acc[q] = fmaf(v.y, w1, acc[q]);
-                acc[q] = fmaf(v.z, w2, acc[q]);
-                acc[q] = fmaf(v.w, w3, acc[q]);
+                for (int c = 0; c < 4; ++c) ap[c] = make_float4(ag[4 * c], ag[4 * c + 1], ag[4 * c + 2], ag[4 * c + 3]);
             }
         }
-        __builtin_amdgcn_wave_barrier();
-        for (int q = 0; q < cnt; ++q) {
-            const int iq = i0 + q;
-            const float zz = wave_sum(fmaxf(acc[q], 0.0f) * cl);
-            if (pre2out) pre2out[(size_t)iq * HID + lane] = acc[q];
-            if (lane == 0) z[iq] = zz + dd;
+        // dense part, the whole wave
+        v4f acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = v4f{bias[t], bias[t], bias[t], bias[t]};
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            // one step's weight loads at a time (hoisting all 128 of them
+            // would cost the occupancy)
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(hs[s], sW[(16 * g + s) * W2_LD + 16 * t + li], acc[t],
+                                                              0, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    ag[s], sW[(HID + 16 * g + s) * W2_LD + 16 * t + li], acc[t], 0, 0, 0);
+        }
+        // z = relu(pre2) . c + d: per lane over its 4 tiles, then over the 16
+        // lanes of its row group (fixed butterfly)
+        float zp[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            zp[v] = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) zp[v] = fmaf(relu(acc[t][v]), cl[t], zp[v]);
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) zp[v] += __shfl_xor(zp[v], off, 64);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int node = i0 + 4 * g + v;
+            if (node < n) {
+                if (li == 0) z[node] = zp[v] + dd;
+                if (pre2out) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) pre2out[(size_t)node * HID + 16 * t + li] = acc[t][v];
+                }
+            }
         }
     }
 }
