@@ -93,25 +93,27 @@ __device__ __forceinline__ float lane_val(float x, int k)
 // features of node i from the replica's fields state[i * stride]
 __global__ void feat_kernel(int32_t n, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
                             const float* __restrict__ state, int64_t stride, uint32_t k0, uint32_t k1, uint32_t draw,
-                            float* __restrict__ X, float* __restrict__ inv_deg)
+                            float* __restrict__ X, float* __restrict__ inv_deg, int with_graph)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int64_t b = row_off[i], e = row_off[i + 1];
-        float ws = 0.0f;
-        for (int64_t k = b; k < e; ++k) ws += __int_as_float(adj[k].y);
-        const float deg = (float)(e - b);
+        float* x = X + (size_t)i * D_IN;
+        if (with_graph) {   // inputs 0..2 and 1 / deg depend on the graph only
+            const int64_t b = row_off[i], e = row_off[i + 1];
+            float ws = 0.0f;
+            for (int64_t k = b; k < e; ++k) ws += __int_as_float(adj[k].y);
+            const float deg = (float)(e - b);
+            x[0] = 1.0f;
+            x[1] = log1pf(deg);
+            x[2] = e > b ? ws / deg : 0.0f;
+            inv_deg[i] = 1.0f / fmaxf(deg, 1.0f);
+        }
         const float sv = state[(size_t)i * stride];
         const U4 r0 = philox((uint32_t)i, draw, 0u, 0u, k0, k1);
-        float* x = X + (size_t)i * D_IN;
-        x[0] = 1.0f;
-        x[1] = log1pf(deg);
-        x[2] = e > b ? ws / deg : 0.0f;
         x[3] = tanhf(0.5f * sv);
         x[4] = fminf(fmaxf(0.25f * sv, -2.0f), 2.0f);
         x[5] = upm1(r0.x);
         x[6] = upm1(r0.y);
         x[7] = upm1(r0.z);
-        inv_deg[i] = 1.0f / fmaxf(deg, 1.0f);
     }
 }
 
@@ -643,15 +645,17 @@ static int grid_rows(int32_t n, int waves_per_block)
 }
 
 // forward for one replica state (device, state[i * stride]) and draw: z (and,
-// with train, the activations kept for backward)
+// with train, the activations kept for backward).  graph_ready: the graph-only
+// inputs of this problem are already in the work buffers (a previous forward
+// of the same call).
 static fem_status forward(fem_mpnn* m, const Problem& p, const float* state, int64_t stride, uint64_t seed,
-                          int32_t draw, bool train, hipStream_t st)
+                          int32_t draw, bool train, hipStream_t st, bool graph_ready = false)
 {
     const int32_t n = p.n;
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     (void)hipGetLastError();
     feat_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, p.row_off, p.adj, state, stride, k0, k1, (uint32_t)draw, m->X,
-                                                 m->inv_deg);
+                                                 m->inv_deg, graph_ready ? 0 : 1);
     layer1_kernel<<<grid_rows((n + L1_NB - 1) / L1_NB, 4), 256, 0, st>>>(n, p.row_off, p.adj, m->X, m->inv_deg, m->wbf,
                                                                          m->A1agg, m->pre1);
     layer2_kernel<<<grid_rows((n + L2_NB - 1) / L2_NB, 4), 256, 0, st>>>(
@@ -820,7 +824,7 @@ fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, const f
         dst = tmp + (size_t)p.n * R;
     }
     for (int32_t r = 0; r < R && s == FEM_OK; ++r) {
-        s = forward(m, p, src + r, R, seed, r, false, nullptr);
+        s = forward(m, p, src + r, R, seed, r, false, nullptr, r > 0);
         if (s != FEM_OK) break;
         const int blocks = (int)std::min<int64_t>(((int64_t)p.n + 255) / 256, 65536);
         write_col_kernel<<<blocks > 0 ? blocks : 1, 256>>>(p.n, R, r, alpha, m->z, dst);
