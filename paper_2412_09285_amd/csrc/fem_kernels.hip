@@ -73,6 +73,20 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
             for (int v = 0; v < V; ++v) acc[v] = (CT)0;
             int64_t k = a.row_off[i];
             const int64_t kend = a.row_off[i + 1];
+            if constexpr (V == 1) {
+                // one value per lane (few replicas, dense rows): rounds of
+                // eight neighbours in flight shorten the row's latency chain
+                for (; k + 8 <= kend; k += 8) {
+                    int2 e[8];
+                    float x[8][1];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) e[u] = a.adj[k + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) ld_marg<MT, 1>(mc + (size_t)e[u].x * R + rb, x[u]);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[0] = fma((CT)__int_as_float(e[u].y), (CT)x[u][0], acc[0]);
+                }
+            }
             for (; k + 4 <= kend; k += 4) {
                 const int2 e0 = a.adj[k], e1 = a.adj[k + 1], e2 = a.adj[k + 2], e3 = a.adj[k + 3];
                 float x0[V], x1[V], x2[V], x3[V];
