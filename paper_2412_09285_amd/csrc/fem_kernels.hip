@@ -75,7 +75,18 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
             const int64_t kend = a.row_off[i + 1];
             if constexpr (V == 1) {
                 // one value per lane (few replicas, dense rows): rounds of
-                // eight neighbours in flight shorten the row's latency chain
+                // sixteen, then eight neighbours in flight shorten the row's
+                // latency chain
+                for (; k + 16 <= kend; k += 16) {
+                    int2 e[16];
+                    float x[16][1];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) e[u] = a.adj[k + u];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) ld_marg<MT, 1>(mc + (size_t)e[u].x * R + rb, x[u]);
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) acc[0] = fma((CT)__int_as_float(e[u].y), (CT)x[u][0], acc[0]);
+                }
                 for (; k + 8 <= kend; k += 8) {
                     int2 e[8];
                     float x[8][1];
