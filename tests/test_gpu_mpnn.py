@@ -101,6 +101,23 @@ def test_infer_on_device_tensors():
     assert np.array_equal(out.cpu().numpy(), host)
 
 
+def test_forward_of_an_instance_does_not_depend_on_its_batch():
+    """Each node's output is formed from its own inputs in a fixed order
+    (layer 2's matrix-core steps included), so the first instance of a batch
+    gets bit-identical outputs alone and in the batch (its node indices, and
+    so its random features, are the same).  Sizes make the 16-node groups of
+    layer 2 straddle the instance boundary."""
+    graphs, off, _, batch = small_batch((301, 517, 250))
+    g = graphs[0]
+    alone = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
+    net = fem.MPNN(W.mpnn_init_weights(21))
+    st = state_of(batch.n, 8)
+    for draw in (0, 5):
+        zb = net.forward(batch, st, seed=77, draw=draw)
+        za = net.forward(alone, st[: g.n].copy(), seed=77, draw=draw)
+        assert np.array_equal(zb[: g.n], za)
+
+
 def test_training_lowers_the_loss():
     _, off, ops, batch = small_batch((600, 800, 1000, 700))
     st = state_of(batch.n, 5)
