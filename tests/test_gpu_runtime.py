@@ -97,7 +97,7 @@ def test_determinism():
     assert np.array_equal(sa.energies()[2], sb.energies()[2])
 
 
-@pytest.mark.parametrize("kind", ["maxcut", "maxsat", "bmincut"])
+@pytest.mark.parametrize("kind", ["maxcut", "maxcut_dense_rows", "maxsat", "bmincut"])
 def test_every_tile_shape_gives_identical_fields(kind):
     R = 64
     if kind == "maxcut":
@@ -105,6 +105,14 @@ def test_every_tile_shape_gives_identical_fields(kind):
         h0 = W.initial_fields(g.n, R, seed=9)
         shapes = [(1, 4, 4), (2, 1, 1, 1), (4, 8, 2), (4, 8, 2, 1), (8, 2, 16), (8, 4, 4, 1), (4, 16, 1),
                   (4, 4, 4, 1, 2), (1, 8, 2, 0, 8)]
+        kw = {}
+    elif kind == "maxcut_dense_rows":
+        # mean degree 40: one value per lane takes rows in rounds of sixteen
+        # and eight, more values per lane in rounds of four; same sums
+        g = W.random_sparse_graph(600, 12000, seed=19, weights="pm1")
+        prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
+        h0 = W.initial_fields(g.n, R, seed=19)
+        shapes = [(1, 4, 4), (4, 4, 4), (1, 2, 1, 0, 8), (2, 8, 2, 1), (8, 1, 3)]
         kw = {}
     elif kind == "maxsat":
         cnf = W.random_ksat(1500, 12000, 3, seed=9)
