@@ -343,6 +343,38 @@ __global__ void write_col_kernel(int32_t n, int32_t R, int32_t r, float alpha, c
         out[(size_t)i * R + r] = alpha * z[i];
 }
 
+// dst[c][r] = src[r][c] for a rows x cols float matrix, 32 x 32 tiles through
+// LDS (both sides coalesced); workgroup b takes tile (b mod row tiles, b div
+// row tiles) of a one-dimensional grid
+__global__ void __launch_bounds__(256) transpose_kernel(const float* __restrict__ src, int64_t rows, int32_t cols,
+                                                        float* __restrict__ dst)
+{
+    __shared__ float t[32][33];
+    const int64_t tiles_r = (rows + 31) / 32;
+    const int64_t r0 = ((int64_t)blockIdx.x % tiles_r) * 32;
+    const int c0 = (int)((int64_t)blockIdx.x / tiles_r) * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = r0 + k;
+        const int c = c0 + tx;
+        if (r < rows && c < cols) t[k][tx] = src[r * cols + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int c = c0 + k;
+        const int64_t r = r0 + tx;
+        if (r < rows && c < cols) dst[(int64_t)c * rows + r] = t[tx][k];
+    }
+}
+
+static hipError_t transpose(const float* src, int64_t rows, int32_t cols, float* dst)
+{
+    const int64_t tiles = ((rows + 31) / 32) * (((int64_t)cols + 31) / 32);
+    if (tiles < 1) return hipSuccess;
+    transpose_kernel<<<(unsigned)tiles, 256>>>(src, rows, cols, dst);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ training ----
 __device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
 
@@ -591,6 +623,8 @@ struct fem_mpnn {
     float* state = nullptr;   // one replica's fields (training input)
     int32_t *y = nullptr, *inst_of = nullptr, *inst_off = nullptr;
     double* L = nullptr;
+    float* tbuf = nullptr;   // inference: replica-major copies of the fields and the proposal
+    size_t tcap = 0;         // floats tbuf holds
 };
 
 template <typename T>
@@ -700,6 +734,7 @@ void fem_mpnn_destroy(fem_mpnn* m)
     if (!m) return;
     (void)hipSetDevice(m->device);
     free_work(m);
+    mfree(m->tbuf);
     mfree(m->theta); mfree(m->wbf); mfree(m->m1); mfree(m->m2); mfree(m->grad); mfree(m->part);
     delete m;
 }
@@ -823,13 +858,45 @@ fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, const f
         src = tmp;
         dst = tmp + (size_t)p.n * R;
     }
+    // replica-major copies: each forward reads its replica's fields, and
+    // writes its proposal, contiguously; one transposition each way
+    const size_t nR = (size_t)p.n * R;
+    float* tin = nullptr;
+    float* tout = nullptr;
+    if (R > 1) {
+        if (m->tcap < 2 * nR) {
+            mfree(m->tbuf);
+            m->tcap = 0;
+            hipError_t ea = hipMalloc(&m->tbuf, 2 * nR * 4);
+            if (ea != hipSuccess) {
+                m->tbuf = nullptr;
+                if (tmp) (void)hipFree(tmp);
+                return mfail(FEM_E_NOMEM, "device allocation of the replica-major copies", ea);
+            }
+            m->tcap = 2 * nR;
+        }
+        tin = m->tbuf;
+        tout = m->tbuf + nR;
+        hipError_t et = transpose(src, p.n, R, tin);
+        if (et != hipSuccess) s = mfail(FEM_E_HIP, "transpose_kernel", et);
+    }
+    const int blocks = (int)std::min<int64_t>(((int64_t)p.n + 255) / 256, 65536);
     for (int32_t r = 0; r < R && s == FEM_OK; ++r) {
-        s = forward(m, p, src + r, R, seed, r, false, nullptr, r > 0);
-        if (s != FEM_OK) break;
-        const int blocks = (int)std::min<int64_t>(((int64_t)p.n + 255) / 256, 65536);
-        write_col_kernel<<<blocks > 0 ? blocks : 1, 256>>>(p.n, R, r, alpha, m->z, dst);
+        if (R > 1) {
+            s = forward(m, p, tin + (size_t)r * p.n, 1, seed, r, false, nullptr, r > 0);
+            if (s != FEM_OK) break;
+            write_col_kernel<<<blocks > 0 ? blocks : 1, 256>>>(p.n, 1, 0, alpha, m->z, tout + (size_t)r * p.n);
+        } else {
+            s = forward(m, p, src, 1, seed, r, false, nullptr, false);
+            if (s != FEM_OK) break;
+            write_col_kernel<<<blocks > 0 ? blocks : 1, 256>>>(p.n, 1, 0, alpha, m->z, dst);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) s = mfail(FEM_E_HIP, "write_col_kernel", e);
+    }
+    if (s == FEM_OK && R > 1) {
+        hipError_t et = transpose(tout, R, p.n, dst);
+        if (et != hipSuccess) s = mfail(FEM_E_HIP, "transpose_kernel", et);
     }
     hipError_t e = hipDeviceSynchronize();
     if (s == FEM_OK && e != hipSuccess) s = mfail(FEM_E_HIP, "fem_mpnn_infer", e);
