@@ -1,33 +1,37 @@
 #!/usr/bin/env python3
-"""Throughput benchmark of the FEM hot path on one MI355X.
+"""Benchmark of the FEM hot path on one MI355X.
 
-Workload (default): MaxCut on a random sparse graph, N = 100,000 nodes,
-300,000 edges with uniform endpoints and +/-1 weights, R = 256 replicas,
-a 2,000-step anneal (linear beta 0.01 -> 5, Adam lr 0.1), float32 fields and
-Adam state, float32 (or --dtype bf16) marginal copy.  One "step" is one pass
-of the whole hot path: sparse field product, gradient, Adam, new marginals,
-and per-replica energies U, S, F; the read-out runs at the end of the anneal.
+Default workload (batch512): 512 MaxCut instances of uneven size (N
+log-uniform in [1000, 50000], even b random 3-regular, odd b G(n, 5n), +/-1
+weights), R = 32 replicas each, linear beta 0.01 -> 5, Adam lr 0.1.  One
+"step" is one pass of the whole hot path over the block-diagonal union of all
+512 instances in one launch: sparse field product, gradient, Adam, new
+bfloat16 marginal copy (float32 fields, accumulation and Adam state),
+per-replica energies U, S, F, and the anytime read-out with integer
+evaluation every 25 steps.
 
-Metric: replica-edge updates per second = nnz * R * steps / seconds, with
-nnz = 2 x edges, timed over one captured HIP graph of all K steps with the
-inputs resident in HBM.  Prints one JSON line.
+Metric: replica-edge updates per second = nnz * R * K / seconds over K
+steps in one captured HIP graph, inputs resident in HBM (nnz = 2 x edges,
+summed over instances).  The same line carries the time to a best cut within
+0.1% of plain FEM (per-instance float32 solvers) for batched float32,
+batched bfloat16 and batched bfloat16 with the learned warm start, and the
+FP64 C oracle timed on the host as a baseline.  Prints one JSON line.
 
---gradient manipulated runs the same workload with the paper's manipulated
-gradients (one-hot neighbour read-outs, 1/sum|W| normalisation): the gather
-then reads sign bits, and no energies are formed.
+Other workloads (--workload): maxcut1e5 (N = 10^5, 3*10^5 +/-1 edges,
+R = 256; --dtype, --gradient manipulated), bmincut1e6 (3-D RGG, N = 10^6,
+q = 8, R = 16), max3sat1e5 (N = 10^5, M = 8*10^5, R = 64), er800 (G(800,
+19176), R = 16), k2000dense (complete graph K_2000, the dense matrix-core
+path, R = 1000), copy (a plain device copy that calibrates the HBM counters).
 
---workload k2000dense is the dense-W path: MaxCut on a complete graph of
-2,000 nodes with +/-1 weights (the shape of the paper's K2000 benchmark),
-R = 1,000, RMSprop with the paper's K2000 settings.  With integral weights the
-field product is formed exactly from int8 digit planes of the fixed-point
-marginals on the int8 matrix cores (four int8 products per step), so its
-roofline is the int8 MFMA peak; other weights run on the FP64 matrix cores.
-
-roofline.traffic is the HBM traffic of one step-kernel launch measured with
-the FETCH_SIZE and WRITE_SIZE counters (scaled by a plain copy of known
-size), read from the committed counter summary of this workload; it is null
-when the kernel sources, launch shape or marginal type differ from the ones
-the counters were taken with.
+roofline.achieved is the algorithmic bytes of one step-kernel launch (each
+array touched once: h, m1, m2 read and written, the marginal copy read once
+and written once, the graph as 4-byte row offsets and 4-byte entries) over
+the kernel's average duration from HIP events on the solver's stream.
+roofline.traffic is the HBM traffic of one launch measured with the
+FETCH_SIZE and WRITE_SIZE counters (scaled by a plain copy of known size),
+read from the committed counter summary of the workload; it is null when the
+kernel sources, launch shape or marginal type differ from the ones the
+counters were taken with.
 """
 import argparse
 import hashlib
@@ -50,23 +54,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def step_kernel_bytes(n, R, nnz, mbytes, n_tiles, NE=2):
-    """Algorithmic bytes of one step-kernel launch (MaxCut): h, m1, m2 read and
-    written (24 B per replica-node), the marginal copy read once and written
-    once, the CSR (int64 row offsets, 8-byte {col, weight} entries) and the
-    per-tile energy partials."""
-    state = n * R * (24 + 2 * mbytes)
-    csr = 8 * (n + 1) + 8 * nnz
-    parts = 8 * NE * R * n_tiles
-    return state + csr + parts
+def step_kernel_bytes(n, R, nnz, mbytes):
+    """Algorithmic bytes of one MaxCut step launch: h, m1, m2 read and written
+    (24 B per replica-node), the marginal copy read once and written once
+    (2 b per replica-node), the graph as 4-byte row offsets and 4-byte entries
+    (a column with the sign of a +/-1 weight)."""
+    return n * R * (24 + 2 * mbytes) + 4 * (n + 1) + 4 * nnz
 
 
 def manip_kernel_bytes(n, R, nnz):
     """Algorithmic bytes of one manipulated-gradient MaxCut launch: h, m1, m2
     read and written, the sign bits (ceil(R/32) words per row) read once and
-    written once, the CSR and the per-node normaliser (8 B)."""
+    written once, the graph (4-byte offsets and entries) and the per-node
+    normaliser (4 B)."""
     rw = (R + 31) // 32
-    return n * R * 24 + 2 * 4 * n * rw + 8 * (n + 1) + 8 * nnz + 8 * n
+    return n * R * 24 + 2 * 4 * n * rw + 4 * (n + 1) + 4 * nnz + 4 * n
 
 
 KERNEL_SOURCES = {
@@ -100,22 +102,112 @@ def measured_traffic(path, gradient, tile, marginals, layout="interleaved"):
     return int(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(graph, R_sample, steps_sample):
+def _oracle_setup(kind, key, R):
     import oracle as O
     from paper_2412_09285_amd import workloads as W
 
-    h0 = W.initial_fields(graph.n, R_sample, seed=102)
-    run = O.maxcut_run(graph, O.Params(R=R_sample, T=2000), h0)
+    if kind == "batch":
+        g = W.batch_instance(key)
+        h0 = W.initial_fields(g.n, R, seed=1_000_000 + g.meta["seed"])
+        T = 1000
+    else:
+        g = W.config_graph(key)
+        h0 = W.initial_fields(g.n, R, seed=100 + key)
+        T = 2000
+    return g.nnz * R, O.maxcut_run(g, O.Params(R=R, T=T), h0)
+
+
+def _oracle_maxcut_task(task):
+    """One oracle run (FP64 C, one thread): `steps` steps of an instance;
+    (updates, seconds of the run alone)."""
+    kind, key, R, steps = task
+    upd, run = _oracle_setup(kind, key, R)
     t0 = time.perf_counter()
-    run.step(steps_sample)
-    dt = time.perf_counter() - t0
+    run.step(steps)
+    return upd * steps, time.perf_counter() - t0
+
+
+def _oracle_worker(tasks, barrier, results):
+    """Builds its oracle runs, waits at the barrier, runs them all, reports."""
+    runs = [(_oracle_setup(kind, key, R), steps) for (kind, key, R, steps) in tasks]
+    barrier.wait()
+    upd = 0
+    for (u, run), steps in runs:
+        run.step(steps)
+        upd += u * steps
+    results.put(upd)
+
+
+def host_threads():
+    """Threads the CPU baseline uses: the cores this process may run on,
+    at most 16 (one GPU's share of a shared host)."""
+    return min(len(os.sched_getaffinity(0)), 16)
+
+
+def oracle_parallel(tasks, threads):
+    """Runs the tasks on `threads` processes (task k on process k mod
+    threads); every process builds its inputs first, then all start
+    together.  Returns (updates, wall seconds of the runs)."""
+    import multiprocessing as mp
+
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(threads + 1)
+    results = ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker, args=(tasks[k::threads], barrier, results)) for k in range(threads)]
+    for p in procs:
+        p.start()
+    barrier.wait()
+    t0 = time.perf_counter()
+    upd = sum(results.get() for _ in procs)
+    wall = time.perf_counter() - t0
+    for p in procs:
+        p.join()
+    return upd, wall
+
+
+def cpu_baseline_batch(n_inst, R, steps, one_thread_instances):
+    """The oracle on the batch: every instance for `steps` steps with one
+    process per host thread (all cores), then a sample of instances in one
+    thread.  Rate = summed nnz * R * steps / wall time of the runs."""
+    import numpy as np
+
+    threads = host_threads()
+    upd, wall = oracle_parallel([("batch", b, R, steps) for b in range(n_inst)], threads)
+    sample = [int(b) for b in np.random.default_rng(7).permutation(n_inst)[:one_thread_instances]]
+    one = [_oracle_maxcut_task(("batch", b, R, steps)) for b in sample]
+    upd1, t1 = sum(r[0] for r in one), sum(r[1] for r in one)
     return {
-        "value": graph.nnz * R_sample * steps_sample / dt,
+        "value": upd / wall,
         "unit": "replica-edge updates/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"same graph (N={graph.n}, nnz={graph.nnz}), {R_sample} of the replicas, first "
-                  f"{steps_sample} steps, FP64 single-threaded C oracle, {dt:.1f} s",
+        "nproc": os.cpu_count(),
+        "affinity_cores": len(os.sched_getaffinity(0)),
+        "sample": f"all {n_inst} instances, R = {R}, the first {steps} steps of each, FP64 C oracle, one process "
+                  f"per thread on {threads} threads (instances dealt round-robin): {wall:.1f} s wall",
+        "one_thread": {"value": upd1 / t1, "cores": 1,
+                       "sample": f"{one_thread_instances} instances (seeded sample), the first {steps} steps, "
+                                 f"one thread: {t1:.1f} s"},
+    }
+
+
+def cpu_baseline_graph(cfg, R_sample, steps_sample):
+    """The oracle on one graph workload: one process per host thread, each
+    running R_sample replicas of it, and one thread alone."""
+    threads = host_threads()
+    upd1, t1 = _oracle_maxcut_task(("config", cfg, R_sample, steps_sample))
+    upd, wall = oracle_parallel([("config", cfg, R_sample, steps_sample)] * threads, threads)
+    return {
+        "value": upd / wall,
+        "unit": "replica-edge updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "nproc": os.cpu_count(),
+        "affinity_cores": len(os.sched_getaffinity(0)),
+        "sample": f"same graph, {threads} processes of {R_sample} replicas each, the first {steps_sample} steps, "
+                  f"FP64 C oracle: {wall:.1f} s wall",
+        "one_thread": {"value": upd1 / t1, "cores": 1,
+                       "sample": f"{R_sample} replicas, the first {steps_sample} steps, one thread: {t1:.1f} s"},
     }
 
 
@@ -132,21 +224,25 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--retune", action="store_true", help="time every launch shape even if one is cached")
-    ap.add_argument("--cpu-replicas", type=int, default=8)
-    ap.add_argument("--cpu-steps", type=int, default=400,
-                    help="oracle steps of the CPU baseline sample (8 replicas by default): 10-20 s of CPU work")
-    ap.add_argument("--workload", choices=["maxcut1e5", "bmincut1e6", "max3sat1e5", "k2000dense", "er800", "batch512",
+    ap.add_argument("--cpu-replicas", type=int, default=8,
+                    help="single-graph workloads: replicas per oracle process in the CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps of the CPU baseline (default: 10 for batch512, 100 for maxcut1e5)")
+    ap.add_argument("--cpu-one-thread", type=int, default=32,
+                    help="batch512: instances in the one-thread CPU baseline sample")
+    ap.add_argument("--workload", choices=["batch512", "maxcut1e5", "bmincut1e6", "max3sat1e5", "k2000dense", "er800",
                                            "copy"],
-                    default="maxcut1e5",
-                    help="maxcut1e5: the throughput line; bmincut1e6 / max3sat1e5: the Potts and Max-3-SAT "
+                    default="batch512",
+                    help="batch512 (default): 512 uneven MaxCut instances, R = 32, in one launch per step, with time "
+                         "to target; maxcut1e5: N = 10^5, R = 256; bmincut1e6 / max3sat1e5: the Potts and Max-3-SAT "
                          "kernels at full size; er800: a G-set-sized instance (800 nodes, R = 16), launch-bound; "
-                         "k2000dense: the dense-W (matrix-core) path on a complete "
-                         "2000-node graph; batch512: time to target on 512 uneven MaxCut instances; "
+                         "k2000dense: the dense-W (matrix-core) path on a complete 2000-node graph; "
                          "copy: a plain device copy (calibrates HBM counters)")
     ap.add_argument("--order", choices=["draw", "rcm"], default="rcm",
                     help="bmincut1e6: node order of the graph (rcm: relabelled by fem_graph_order before the "
                          "problem is built; draw: as generated)")
     ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--no-ttt", action="store_true", help="batch512: skip the time-to-target runs")
     ap.add_argument("--plain-steps", type=int, default=1000)
     ap.add_argument("--early-steps", type=int, default=100, help="batch512: plain steps before the proposal")
     ap.add_argument("--warm-steps", type=int, default=300, help="batch512: length of the continued anneal")
@@ -188,18 +284,70 @@ def main():
                           "copies": 6, "ms_per_copy": ms, "read_plus_write_GBps": 8 * n / (ms * 1e-3) / 1e9}))
         return
     if args.workload == "batch512":
-        from paper_2412_09285_amd import batchbench
-
-        res = batchbench.main_batch(args, torch.cuda.Stream())
-        plain = res["plain_per_instance_s"]
-        best = res.get("batched_bf16_warm", {}).get("time_to_target_s") or \
-            res["batched_bf16"]["time_to_target_s"]
-        print(json.dumps({"metric": "time to best cut within 0.1% of plain FEM", "value": best, "unit": "s",
-                          "higher_is_better": False, "n_gpus": 1, "vs_baseline": None,
-                          "dtype": "f32 fields/Adam + bf16 marginals", "data": "synthetic",
-                          "config": dict(workload="batch512_maxcut", **res["config"]), "result": res}))
+        batch_headline(args)
         return
     throughput(args)
+
+
+def batch_headline(args):
+    """The default line: throughput of the batched step over the 512-instance
+    union, its roofline, the CPU oracle baseline, and the time to target."""
+    import torch
+
+    from paper_2412_09285_amd import batchbench as BB
+    from paper_2412_09285_amd import fem
+
+    K = args.steps if args.steps else 200
+    Wm = args.warmup
+    R = BB.R_BATCH
+    t0 = time.perf_counter()
+    graphs = BB.instances(args.instances)
+    b = BB.Batch(graphs, R)
+    log(f"{len(graphs)} instances, {b.n} nodes, nnz {b.nnz}, R = {R} ({time.perf_counter() - t0:.1f} s to build)")
+    stream = torch.cuda.Stream()
+    thr = BB.throughput(b, K, Wm, stream, dtype=fem.BF16, eval_every=args.eval_every, tune=not args.no_tune)
+    log(f"timed {K} steps in {thr['seconds'] * 1e3:.1f} ms: {thr['updates_per_s']:.3e} updates/s; step kernel "
+        f"{thr['kernel_ms'] * 1e3:.1f} us (launch shape {thr['tile']})")
+    alg = step_kernel_bytes(b.n, R, b.nnz, 2)
+    achieved = alg / (thr["kernel_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(os.path.join(ROOT, "profiles", "maxcut_batch512_R32_bf16_hbm_counters.md"),
+                               "explicit", thr["tile"], "bf16")
+    out = {
+        "metric": "replica-edge updates/s (nnz*R*steps/s) + time to best cut within 0.1% of plain",
+        "value": thr["updates_per_s"],
+        "unit": "replica-edge updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": thr["seconds"] * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16-marginals",
+        "data": "synthetic (seeded generator: 512 MaxCut instances, N log-uniform in [1000, 50000], random "
+                "3-regular and G(n, 5n), +/-1 weights)",
+        "config": {"workload": "maxcut_batch512_uneven_R32", "instances": len(graphs), "n": b.n, "nnz": b.nnz,
+                   "replicas": R, "marginals": "bf16", "energies": "every step", "eval_every": min(args.eval_every, K),
+                   "schedule": "linear beta 0.01->5, Adam lr 0.1", "tile": list(thr["tile"]),
+                   "parallelism": "single GPU, one launch per step over the block-diagonal union"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "maxcut_step_kernel", "kernel_avg_ms": round(thr["kernel_ms"], 5),
+                     "kernel_launches": thr["kernel_launches"], "alg_bytes_per_launch": int(alg),
+                     "alg_bytes_model": "28 B per replica-node (h, m1, m2 read and written, bf16 copy read and "
+                                        "written) + 4 B per row offset + 4 B per adjacency entry",
+                     "kernel_sources_sha256": kernel_sources_sha("explicit")},
+        "result": {"U_mean": thr["U_mean"], "anytime_best_cut_sum": thr["best_sum"]},
+    }
+    if not args.no_ttt:
+        log("time to target ...")
+        out["time_to_target"] = BB.time_to_target(b, stream, plain_steps=args.plain_steps, K=args.eval_every,
+                                                  early_steps=args.early_steps, warm_steps=args.warm_steps,
+                                                  beta_start=args.beta_start, alpha=args.alpha, params=args.params)
+    if not args.no_cpu:
+        log("timing the CPU oracle ...")
+        out["cpu_baseline"] = cpu_baseline_batch(args.instances, R, args.cpu_steps or 10, args.cpu_one_thread)
+    print(json.dumps(out), flush=True)
 
 
 # The single-GPU throughput workloads: the default line (MaxCut, N = 10^5,
@@ -231,25 +379,22 @@ K2000_PARAMS = dict(optimizer=1, rms_alpha=0.56, momentum=0.63, weight_decay=0.0
 def dense_kernel_bytes(n, R, w_bytes):
     """Algorithmic bytes of one dense step launch: W once (w_bytes per entry:
     4 float, 1 int8), the marginal copy read and written (4 B per value as
-    float or as four int8 digits), h, m1, m2 read and written, the energy
-    partials."""
-    return w_bytes * n * n + n * R * (24 + 8) + 16 * R * (-(-n // 64))
+    float or as four int8 digits), h, m1, m2 read and written."""
+    return w_bytes * n * n + n * R * (24 + 8)
 
 
-def potts_kernel_bytes(n, R, q, nnz, mbytes, n_tiles):
+def potts_kernel_bytes(n, R, q, nnz, mbytes):
     """Algorithmic bytes of one bMinCut launch: h, m1, m2 read and written and
     the marginal copy read once and written once (24 + 2 b per replica-node-
-    state), the CSR, the weighted degree (4 B per node), and per tile the
-    centred column sums read, the column-sum partials and the three energy
-    partials written (8 B each per replica and state / replica)."""
-    return n * R * q * (24 + 2 * mbytes) + 8 * (n + 1) + 8 * nnz + 4 * n + 8 * R * (2 * q + 3) * n_tiles
+    state) and the graph (4-byte row offsets and entries; unit weights)."""
+    return n * R * q * (24 + 2 * mbytes) + 4 * (n + 1) + 4 * nnz
 
 
-def sat_kernel_bytes(n, R, nnz, mbytes, n_tiles, rec_bytes=8):
+def sat_kernel_bytes(n, R, nnz, mbytes, rec_bytes=8):
     """Algorithmic bytes of one Max-k-SAT launch: h, m1, m2 and the marginal
-    copy as for MaxCut, the incidence records (8 B each for 3-SAT), the row
-    offsets and the per-tile energy partials."""
-    return n * R * (24 + 2 * mbytes) + 8 * (n + 1) + rec_bytes * nnz + 16 * R * n_tiles
+    copy as for MaxCut, one record per literal incidence (the other two
+    literals of a 3-SAT clause, 4 B each) and 4-byte row offsets."""
+    return n * R * (24 + 2 * mbytes) + 4 * (n + 1) + rec_bytes * nnz
 
 
 def throughput(args):
@@ -340,10 +485,6 @@ def throughput(args):
     s.step(min(K, 200))
     kern_ms, n_k = s.profile_result()
     s.profile(False)
-    vec, waves, rows, nt, lanes = tile
-    per_lane = vec if kind != "bmincut" else 1
-    lanes = min(lanes, 64)
-    n_tiles = -(-n // (waves * (64 // lanes) * rows))
     mbytes = 2 if dtype == fem.BF16 else 4
     if manip:
         alg_bytes = manip_kernel_bytes(n, R, nnz)
@@ -353,14 +494,14 @@ def throughput(args):
         kname = "maxcut_dense_i8_step_kernel" if dense_i8 else "maxcut_dense_step_kernel"
         counters = f"{wl['counters']}_{'i8' if dense_i8 else 'f64'}_hbm_counters.md"
     elif kind == "maxcut":
-        alg_bytes = step_kernel_bytes(n, R, nnz, mbytes, n_tiles)
+        alg_bytes = step_kernel_bytes(n, R, nnz, mbytes)
         kname, counters = "maxcut_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
     elif kind == "bmincut":
-        alg_bytes = potts_kernel_bytes(n, R, q, nnz, mbytes, n_tiles)
+        alg_bytes = potts_kernel_bytes(n, R, q, nnz, mbytes)
         rcm = "_rcm" if args.order == "rcm" else ""
         kname, counters = "potts_step_kernel", f"{wl['counters']}{rcm}_{args.dtype}_hbm_counters.md"
     else:
-        alg_bytes = sat_kernel_bytes(n, R, nnz, mbytes, n_tiles)
+        alg_bytes = sat_kernel_bytes(n, R, nnz, mbytes)
         kname, counters = "sat_step_kernel", f"{wl['counters']}_{args.dtype}_hbm_counters.md"
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     if args.state_layout != "interleaved":
@@ -416,9 +557,10 @@ def throughput(args):
                    "U_mean_final": float(np.mean(U)) if U is not None else None},
         "roofline": roof,
     }
-    if kind in ("maxcut", "maxcut_dense") and not args.no_cpu and not manip:
+    if kind == "maxcut" and not args.no_cpu and not manip:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(g, args.cpu_replicas, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline_graph(wl["recipe"], args.cpu_replicas,
+                                                 args.cpu_steps or (100 if n > 10_000 else 500))
     print(json.dumps(out), flush=True)
 
 

@@ -51,7 +51,7 @@ class _Problem(C.Structure):
         ("lr", C.c_double), ("b1", C.c_double), ("b2", C.c_double),
         ("eps", C.c_double), ("wd", C.c_double),
         ("opt", C.c_int32), ("momentum", C.c_double), ("rms_alpha", C.c_double), ("dampening", C.c_double),
-        ("manip", C.c_int32), ("gamma", C.c_double), ("nw", C.c_void_p),
+        ("manip", C.c_int32), ("gamma", C.c_double), ("nw", C.c_void_p), ("mdt", C.c_int32),
     ]
 
 
@@ -67,12 +67,14 @@ def lib():
         L.orc_lambda.restype = C.c_double
         L.orc_lambda.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_int32]
         L.orc_maxcut_grad.restype = C.c_int
-        L.orc_maxcut_grad.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, C.c_double, P, P, P]
+        L.orc_round_bf16.restype = C.c_double
+        L.orc_round_bf16.argtypes = [C.c_double]
+        L.orc_maxcut_grad.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, C.c_double, C.c_int32, P, P, P]
         L.orc_bmincut_grad.restype = C.c_int
         L.orc_bmincut_grad.argtypes = [C.c_int32, C.c_int64, P, P, P, P, C.c_int32, C.c_double,
-                                       C.c_int32, P, C.c_double, P, P, P]
+                                       C.c_int32, P, C.c_double, C.c_int32, P, P, P]
         L.orc_maxsat_grad.restype = C.c_int
-        L.orc_maxsat_grad.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P, C.c_double, P, P, P]
+        L.orc_maxsat_grad.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P, C.c_double, C.c_int32, P, P, P]
         L.orc_maxcut_grad_manip.restype = C.c_int
         L.orc_maxcut_grad_manip.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, C.c_double,
                                             C.c_double, P]
@@ -134,22 +136,29 @@ def lam(ramp: int, lam_max: float, T: int, t: int) -> float:
 # --------------------------------------------------------------------------
 # per-step gradient and energies (one call = one evaluation at fixed h, beta)
 # --------------------------------------------------------------------------
-def maxcut_grad(n, u, v, w, h, beta_, want_grad=True):
-    """h: [n][R] float64.  Returns (g [n][R] or None, U [R], S [R])."""
+def round_bf16(x: float) -> float:
+    """The nearest bfloat16 value of x (ties to even)."""
+    return lib().orc_round_bf16(float(x))
+
+
+def maxcut_grad(n, u, v, w, h, beta_, want_grad=True, mdt=0):
+    """h: [n][R] float64; mdt = 1: neighbours read a bfloat16 copy of m.
+    Returns (g [n][R] or None, U [R], S [R])."""
     h = _f64(h)
     R = h.shape[1]
     u, v, w = _i32(u), _i32(v), _f64(w)
     g = np.zeros_like(h) if want_grad else None
     U = np.zeros(R)
     S = np.zeros(R)
-    rc = lib().orc_maxcut_grad(n, u.shape[0], _p(u), _p(v), _p(w), R, _p(h), beta_, _p(g), _p(U), _p(S))
+    rc = lib().orc_maxcut_grad(n, u.shape[0], _p(u), _p(v), _p(w), R, _p(h), beta_, int(mdt), _p(g), _p(U), _p(S))
     if rc:
         raise MemoryError(rc)
     return g, U, S
 
 
-def bmincut_grad(n, u, v, w, q, lam_, h, beta_, want_grad=True, node_w=None):
-    """h: [n][R][q] float64; node_w: node weights V (None: all 1)."""
+def bmincut_grad(n, u, v, w, q, lam_, h, beta_, want_grad=True, node_w=None, mdt=0):
+    """h: [n][R][q] float64; node_w: node weights V (None: all 1); mdt = 1:
+    neighbours read a bfloat16 copy of P."""
     h = _f64(h)
     R = h.shape[1]
     u, v, w = _i32(u), _i32(v), _f64(w)
@@ -157,21 +166,24 @@ def bmincut_grad(n, u, v, w, q, lam_, h, beta_, want_grad=True, node_w=None):
     g = np.zeros_like(h) if want_grad else None
     U = np.zeros(R)
     S = np.zeros(R)
-    rc = lib().orc_bmincut_grad(n, u.shape[0], _p(u), _p(v), _p(w), _p(V), q, lam_, R, _p(h), beta_,
+    rc = lib().orc_bmincut_grad(n, u.shape[0], _p(u), _p(v), _p(w), _p(V), q, lam_, R, _p(h), beta_, int(mdt),
                                 _p(g), _p(U), _p(S))
     if rc:
         raise MemoryError(rc)
     return g, U, S
 
 
-def maxsat_grad(n, off, lits, h, beta_, want_grad=True):
+def maxsat_grad(n, off, lits, h, beta_, want_grad=True, mdt=0):
+    """mdt = 1: the other literals of a clause are read from a bfloat16 copy
+    of min(P, 1 - P)."""
     h = _f64(h)
     R = h.shape[1]
     off, lits = _i64(off), _i32(lits)
     g = np.zeros_like(h) if want_grad else None
     U = np.zeros(R)
     S = np.zeros(R)
-    rc = lib().orc_maxsat_grad(n, off.shape[0] - 1, _p(off), _p(lits), R, _p(h), beta_, _p(g), _p(U), _p(S))
+    rc = lib().orc_maxsat_grad(n, off.shape[0] - 1, _p(off), _p(lits), R, _p(h), beta_, int(mdt), _p(g), _p(U),
+                               _p(S))
     if rc:
         raise MemoryError(rc)
     return g, U, S
@@ -301,6 +313,7 @@ class Params:
     dampening: float = 0.0
     manip: int = 0          # 1: manipulated gradients (energies are not formed)
     gamma: float = 1.0      # gamma_grad of the manipulated form
+    mdt: int = 0            # 1: neighbours read a bfloat16 copy of the marginals
 
 
 class Run:
@@ -332,6 +345,7 @@ class Run:
         pb.opt, pb.momentum, pb.rms_alpha, pb.dampening = params.opt, params.momentum, params.rms_alpha, \
             params.dampening
         pb.manip, pb.gamma = int(params.manip), params.gamma
+        pb.mdt = int(params.mdt)
         self.node_w = None if node_w is None else _f64(node_w)
         pb.nw = None if self.node_w is None else self.node_w.ctypes.data
         self._pb = pb
@@ -374,12 +388,13 @@ class Run:
             return maxsat_grad_manip(self.n, off, lits, h, b, p.gamma), None, None
         if self.kind == KIND_MAXCUT:
             u, v, w = self._keep
-            return maxcut_grad(self.n, u, v, w, h, b)
+            return maxcut_grad(self.n, u, v, w, h, b, mdt=p.mdt)
         if self.kind == KIND_BMINCUT:
             u, v, w = self._keep
-            return bmincut_grad(self.n, u, v, w, self.q, lam(p.lam_ramp, p.lam, p.T, t), h, b, node_w=self.node_w)
+            return bmincut_grad(self.n, u, v, w, self.q, lam(p.lam_ramp, p.lam, p.T, t), h, b, node_w=self.node_w,
+                                mdt=p.mdt)
         off, lits = self._keep
-        return maxsat_grad(self.n, off, lits, h, b)
+        return maxsat_grad(self.n, off, lits, h, b, mdt=p.mdt)
 
     def adam_from(self, h, m1, m2, g, t):
         """Fields after the optimiser step of step t from (h, m1, m2) with

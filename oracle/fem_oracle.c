@@ -62,6 +62,21 @@ static double sigmoid(double x)
     return e / (1.0 + e);
 }
 
+/* The nearest bfloat16 value (8 significant bits, exponent range of float32,
+ * ties to the even neighbour): the storage type of the marginal copy that
+ * neighbours read when the copy is kept in bfloat16 (mdt = 1 below).  The
+ * spacing of bfloat16 values is 2^(e-8) for |x| in [2^(e-1), 2^e), and
+ * 2^-133 below 2^-126 (subnormals). */
+double orc_round_bf16(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    frexp(x, &e);
+    int q = e - 8;
+    if (q < -133) q = -133;
+    return ldexp(nearbyint(ldexp(x, -q)), q);   /* nearbyint: ties to even */
+}
+
 /* ------------------------------------------------------------------------- */
 /* Annealing schedules (Methods, "Different annealing schedules for the      */
 /* inverse temperature").                                                     */
@@ -101,27 +116,34 @@ double orc_lambda(int32_t ramp, double lam, int32_t T, int32_t t)
  * g may be NULL (energies only); U, S may be NULL.
  */
 int orc_maxcut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
-                    const double* w, int32_t R, const double* h, double beta,
+                    const double* w, int32_t R, const double* h, double beta, int32_t mdt,
                     double* g, double* U, double* S)
 {
     double* P = (double*)malloc(sizeof(double) * (size_t)n);
+    double* Pn = (double*)malloc(sizeof(double) * (size_t)n);     /* P as neighbours read it */
     double* Wsum = (double*)malloc(sizeof(double) * (size_t)n);   /* sum_j W_ij [2P_j(+)-1] */
-    if (!P || !Wsum) { free(P); free(Wsum); return -2; }
+    if (!P || !Pn || !Wsum) { free(P); free(Pn); free(Wsum); return -2; }
     for (int32_t r = 0; r < R; ++r) {
-        for (int32_t i = 0; i < n; ++i) P[i] = sigmoid(h[(size_t)i * R + r]);
+        for (int32_t i = 0; i < n; ++i) {
+            double x = h[(size_t)i * R + r];
+            P[i] = sigmoid(x);
+            /* bfloat16 copy: m = 2P - 1 = tanh(h/2) is what is stored */
+            Pn[i] = mdt ? 0.5 * (1.0 + orc_round_bf16(tanh(0.5 * x))) : P[i];
+        }
         double u_acc = 0.0, s_acc = 0.0;
         for (int32_t i = 0; i < n; ++i) Wsum[i] = 0.0;
         for (int64_t e = 0; e < ne; ++e) {
             int32_t i = eu[e], j = ev[e];
-            double pi = P[i], pj = P[j];
-            /* the two orderings (i,j) and (j,i) of the undirected edge */
-            double same_ij = pi * pj + (1.0 - pi) * (1.0 - pj);
+            /* the two orderings (i,j) and (j,i) of the undirected edge; the
+               first index reads its own marginal, the second the stored one */
+            double same_ij = P[i] * Pn[j] + (1.0 - P[i]) * (1.0 - Pn[j]);
+            double same_ji = P[j] * Pn[i] + (1.0 - P[j]) * (1.0 - Pn[i]);
             u_acc += -w[e] * (1.0 - same_ij);   /* (i,j): sum_s P_i(s)[1-P_j(s)] */
-            u_acc += -w[e] * (1.0 - same_ij);   /* (j,i) */
+            u_acc += -w[e] * (1.0 - same_ji);   /* (j,i) */
             /* sum_j W_ij [2 P_j(+) - 1] minus the same for state (-):
                [2P_j(+)-1] - [2P_j(-)-1] = 2(2P_j(+)-1) */
-            Wsum[i] += w[e] * (2.0 * pj - 1.0);
-            Wsum[j] += w[e] * (2.0 * pi - 1.0);
+            Wsum[i] += w[e] * (2.0 * Pn[j] - 1.0);
+            Wsum[j] += w[e] * (2.0 * Pn[i] - 1.0);
         }
         for (int32_t i = 0; i < n; ++i) {
             double x = h[(size_t)i * R + r];
@@ -141,6 +163,7 @@ int orc_maxcut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
         if (S) S[r] = s_acc;
     }
     free(P);
+    free(Pn);
     free(Wsum);
     return 0;
 }
@@ -164,16 +187,17 @@ int orc_maxcut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
  */
 int orc_bmincut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev,
                      const double* w, const double* V, int32_t q, double lam, int32_t R,
-                     const double* h, double beta, double* g, double* U, double* S)
+                     const double* h, double beta, int32_t mdt, double* g, double* U, double* S)
 {
     size_t nq = (size_t)n * (size_t)q;
     double* P = (double*)malloc(sizeof(double) * nq);
+    double* Pn = (double*)malloc(sizeof(double) * nq);   /* P as neighbours read it */
     double* lnP = (double*)malloc(sizeof(double) * nq);
     double* Phi = (double*)malloc(sizeof(double) * nq);
     double* C = (double*)malloc(sizeof(double) * (size_t)q);
     double* gp = (double*)malloc(sizeof(double) * (size_t)q);
-    if (!P || !lnP || !Phi || !C || !gp) {
-        free(P); free(lnP); free(Phi); free(C); free(gp);
+    if (!P || !Pn || !lnP || !Phi || !C || !gp) {
+        free(P); free(Pn); free(lnP); free(Phi); free(C); free(gp);
         return -2;
     }
     for (int32_t r = 0; r < R; ++r) {
@@ -186,8 +210,10 @@ int orc_bmincut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev
             for (int32_t s = 0; s < q; ++s) Z += exp(hi[s] - mx);
             double lz = log(Z);
             for (int32_t s = 0; s < q; ++s) {
-                lnP[(size_t)i * q + s] = hi[s] - mx - lz;
-                P[(size_t)i * q + s] = exp(lnP[(size_t)i * q + s]);
+                size_t k = (size_t)i * q + s;
+                lnP[k] = hi[s] - mx - lz;
+                P[k] = exp(lnP[k]);
+                Pn[k] = mdt ? orc_round_bf16(P[k]) : P[k];
             }
         }
         for (int32_t s = 0; s < q; ++s) C[s] = 0.0;
@@ -197,15 +223,17 @@ int orc_bmincut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev
         double cut_acc = 0.0;
         for (int64_t e = 0; e < ne; ++e) {
             int32_t i = eu[e], j = ev[e];
-            double dot = 0.0;
+            /* ordering (i,j) reads P_i and the stored P_j, (j,i) the reverse */
+            double dot_ij = 0.0, dot_ji = 0.0;
             for (int32_t s = 0; s < q; ++s) {
-                dot += P[(size_t)i * q + s] * P[(size_t)j * q + s];
-                Phi[(size_t)i * q + s] += w[e] * P[(size_t)j * q + s];
-                Phi[(size_t)j * q + s] += w[e] * P[(size_t)i * q + s];
+                dot_ij += P[(size_t)i * q + s] * Pn[(size_t)j * q + s];
+                dot_ji += P[(size_t)j * q + s] * Pn[(size_t)i * q + s];
+                Phi[(size_t)i * q + s] += w[e] * Pn[(size_t)j * q + s];
+                Phi[(size_t)j * q + s] += w[e] * Pn[(size_t)i * q + s];
             }
             /* sum_s P_i(s)[1-P_j(s)] = 1 - P_i.P_j, once per ordering */
-            cut_acc += w[e] * (1.0 - dot);
-            cut_acc += w[e] * (1.0 - dot);
+            cut_acc += w[e] * (1.0 - dot_ij);
+            cut_acc += w[e] * (1.0 - dot_ji);
         }
         double bal = 0.0;
         for (int32_t s = 0; s < q; ++s) {
@@ -236,7 +264,7 @@ int orc_bmincut_grad(int32_t n, int64_t ne, const int32_t* eu, const int32_t* ev
             }
         }
     }
-    free(P); free(lnP); free(Phi); free(C); free(gp);
+    free(P); free(Pn); free(lnP); free(Phi); free(C); free(gp);
     return 0;
 }
 
@@ -277,17 +305,18 @@ static int canon_clause(const int32_t* lit, int64_t len, int32_t* var, int32_t* 
  *   g^h_i = [g^p_i(1) - g^p_i(0)] P_i(1) P_i(0)
  */
 int orc_maxsat_grad(int32_t n, int64_t M, const int64_t* off, const int32_t* lits,
-                    int32_t R, const double* h, double beta, double* g, double* U, double* S)
+                    int32_t R, const double* h, double beta, int32_t mdt, double* g, double* U, double* S)
 {
     int64_t kmax = 0;
     for (int64_t m = 0; m < M; ++m) if (off[m + 1] - off[m] > kmax) kmax = off[m + 1] - off[m];
     int32_t* var = (int32_t*)malloc(sizeof(int32_t) * (size_t)(kmax + 1));
     int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (size_t)(kmax + 1));
     double* ufalse = (double*)malloc(sizeof(double) * (size_t)(kmax + 1));
+    double* ustore = (double*)malloc(sizeof(double) * (size_t)(kmax + 1));   /* as other literals read it */
     double* gp1 = (double*)malloc(sizeof(double) * (size_t)n);  /* energy part of g^p_i(1) */
     double* gp0 = (double*)malloc(sizeof(double) * (size_t)n);  /* energy part of g^p_i(0) */
-    if (!var || !pos || !ufalse || !gp1 || !gp0) {
-        free(var); free(pos); free(ufalse); free(gp1); free(gp0);
+    if (!var || !pos || !ufalse || !ustore || !gp1 || !gp0) {
+        free(var); free(pos); free(ufalse); free(ustore); free(gp1); free(gp0);
         return -2;
     }
     for (int32_t r = 0; r < R; ++r) {
@@ -297,16 +326,27 @@ int orc_maxsat_grad(int32_t n, int64_t M, const int64_t* off, const int32_t* lit
             int k = canon_clause(lits + off[m], off[m + 1] - off[m], var, pos);
             if (k < 0) continue;
             for (int a = 0; a < k; ++a) {
-                double p1 = sigmoid(h[(size_t)var[a] * R + r]);
+                double x = h[(size_t)var[a] * R + r];
+                double p1 = sigmoid(x);
                 /* 1 - P_i(W_mi): the probability that this literal is false */
                 ufalse[a] = pos[a] ? 1.0 - p1 : p1;
+                ustore[a] = ufalse[a];
+                if (mdt) {
+                    /* bfloat16 copy: the smaller marginal min(P, 1 - P) is
+                       stored, the larger one is 1 minus it */
+                    double small = orc_round_bf16(sigmoid(-fabs(x)));
+                    int literal_likely = (x > 0.0) == (pos[a] != 0);
+                    ustore[a] = literal_likely ? small : 1.0 - small;
+                }
             }
-            double prod = 1.0;
-            for (int a = 0; a < k; ++a) prod *= ufalse[a];
+            /* the clause's energy as its first literal evaluates it: its own
+               marginal and the others' stored ones */
+            double prod = ufalse[0];
+            for (int a = 1; a < k; ++a) prod *= ustore[a];
             u_acc += prod;
             for (int a = 0; a < k; ++a) {
                 double cav = 1.0;
-                for (int b = 0; b < k; ++b) if (b != a) cav *= ufalse[b];
+                for (int b = 0; b < k; ++b) if (b != a) cav *= ustore[b];
                 if (pos[a]) gp1[var[a]] -= cav; else gp0[var[a]] -= cav;
             }
         }
@@ -325,7 +365,7 @@ int orc_maxsat_grad(int32_t n, int64_t M, const int64_t* off, const int32_t* lit
         if (U) U[r] = u_acc;
         if (S) S[r] = s_acc;
     }
-    free(var); free(pos); free(ufalse); free(gp1); free(gp0);
+    free(var); free(pos); free(ufalse); free(ustore); free(gp1); free(gp0);
     return 0;
 }
 
@@ -460,7 +500,7 @@ int orc_bmincut_grad_manip(int32_t n, int64_t ne, const int32_t* eu, const int32
 int orc_maxsat_grad_manip(int32_t n, int64_t M, const int64_t* off, const int32_t* lits,
                           int32_t R, const double* h, double beta, double gamma, double* g)
 {
-    int rc = orc_maxsat_grad(n, M, off, lits, R, h, beta, g, NULL, NULL);
+    int rc = orc_maxsat_grad(n, M, off, lits, R, h, beta, 0, g, NULL, NULL);
     if (rc) return rc;
     for (size_t k = 0; k < (size_t)n * (size_t)R; ++k) g[k] *= gamma;
     return 0;
@@ -606,6 +646,7 @@ typedef struct {
     int32_t manip;          /* 1: manipulated gradients (no energies) */
     double gamma;           /* gamma_grad of the manipulated form */
     const double* nw;       /* bMinCut node weights (NULL: all 1) */
+    int32_t mdt;            /* 1: neighbours read a bfloat16 copy of the marginals */
 } orc_problem;
 
 int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, double* m1,
@@ -630,12 +671,12 @@ int orc_run(const orc_problem* pb, int32_t t0, int32_t n_steps, double* h, doubl
         else if (pb->manip)
             rc = orc_maxsat_grad_manip(pb->n, pb->ne, pb->off, pb->lits, pb->R, h, beta, pb->gamma, g);
         else if (pb->kind == 0)
-            rc = orc_maxcut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->R, h, beta, g, U, S);
+            rc = orc_maxcut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->R, h, beta, pb->mdt, g, U, S);
         else if (pb->kind == 1)
             rc = orc_bmincut_grad(pb->n, pb->ne, pb->eu, pb->ev, pb->w, pb->nw, pb->q,
-                                  orc_lambda(pb->lam_ramp, pb->lam, pb->T, t), pb->R, h, beta, g, U, S);
+                                  orc_lambda(pb->lam_ramp, pb->lam, pb->T, t), pb->R, h, beta, pb->mdt, g, U, S);
         else
-            rc = orc_maxsat_grad(pb->n, pb->ne, pb->off, pb->lits, pb->R, h, beta, g, U, S);
+            rc = orc_maxsat_grad(pb->n, pb->ne, pb->off, pb->lits, pb->R, h, beta, pb->mdt, g, U, S);
         if (rc) { free(g); return rc; }
         if (g_hist) memcpy(g_hist + (size_t)k * vals, g, sizeof(double) * vals);
         if (pb->opt == 1)

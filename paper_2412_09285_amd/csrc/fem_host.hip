@@ -159,6 +159,10 @@ static fem_status build_graph(int kind, int device, int32_t n, int64_t n_edges, 
     *out = nullptr;
     if (n < 1) return fail(FEM_E_INVAL, "n must be >= 1 (got %d)", n);
     double v2 = (double)n;
+    // the same bound with unit weights: the column sums of n nodes in 2^-40
+    // fixed point and the squared group sizes stay exact up to n = 2^22
+    if (kind == KIND_BMINCUT && !node_w && n > ((int32_t)1 << 22))
+        return fail(FEM_E_UNSUPPORTED, "bMinCut with more than 2^22 nodes per instance");
     if (node_w) {
         // fixed-point column sums hold sum_i V_i P_i(s) * 2^40 in int64, and
         // group weights are squared exactly in double: sum_i V_i <= 2^22
@@ -980,6 +984,18 @@ fem_status fem_batch_create(int32_t nparts, fem_problem* const* parts, fem_probl
         if (weighted) {   // unit weights for the parts that have none
             if (pb.h_nw.empty()) p.h_nw.insert(p.h_nw.end(), (size_t)pb.n, 1);
             else p.h_nw.insert(p.h_nw.end(), pb.h_nw.begin(), pb.h_nw.end());
+        }
+        if (p.kind == KIND_BMINCUT) {
+            // every instance keeps the bound its part was created under
+            for (size_t k = 0; k + 1 < pb.inst_off.size(); ++k) {
+                int64_t vsum = 0;
+                for (int32_t i = pb.inst_off[k]; i < pb.inst_off[k + 1]; ++i)
+                    vsum += pb.h_nw.empty() ? 1 : pb.h_nw[(size_t)i];
+                if (vsum > ((int64_t)1 << 22)) {
+                    delete fp;
+                    return fail(FEM_E_UNSUPPORTED, "part %d: summed node weight of an instance exceeds 2^22", b);
+                }
+            }
         }
         const int64_t base = p.nnz;
         const int32_t noff = p.n;

@@ -69,6 +69,11 @@ def test_bmincut_rejects():
     with pytest.raises(fem.FemError) as ei:
         fem.Problem.bmincut(3, [0], [1], [-1.0], 4)
     assert ei.value.status == fem.FEM_E_INVAL and "> 0" in ei.value.message
+    # unit weights: the column sums and squared group sizes are exact up to
+    # 2^22 nodes per instance (the bound weighted problems have on sum V_i)
+    with pytest.raises(fem.FemError) as ei:
+        fem.Problem.bmincut((1 << 22) + 1, [0], [1], None, 4)
+    assert ei.value.status == fem.FEM_E_UNSUPPORTED and "2^22" in ei.value.message
 
 
 @pytest.mark.parametrize("n,off,lits,status,msg", [

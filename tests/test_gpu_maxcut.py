@@ -37,15 +37,20 @@ def free_run(graph, R, T, n_steps, seed, dtype=fem.F32, tile=None, lr=0.1):
                 href=run.h, betas=betas, solver=s, prob=prob)
 
 
-def lockstep_maxcut(g, R, T, n_steps, seed, dtype=fem.F32, tile=None, lr=0.1, tag=""):
+def lockstep_maxcut(g, R, T, n_steps, seed, dtype=fem.F32, tile=None, lr=0.1, tag="", sched=0, beta_min=0.01,
+                    beta_max=5.0, tune=False):
     h0 = W.initial_fields(g.n, R, seed)
     prob = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
-    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1, marginal_dtype=dtype, lr=lr))
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1, marginal_dtype=dtype, lr=lr,
+                                            schedule=sched, beta_min=beta_min, beta_max=beta_max))
     if tile is not None:
         s.set_tile(*tile)
-    P = O.Params(R=R, T=T, lr=lr)
+    if tune:
+        s.set_fields(h0)
+        tag += f", tile {s.tune(trial_steps=3, use_cache=True)}"
+    P = O.Params(R=R, T=T, lr=lr, mdt=int(dtype == fem.BF16), sched=sched, beta_min=beta_min, beta_max=beta_max)
     run = O.maxcut_run(g, P, h0)
-    betas = [O.beta(0, P.beta_min, P.beta_max, T, t) for t in range(n_steps)]
+    betas = [O.beta(sched, P.beta_min, P.beta_max, T, t) for t in range(n_steps)]
     return lockstep(s, run, P, n_steps, R, tag, betas)
 
 
@@ -147,29 +152,28 @@ def test_config2_full_size_two_steps():
     lockstep(s, run, P, 2, R, f"C2 full, tile {tile}", [O.beta(0, 0.01, 5.0, T, t) for t in range(2)])
 
 
-def test_bf16_marginals_gradient_bound():
-    """BF16 storage of m = tanh(h/2) changes each gathered value by at most
-    2^-8 |m_j| (round to nearest, 8 significant bits), so
-    |g_bf16 - g| <= P(1-P) * 2 * sum_j |W_ij| |m_j| 2^-8 on top of the float32
-    rounding.  Checked on the first steps of C1 against the FP64 oracle; the
-    free-running error over 100 steps is printed, not asserted."""
-    g = W.config_graph(1)
-    R, T = 16, 500
-    res = free_run(g, R=R, T=T, n_steps=100, seed=101, dtype=fem.BF16)
-    h0 = W.initial_fields(g.n, R, seed=101).astype(np.float64)
-    # bound at step 0, where both sides evaluate the same h0
-    m = np.tanh(h0 / 2)
-    absW = np.zeros(g.n)
-    phi_abs = np.zeros((g.n, R))
-    np.add.at(phi_abs, g.u, np.abs(g.w)[:, None] * np.abs(m[g.v]))
-    np.add.at(phi_abs, g.v, np.abs(g.w)[:, None] * np.abs(m[g.u]))
-    p = 1 / (1 + np.exp(-h0))
-    bound = p * (1 - p) * 2 * phi_abs * 2.0 ** -8 + 1e-5 * np.abs(res["gref"][0]).max()
-    err = np.abs(res["grads"][0] - res["gref"][0])
-    assert np.all(err <= bound), float((err - bound).max())
-    rel, mx = grad_errors(res["grads"][-1], res["gref"][-1], R)
-    hrel, _ = grad_errors(res["h"], res["href"], R)
-    print(f"[C1 bf16] step-99 grad rel err {rel.max():.2e}, h(100) rel err {hrel.max():.2e}", flush=True)
+def test_config1_bf16_first_100_steps():
+    """BF16 marginal copy on C1: every one of the first 100 steps against the
+    oracle with the same bfloat16 copy (it rounds its own FP64 marginals), at
+    the 1e-5 bar except where the float32 and FP64 marginals round to
+    different bfloat16 neighbours (bounded separately, counted in the
+    output)."""
+    lockstep_maxcut(W.config_graph(1), R=16, T=500, n_steps=100, seed=101, dtype=fem.BF16, tag="C1 bf16")
+
+
+def test_config2_bf16_full_size_two_steps():
+    """N = 100,000, 300,000 edges (+/-1), R = 256, BF16 copy, in the tuned
+    launch shape: two lockstep steps on all replicas."""
+    lockstep_maxcut(W.config_graph(2), R=256, T=2000, n_steps=2, seed=102, dtype=fem.BF16, tag="C2 full bf16",
+                    tune=True)
+
+
+@pytest.mark.parametrize("dtype", [fem.F32, fem.BF16])
+def test_exponential_schedule(dtype):
+    """The exponential beta schedule (Methods), beta 0.02 -> 20 over 300
+    steps: 60 lockstep steps on the ER-800 workload."""
+    lockstep_maxcut(W.config_graph(1), R=16, T=300, n_steps=60, seed=13, dtype=dtype, sched=fem.SCHED_EXP,
+                    beta_min=0.02, beta_max=20.0, tag=f"exp schedule dtype {dtype}")
 
 
 @pytest.mark.parametrize("opt,kw", [(fem.OPT_RMSPROP, dict(momentum=0.63, rms_alpha=0.56, lr=0.03, weight_decay=0.013)),

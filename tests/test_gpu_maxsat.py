@@ -50,13 +50,13 @@ def free_run(cnf, R, T, n_steps, seed, dtype=fem.F32, tile=None):
                 Sref=Sh, href=run.h, betas=betas)
 
 
-def lockstep_sat(cnf, R, T, n_steps, seed, tile=None, tag=""):
+def lockstep_sat(cnf, R, T, n_steps, seed, tile=None, tag="", dtype=fem.F32):
     h0 = W.initial_fields(cnf.n_vars, R, seed)
     prob = fem.Problem.maxsat(cnf.n_vars, cnf.clause_off, cnf.lits)
-    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1))
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=T, keep_grad=1, marginal_dtype=dtype))
     if tile is not None:
         s.set_tile(*tile)
-    P = O.Params(R=R, T=T)
+    P = O.Params(R=R, T=T, mdt=int(dtype == fem.BF16))
     run = O.maxsat_run(cnf, P, h0)
     betas = [O.beta(0, P.beta_min, P.beta_max, T, t) for t in range(n_steps)]
     return lockstep(s, run, P, n_steps, R, tag, betas)
@@ -105,15 +105,16 @@ def test_paper_example_cnf():
     assert vals.min() == 0
 
 
-def test_bf16_close():
-    cnf = W.random_ksat(2000, 16000, 3, seed=4)
-    res = free_run(cnf, R=64, T=2000, n_steps=30, seed=104, dtype=fem.BF16)
-    rel, _ = grad_errors(res["grads"][0], res["gref"][0], 64)
-    # stored min(P, 1-P) keeps 8 significant bits: each factor of a cavity
-    # product is off by <= 2^-8 relative
-    assert rel.max() < 4 * 2.0 ** -8, rel.max()
-    rel2, _ = grad_errors(res["grads"][-1], res["gref"][-1], 64)
-    print(f"[3sat bf16] step-0 grad rel {rel.max():.2e}, step-29 grad rel {rel2.max():.2e}", flush=True)
+def test_random_3sat_bf16_first_100_steps():
+    """BF16 copy of min(P, 1 - P): the first 100 steps against the oracle
+    with the same bfloat16 copy, 1e-5 except where the two sides may round a
+    stored value to different bfloat16 neighbours."""
+    lockstep_sat(W.random_ksat(2000, 16000, 3, seed=4), R=64, T=2000, n_steps=100, seed=104, dtype=fem.BF16,
+                 tag="3sat2000 bf16")
+
+
+def test_mixed_lengths_bf16():
+    lockstep_sat(mixed_cnf(300, 1500, seed=5), R=16, T=300, n_steps=40, seed=6, dtype=fem.BF16, tag="mixed bf16")
 
 
 def test_config4_full_size_two_steps():
