@@ -119,22 +119,43 @@ def _clauses(off, lits):
     return out
 
 
+def _abs_adjacency(run):
+    """|W| as a symmetric sparse matrix (cached on the run)."""
+    A = getattr(run, "_absW", None)
+    if A is None:
+        import scipy.sparse as sp
+
+        u, v, w = run._keep
+        aw = np.abs(np.asarray(w, dtype=np.float64))
+        A = sp.csr_matrix((np.concatenate([aw, aw]), (np.concatenate([u, v]), np.concatenate([v, u]))),
+                          shape=(run.n, run.n))
+        run._absW = A
+    return A
+
+
+def _spmm(A, x):
+    """A @ x over the first axis of x (any trailing shape)."""
+    return np.asarray(A @ x.reshape(x.shape[0], -1)).reshape(x.shape)
+
+
 def u_scale(run, h, t):
     """Summed magnitude of the terms U is formed from, per replica (None for
     Max-k-SAT, whose U is a sum of non-negative terms: |U| itself)."""
     h = np.asarray(h, dtype=np.float64)
     if run.kind == O.KIND_MAXCUT:
-        u, v, w = run._keep
-        m = np.tanh(0.5 * h)
-        return np.sum(np.abs(w)[:, None] * (1.0 + np.abs(m[u] * m[v])), axis=0)
+        A = _abs_adjacency(run)
+        am = np.abs(np.tanh(0.5 * h))
+        # sum over edges |W| (1 + |m_u m_v|)
+        return 0.5 * A.sum() + 0.5 * np.sum(am * _spmm(A, am), axis=0)
     if run.kind == O.KIND_BMINCUT:
-        u, v, w = run._keep
         p = run.p
+        A = _abs_adjacency(run)
         P = _softmax(h)
         V = np.ones(h.shape[0]) if run.node_w is None else run.node_w
         C = np.einsum("i,irs->rs", V, P)
         lam = O.lam(p.lam_ramp, p.lam, p.T, t)
-        cut = 2.0 * np.sum(np.abs(w)[:, None] * (1.0 + np.sum(P[u] * P[v], axis=2)), axis=0)
+        # ordered pairs: sum |W| (1 + P_i . P_j)
+        cut = A.sum() + np.sum(P * _spmm(A, P), axis=(0, 2))
         bal = np.sum(C * C, axis=1) + np.einsum("i,irs->r", V * V, P * P)
         return cut + abs(lam) * bal
     return None
@@ -157,23 +178,15 @@ def bf16_slack(run, h, t):
     the stored values which may round differently on the two sides can make."""
     h = np.asarray(h, dtype=np.float64)
     if run.kind == O.KIND_MAXCUT:
-        u, v, w = run._keep
         m = np.tanh(0.5 * h)
         amb, step = _ambiguous(m)
-        d = np.where(amb, step, 0.0)
-        dphi = np.zeros_like(h)
-        np.add.at(dphi, u, np.abs(w)[:, None] * d[v])
-        np.add.at(dphi, v, np.abs(w)[:, None] * d[u])
+        dphi = _spmm(_abs_adjacency(run), np.where(amb, step, 0.0))
         p = _sigmoid(h)
         return p * (1 - p) * 2.0 * dphi, 0.5 * np.sum(np.abs(m) * dphi, axis=0)
     if run.kind == O.KIND_BMINCUT:
-        u, v, w = run._keep
         P = _softmax(h)
         amb, step = _ambiguous(P)
-        d = np.where(amb, step, 0.0)
-        dphi = np.zeros_like(h)
-        np.add.at(dphi, u, np.abs(w)[:, None, None] * d[v])
-        np.add.at(dphi, v, np.abs(w)[:, None, None] * d[u])
+        dphi = _spmm(_abs_adjacency(run), np.where(amb, step, 0.0))
         dA = 2.0 * dphi
         gs = P * (dA + np.sum(P * dA, axis=2, keepdims=True))
         return gs, np.sum(P * dphi, axis=(0, 2))
@@ -185,7 +198,7 @@ def bf16_slack(run, h, t):
     dU = np.zeros(h.shape[1])
     for cl in _clauses(off, lits):
         tot = du[cl].sum(axis=0)
-        for a, x in enumerate(cl):
+        for x in cl:
             dd[x] += tot - du[x]
         dU += tot - du[cl[0]]
     p = _sigmoid(h)
