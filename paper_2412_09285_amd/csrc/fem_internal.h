@@ -74,6 +74,11 @@ __host__ __device__ constexpr int step_max_threads(int kind, int per_lane)
                                 : (per_lane >= 8 ? 512 : 1024);
 }
 
+// Waves per SIMD the bMinCut step kernel is compiled for: at q = 8 the
+// register budget of four waves (128 VGPRs) holds eight gathered rows in
+// flight with double field sums; other q take what the compiler chooses.
+__host__ __device__ constexpr int potts_min_waves(int q) { return q == 8 ? 4 : 1; }
+
 // bMinCut step kernel: per-lane running sums in LDS up to q = 16 (q + 3
 // doubles per thread); the block reduction reuses that space
 __host__ __device__ constexpr bool potts_lds_acc(int q) { return q <= 16; }

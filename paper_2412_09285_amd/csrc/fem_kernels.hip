@@ -47,8 +47,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
     const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
-    // compute type of the field sums and the gradient combination
-    using CT = typename std::conditional<sizeof(MT) == 4, double, float>::type;
+    // the field sums and the gradient combination are formed in double for
+    // either marginal type: near equilibrium g is a small difference of
+    // 2 phi and h / beta, and float sums of neighbour values that span many
+    // binades would lose the low bits of that difference
+    using CT = double;
     // per-lane energy terms over the few rows of one team (float), widened
     // to double for the workgroup and tile sums
     float eacc[2 * V];
@@ -64,10 +67,6 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
             ld_state<V, NT>(a.h + sbase, hv);
             ld_state<V, NT>(a.m1 + sbase, m1v);
             ld_state<V, NT>(a.m2 + sbase, m2v);
-            // phi accumulates in double for float32 marginals (near
-            // equilibrium g is a small difference of 2 phi and h / beta); a
-            // bfloat16 copy carries 8 bits, so float accumulation is exact
-            // enough there
             CT acc[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) acc[v] = (CT)0;
@@ -190,7 +189,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
 // in flight (at q = 8: 121 VGPRs, 4 waves per SIMD, instead of 164 and 3).
 // The sums are formed in the same order either way.
 template <int Q, typename MT, bool EN, bool NT>
-__global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_kernel(StepArgs a)
+__global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q), potts_min_waves(Q)) potts_step_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blk_tile(a.seg_major)];
     const int seg = blk_seg(a.seg_major);
@@ -202,11 +201,11 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
     const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
-    // Phi accumulates and the gradient terms combine in double for float32
-    // marginals up to q = 8 (at larger q the registers would not hold it);
-    // bfloat16 marginals carry 8 bits, so float is exact enough there
-    using AccT = typename std::conditional<(Q <= 8 && sizeof(MT) == 4), double, float>::type;
-    using CT = typename std::conditional<sizeof(MT) == 4, double, float>::type;
+    // Phi accumulates in double up to q = 8 (at larger q the registers would
+    // not hold it) and the gradient terms combine in double, for either
+    // marginal type: the bfloat16 copy changes only the values gathered
+    using AccT = typename std::conditional<(Q <= 8), double, float>::type;
+    using CT = double;
     constexpr bool LA = potts_lds_acc(Q);
     extern __shared__ double lds_d[];
     const int nthr = blockDim.x, tid = threadIdx.x;
@@ -367,20 +366,14 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_
             const float invZ2 = 1.0f / Z2;
 #pragma unroll
             for (int s = 0; s < Q; ++s) Pn[s] *= invZ2;
-            // column-sum contributions: a double-precision softmax for float32
-            // marginals (their rounding, summed over all nodes, would carry
-            // into the balance term); the float softmax for bfloat16 ones,
-            // whose own rounding is 2^-8
+            // column-sum contributions from a double-precision softmax (the
+            // rounding of float32 marginals, summed over all nodes, would
+            // carry into the balance term), whatever the copy's type
             if constexpr (LA) {
 #pragma unroll
                 for (int s = 0; s < Q; ++s) cs[s] = 0;
             }
-            if constexpr (sizeof(MT) == 4) {
-                colsum_add<Q>(hv, cs, (double)vw);
-            } else {
-#pragma unroll
-                for (int s = 0; s < Q; ++s) cs[s] += to_fixed((double)vw * (double)Pn[s]);
-            }
+            colsum_add<Q>(hv, cs, (double)vw);
             if constexpr (LA) {
 #pragma unroll
                 for (int s = 0; s < Q; ++s) cs_l[s * nthr + tid] += cs[s];
@@ -445,8 +438,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
     const MT* __restrict__ mc = static_cast<const MT*>(a.marg_cur);
     MT* __restrict__ mn = static_cast<MT*>(a.marg_nxt);
     const StepScalars sc = a.sc;
-    // compute type of the clause sums and the gradient combination
-    using CT = typename std::conditional<sizeof(MT) == 4, double, float>::type;
+    // the clause sums and the gradient combination are formed in double for
+    // either marginal type
+    using CT = double;
     float eacc[2 * V];
 #pragma unroll
     for (int k = 0; k < 2 * V; ++k) eacc[k] = 0.0f;
