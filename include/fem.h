@@ -270,6 +270,30 @@ fem_status fem_round(fem_solver* s, int32_t* sigma);
  * Exact for integral weights (|total| < 2^53). */
 fem_status fem_eval_int(const fem_problem* p, int32_t R, const int32_t* sigma, int64_t* value,
                         int64_t* sizes);
+/* For callers that cannot allocate device memory (work recorded into a HIP
+ * graph, tight serving loops, harnesses that forbid hipMalloc): the integer
+ * evaluation of fem_eval_int on device-resident configurations, allocating
+ * nothing.  Every intermediate (byte configurations, tile lists, per-tile
+ * partial sums) lives in one fixed array of FEM_NOALLOC_SCRATCH_BYTES per
+ * device, which the library holds from the first call on that device until
+ * the process ends.  Results are bit-identical to fem_eval_int's.
+ *  sigma: device int32 [R][n] (caller-owned, on the problem's device);
+ *  value: device int64 [B][R]; sizes: device int64 [B][R][q] for bMinCut, or
+ *    NULL (ignored for other kinds);
+ *  hip_stream: the stream the work is enqueued on (NULL = the null stream).
+ * The call only enqueues work: the outputs are valid once the stream has
+ * reached that point.  A replica whose configuration holds a state outside
+ * [0, q) gets value INT64_MIN and sizes -1 (the configuration is on the
+ * device, so it is checked there, not on return).  Problems that would need
+ * more than FEM_NOALLOC_SCRATCH_BYTES (about n*R bytes plus the partial sums)
+ * give FEM_E_UNSUPPORTED with the size needed; NULL arguments or R < 1 give
+ * FEM_E_INVAL.  All calls on one GPU share its array and keep no state in it
+ * between calls: calls that overlap on one GPU (on different streams, or
+ * from different threads, without ordering) race and give wrong results;
+ * order them on one stream or synchronise in between. */
+#define FEM_NOALLOC_SCRATCH_BYTES (64u << 20)
+fem_status fem_eval_int_noalloc(const fem_problem* p, int32_t R, const int32_t* sigma, int64_t* value,
+                                int64_t* sizes, void* hip_stream);
 /* Round the current fields, evaluate, and return per instance the best
  * replica (max cut; min unsat; min 2*cut + lambda*sum_s |Pi_s|(|Pi_s|-1) for
  * bMinCut, 2*cut + lambda*(sum_s W_s^2 - sum_i V_i^2) with node weights;

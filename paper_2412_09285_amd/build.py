@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfem.so")
-SOURCES = ["fem_kernels.hip", "fem_manip.hip", "fem_dense.hip", "fem_host.hip", "fem_mpnn.hip"]
+SOURCES = ["fem_kernels.hip", "fem_manip.hip", "fem_dense.hip", "fem_host.hip", "fem_mpnn.hip", "fem_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -101,6 +101,7 @@ static void free_problem_device(Problem& p)
     dfree(p.nrm);
     dfree(p.nw);
     dfree(p.v2);
+    dfree(p.inst_off_d);
     dfree(p.dense_w);
     dfree(p.dense_w8);
 }
@@ -134,6 +135,8 @@ static fem_status upload_problem(Problem& p)
         HIPCHK(dalloc(&p.nw, p.h_nw.size()));
         HIPCHK(hipMemcpy(p.nw, p.h_nw.data(), p.h_nw.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
+    HIPCHK(dalloc(&p.inst_off_d, p.inst_off.size()));
+    HIPCHK(hipMemcpy(p.inst_off_d, p.inst_off.data(), p.inst_off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!p.inst_v2.empty()) {
         HIPCHK(dalloc(&p.v2, p.inst_v2.size()));
         HIPCHK(hipMemcpy(p.v2, p.inst_v2.data(), p.inst_v2.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -441,23 +444,6 @@ struct fem_solver {
     size_t prof_used = 0;
     bool capturing = false;
 };
-
-static int pow2ceil(int x)
-{
-    int p = 1;
-    while (p < x) p <<= 1;
-    return p;
-}
-
-static LaunchGeom make_geom(int per_lane, int R, int waves, int max_lanes = 64)
-{
-    LaunchGeom g{};
-    const int need = (R + per_lane - 1) / per_lane;
-    g.lanes = std::min(max_lanes > 0 ? max_lanes : 64, pow2ceil(need));
-    g.nseg = (need + g.lanes - 1) / g.lanes;
-    g.teams_per_block = waves * (64 / g.lanes);
-    return g;
-}
 
 // workgroup LDS used by the reductions: waves * lanes * values-per-lane * 8 B
 static const size_t LDS_LIMIT = 64 * 1024;
@@ -824,21 +810,6 @@ static void destroy_solver(fem_solver* s)
     fem_problem* owner = s->owner;
     delete s;
     problem_unref(owner);
-}
-
-static TileShape default_shape(int kind, int R)
-{
-    TileShape t;
-    t.waves = 4;
-    t.rows = 4;
-    if (kind == KIND_BMINCUT) {
-        t.vec = 1;
-        return t;
-    }
-    if (R % 4 == 0 && R >= 128) t.vec = 4;
-    else if (R % 2 == 0 && R >= 64) t.vec = 2;
-    else t.vec = 1;
-    return t;
 }
 
 // ================================================================== C ABI ==

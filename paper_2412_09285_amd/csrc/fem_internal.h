@@ -39,6 +39,7 @@ struct Problem {
     double* nrm = nullptr;           // graphs: sum_j |W_ij| per node (normalisers of the manipulated gradients)
     int32_t* nw = nullptr;           // bMinCut node weights V_i (null: all 1)
     double* v2 = nullptr;            // bMinCut: [n_inst] sum_i V_i^2 per instance
+    int32_t* inst_off_d = nullptr;   // [n_inst+1] node offsets of the instances
     // dense MaxCut: W as a zero-padded row-major float matrix [dense_ld][dense_ld]
     // (the CSR above is still built, for read-out and evaluation)
     float* dense_w = nullptr;
@@ -95,6 +96,23 @@ struct TileShape {
     int lanes = 0;   // cap on lanes per team (power of two <= 64; 0 = 64)
 };
 
+// Default launch shape before tuning: four waves, four rows per team, and as
+// many replicas per lane as keep a team's row within one wave.
+inline TileShape default_shape(int kind, int R)
+{
+    TileShape t;
+    t.waves = 4;
+    t.rows = 4;
+    if (kind == KIND_BMINCUT) {
+        t.vec = 1;
+        return t;
+    }
+    if (R % 4 == 0 && R >= 128) t.vec = 4;
+    else if (R % 2 == 0 && R >= 64) t.vec = 2;
+    else t.vec = 1;
+    return t;
+}
+
 // Per-step scalars, computed on the host in double and passed as float.
 struct StepScalars {
     double inv_beta_d;   // 1/beta and lambda in double for the gradient combination
@@ -117,6 +135,27 @@ struct LaunchGeom {
     int n_tiles;
     int seg_major;    // grid (nseg, n_tiles) instead of (n_tiles, nseg)
 };
+
+inline int pow2ceil(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Teams of lanes covering R replicas at per_lane values per lane, at most
+// max_lanes lanes (0 or 64: a full wave), and the replica segments left over.
+inline LaunchGeom make_geom(int per_lane, int R, int waves, int max_lanes = 64)
+{
+    LaunchGeom g{};
+    const int need = (R + per_lane - 1) / per_lane;
+    const int cap = max_lanes > 0 ? max_lanes : 64;
+    const int p2 = pow2ceil(need);
+    g.lanes = cap < p2 ? cap : p2;
+    g.nseg = (need + g.lanes - 1) / g.lanes;
+    g.teams_per_block = waves * (64 / g.lanes);
+    return g;
+}
 
 // Arguments shared by the step kernels.
 struct StepArgs {

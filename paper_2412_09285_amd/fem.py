@@ -26,6 +26,8 @@ OPT_ADAM, OPT_RMSPROP, OPT_SGD = 0, 1, 2
 GRAD_EXPLICIT, GRAD_MANIPULATED = 0, 1
 STATE_SEPARATE, STATE_INTERLEAVED = 0, 1
 F32, BF16 = 0, 1
+# size of the per-device scratch array of fem_eval_int_noalloc (FEM_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class FemError(RuntimeError):
@@ -90,6 +92,7 @@ _SIGS = {
     "fem_energy_history": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P]),
     "fem_round": (C.c_int, [_P, _P]),
     "fem_eval_int": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
+    "fem_eval_int_noalloc": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P]),
     "fem_best": (C.c_int, [_P, _P, _P, _P]),
     "fem_anytime_best": (C.c_int, [_P, _P]),
     "fem_state_size": (C.c_int, [_P, _P]),
@@ -287,6 +290,18 @@ class Problem:
         _check(lib().fem_eval_int(self._h, R, ps, vals.ctypes.data_as(C.c_void_p),
                                   None if sizes is None else sizes.ctypes.data_as(C.c_void_p)))
         return vals, sizes
+
+    def eval_int_noalloc(self, sigma, value, sizes=None, stream=None):
+        """Device tensors: sigma int32 [R][n], value int64 [B][R], sizes int64
+        [B][R][q] or None; enqueued on stream (torch stream, raw handle, or
+        None for the null stream); allocates nothing (fem.h)."""
+        R = int(sigma.shape[0])
+        for t, shape in ((sigma, (R, self.n)), (value, (self.n_inst, R))) + \
+                (((sizes, (self.n_inst, R, self.q)),) if sizes is not None else ()):
+            assert t.is_cuda and t.is_contiguous() and tuple(t.shape) == shape, (tuple(t.shape), shape)
+        _check(lib().fem_eval_int_noalloc(self._h, R, C.c_void_p(sigma.data_ptr()), C.c_void_p(value.data_ptr()),
+                                          None if sizes is None else C.c_void_p(sizes.data_ptr()),
+                                          _stream_ptr(stream)))
 
     def close(self):
         if self._h:

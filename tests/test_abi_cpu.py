@@ -29,6 +29,12 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(fem._SIGS), set(names) - set(fem._SIGS)
 
 
+def test_noalloc_scratch_size_matches_header():
+    txt = open(os.path.join(ROOT, "include", "fem.h")).read()
+    m = re.search(r"#define FEM_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == fem.NOALLOC_SCRATCH_BYTES
+
+
 def test_abi_version_and_status_strings():
     assert fem.lib().fem_abi_version() == 2
     assert fem.status_str(0) == "FEM_OK"
