@@ -69,13 +69,16 @@ __device__ __forceinline__ float dense_update(const StepArgs& a, const StepScala
 {
     const size_t sbase = (size_t)i * a.srow + r;
     const float ax = fabsf(x);
-    const float e = expf(-ax);
-    const float ope = 1.0f + e;
-    const float pq = e / (ope * ope);   // P(1-P) without cancellation
-    const float g = (float)((double)pq * (2.0 * phi + (double)x * sc.inv_beta_d));
+    const float e = exp_neg(ax);
+    const float rr = rcp_f(1.0f + e);
+    const float pmin = e * rr;          // min(P, 1 - P)
+    const float pq = pmin * rr;         // P(1-P) without cancellation
+    const float g = (float)((double)pq * fma((double)x, sc.inv_beta_d, 2.0 * phi));
     if constexpr (EN) {
-        e_mphi += (double)tanhf(0.5f * x) * phi;
-        e_h2 += (double)(log1pf(e) + ax * (e / ope));
+        // own marginal sign(h) (1 - e) / (1 + e): its cancellation near h = 0
+        // leaves an absolute error of about 1e-7, far below the scale of U
+        e_mphi += (double)copysignf((1.0f - e) * rr, x) * phi;
+        e_h2 += (double)(log1p_f(e) + ax * pmin);
     }
     const float nh = adam_update(x, g, m1v, m2v, sc);
     if constexpr (NT) {
@@ -88,7 +91,7 @@ __device__ __forceinline__ float dense_update(const StepArgs& a, const StepScala
         a.m2[sbase] = m2v;
     }
     if (a.grad) a.grad[(size_t)i * a.R + r] = g;
-    return tanhf(0.5f * nh);
+    return tanh_half(nh);
 }
 
 template <bool EN, bool NT>
@@ -385,7 +388,7 @@ __global__ void dense_i8_init_kernel(const float* __restrict__ h, int64_t srow, 
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
         const int r = (int)(k / n), j = (int)(k % n);
         int dg[4];
-        to_digits(tanhf(0.5f * h[(size_t)j * srow + r]), dg);
+        to_digits(tanh_half(h[(size_t)j * srow + r]), dg);
 #pragma unroll
         for (int d = 0; d < 4; ++d) q[d * plane + (size_t)r * ld + j] = (int8_t)dg[d];
     }

@@ -163,6 +163,64 @@ __device__ __forceinline__ void st_state(float* __restrict__ p, const float (&x)
     }
 }
 
+// ------------------------------------------------------------- fast math --
+// The step kernels are bound by their vector ALU, not by memory, once the
+// neighbour gathers hit L2: the general-purpose expf / tanhf / log1pf and
+// IEEE divisions cost tens of instructions each.  These forms use the
+// hardware base-2 exponential and logarithm, reciprocal and square root
+// (about 1 ulp each) with the corrections below, a few ulp in all; the
+// gradient's cancellation-prone combination stays in double in the callers.
+
+// exp(-a), a >= 0 (any a): 2^t with t = -a log2(e) rounded, and the rounding
+// error of t (exact product error by fma, plus the low part of log2(e))
+// applied as the first-order factor 1 + c ln 2
+__device__ __forceinline__ float exp_neg(float a)
+{
+    constexpr float L2E = 1.44269502162933349609375f;      // float(log2 e)
+    constexpr float L2E_LO = 1.925963033500011e-08f;       // log2 e - L2E
+    constexpr float LN2 = 0.693147180559945309f;
+    const float t = -a * L2E;
+    const float c = fmaf(-a, L2E_LO, fmaf(-a, L2E, -t));
+    const float e0 = __builtin_amdgcn_exp2f(t);
+    return fmaf(e0, c * LN2, e0);
+}
+
+__device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_f(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// tanh(y / 2): the odd Taylor series of tanh(z), z = |y|/2, up to z^11 where
+// |y| < 0.55 (truncation below 1e-9 relative), else (1 - e)/(1 + e) with
+// e = exp(-|y|), where 1 - e >= 0.42 keeps its relative precision; the sign
+// of y restored
+__device__ __forceinline__ float tanh_half(float y)
+{
+    const float a = fabsf(y);
+    const float z = 0.5f * a, z2 = z * z;
+    float p = fmaf(z2, 21844.0f / 6081075.0f, -1382.0f / 155925.0f);
+    p = fmaf(p, z2, 62.0f / 2835.0f);
+    p = fmaf(p, z2, -17.0f / 315.0f);
+    p = fmaf(p, z2, 2.0f / 15.0f);
+    p = fmaf(p, z2, -1.0f / 3.0f);
+    const float small = fmaf(p * z2, z, z);
+    const float e = exp_neg(a);
+    const float large = (1.0f - e) * rcp_f(1.0f + e);
+    return copysignf(a < 0.55f ? small : large, y);
+}
+
+// ln(1 + e) for e >= 0: u = 1 + e rounded, then ln(u) e / (u - 1) (the
+// quotient cancels the rounding of u); e itself where u rounds to 1
+__device__ __forceinline__ float log1p_f(float e)
+{
+    constexpr float LN2 = 0.693147180559945309f;
+    const float u = 1.0f + e;
+    const float d = u - 1.0f;
+    const float l = __builtin_amdgcn_logf(u) * LN2;
+    return d == 0.0f ? e : l * (e * rcp_f(d));
+}
+
+// For one logit h with e = exp(-|h|) and r = 1/(1+e): the smaller of P and
+// 1 - P is e r, and P(1 - P) = e r^2, both without cancellation.
+
 // The optimiser step, torch.optim semantics (a uniform branch):
 //  Adam:    g += wd h; m1 = b1 m1 + (1-b1) g; m2 = b2 m2 + (1-b2) g^2;
 //           h -= step_size * m1 / (sqrt(m2)/sqrt(1-b2^n) + eps)
@@ -170,29 +228,31 @@ __device__ __forceinline__ void st_state(float* __restrict__ p, const float (&x)
 //           momentum > 0: m1 = mu m1 + g/d, h -= lr m1;  else h -= lr g/d
 //  SGD:     g += wd h; momentum != 0: m1 = g (first step) or mu m1 + (1-damp) g,
 //           g = m1;  h -= lr g
+// (the divisions by the bias correction and the denominator are taken as
+// products with a reciprocal: 1/sqrt(1 - b2^n) comes from the host in double)
 __device__ __forceinline__ float adam_update(float x, float g, float& m1, float& m2, const StepScalars& s)
 {
-    g = g + s.wd * x;
+    g = fmaf(s.wd, x, g);
     if (s.opt == 0) {
-        m1 = s.b1 * m1 + s.one_m_b1 * g;
-        m2 = s.b2 * m2 + s.one_m_b2 * (g * g);
-        float denom = sqrtf(m2) / s.bc2_sqrt + s.eps;
-        return x - s.step_size * (m1 / denom);
+        m1 = fmaf(s.b1, m1, s.one_m_b1 * g);
+        m2 = fmaf(s.b2, m2, s.one_m_b2 * (g * g));
+        const float denom = fmaf(sqrt_f(m2), s.inv_bc2_sqrt, s.eps);
+        return fmaf(-s.step_size, m1 * rcp_f(denom), x);
     }
     if (s.opt == 1) {
-        m2 = s.rms_alpha * m2 + s.one_m_rms * (g * g);
-        const float d = sqrtf(m2) + s.eps;
+        m2 = fmaf(s.rms_alpha, m2, s.one_m_rms * (g * g));
+        const float id = rcp_f(sqrt_f(m2) + s.eps);
         if (s.mom > 0.0f) {
-            m1 = s.mom * m1 + g / d;
-            return x - s.lr * m1;
+            m1 = fmaf(s.mom, m1, g * id);
+            return fmaf(-s.lr, m1, x);
         }
-        return x - s.lr * (g / d);
+        return fmaf(-s.lr, g * id, x);
     }
     if (s.mom != 0.0f) {
-        m1 = s.first ? g : s.mom * m1 + (1.0f - s.damp) * g;
+        m1 = s.first ? g : fmaf(s.mom, m1, (1.0f - s.damp) * g);
         g = m1;
     }
-    return x - s.lr * g;
+    return fmaf(-s.lr, g, x);
 }
 
 // 2^-40 fixed point of a probability in [0, 1]
@@ -222,8 +282,8 @@ __device__ __forceinline__ void colsum_add(const float (&h)[Q], long long (&cs)[
 // bit set) when P(x=1) > 1/2.  Both tails keep full relative precision.
 __device__ __forceinline__ float sat_encode(float h)
 {
-    float e = expf(-fabsf(h));
-    float small = e / (1.0f + e);
+    const float e = exp_neg(fabsf(h));
+    const float small = e * rcp_f(1.0f + e);
     return h > 0.0f ? -small : small;
 }
 // probability that a literal of polarity pos is false, from the stored value

@@ -618,6 +618,7 @@ static StepScalars step_scalars(const fem_solver* s, int t)
     sc.lam = (float)sc.lam_d;
     sc.step_size = (float)(p.lr / (1.0 - std::pow(p.adam_b1, nstep)));
     sc.bc2_sqrt = (float)std::sqrt(1.0 - std::pow(p.adam_b2, nstep));
+    sc.inv_bc2_sqrt = (float)(1.0 / std::sqrt(1.0 - std::pow(p.adam_b2, nstep)));
     sc.b1 = (float)p.adam_b1;
     sc.one_m_b1 = (float)(1.0 - p.adam_b1);
     sc.b2 = (float)p.adam_b2;

@@ -122,6 +122,7 @@ struct StepScalars {
     float lam;
     float step_size;   // lr / (1 - b1^n)
     float bc2_sqrt;    // sqrt(1 - b2^n)
+    float inv_bc2_sqrt;   // 1 / sqrt(1 - b2^n)
     float b1, one_m_b1, b2, one_m_b2, eps, wd;
     int opt;            // 0 Adam, 1 RMSprop, 2 SGD
     int first;          // SGD: first step (the momentum buffer starts as g)

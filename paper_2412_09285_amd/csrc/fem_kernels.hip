@@ -139,18 +139,23 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
             for (int v = 0; v < V; ++v) {
                 const float x = hv[v];
                 const float ax = fabsf(x);
-                const float e = expf(-ax);
-                const float ope = 1.0f + e;
-                const float pq = e / (ope * ope);   // P(1-P) without cancellation
-                const float g = (float)((CT)pq * ((CT)2 * acc[v] + (CT)x * (CT)sc.inv_beta_d));
+                const float e = exp_neg(ax);
+                const float r = rcp_f(1.0f + e);
+                const float pmin = e * r;            // min(P, 1 - P)
+                const float pq = pmin * r;           // P (1 - P)
+                const float g = (float)((CT)pq * fma((CT)x, (CT)sc.inv_beta_d, (CT)2 * acc[v]));
                 gv[v] = g;
                 if constexpr (EN) {
-                    eacc[v] += (float)((CT)tanhf(0.5f * x) * acc[v]);
-                    eacc[V + v] += log1pf(e) + ax * (e / ope);
+                    // own marginal tanh(h/2) = sign(h) (1 - e) r: near h = 0
+                    // 1 - e cancels, but its absolute error (about 1e-7)
+                    // stays far below the scale of U
+                    const float m_own = copysignf((1.0f - e) * r, x);
+                    eacc[v] += (float)((CT)m_own * acc[v]);
+                    eacc[V + v] += log1p_f(e) + ax * pmin;
                 }
                 const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
                 hv[v] = nh;
-                mnew[v] = tanhf(0.5f * nh);
+                mnew[v] = tanh_half(nh);
             }
             st_state<V, NT>(a.h + sbase, hv);
             st_state<V, NT>(a.m1 + sbase, m1v);
@@ -311,8 +316,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q), potts_min_w
             for (int s = 1; s < Q; ++s) mx = fmaxf(mx, hv[s]);
             float P[Q], Z = 0.0f;
 #pragma unroll
-            for (int s = 0; s < Q; ++s) { P[s] = expf(hv[s] - mx); Z += P[s]; }
-            const float invZ = 1.0f / Z;
+            for (int s = 0; s < Q; ++s) { P[s] = exp_neg(mx - hv[s]); Z += P[s]; }
+            const float invZ = rcp_f(Z);
 #pragma unroll
             for (int s = 0; s < Q; ++s) P[s] *= invZ;
             // gradient terms combined in double: A(s) - sum_s' P(s') A(s') is a
@@ -338,7 +343,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q), potts_min_w
 #pragma unroll
             for (int s = 0; s < Q; ++s) gv[s] = (float)((Aof(s) - avg) * (CT)P[s]);
             if constexpr (EN) {
-                const float lz = logf(Z);
+                const float lz = __builtin_amdgcn_logf(Z) * 0.693147180559945309f;   // ln Z, Z in [1, q]
                 double dot = 0.0;
                 float sq = 0.0f, ent = 0.0f;
 #pragma unroll
@@ -362,8 +367,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q), potts_min_w
             for (int s = 1; s < Q; ++s) mx2 = fmaxf(mx2, hv[s]);
             float Pn[Q], Z2 = 0.0f;
 #pragma unroll
-            for (int s = 0; s < Q; ++s) { Pn[s] = expf(hv[s] - mx2); Z2 += Pn[s]; }
-            const float invZ2 = 1.0f / Z2;
+            for (int s = 0; s < Q; ++s) { Pn[s] = exp_neg(mx2 - hv[s]); Z2 += Pn[s]; }
+            const float invZ2 = rcp_f(Z2);
 #pragma unroll
             for (int s = 0; s < Q; ++s) Pn[s] *= invZ2;
             // column-sum contributions from a double-precision softmax (the
@@ -455,13 +460,17 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
             ld_state<V, NT>(a.h + sbase, hv);
             ld_state<V, NT>(a.m1 + sbase, m1v);
             ld_state<V, NT>(a.m2 + sbase, m2v);
+            // the variable's own min(P, 1 - P) and side, for the clause
+            // energies at owner incidences
             float own_small[V];
             bool own_hi[V];
+            if constexpr (EN) {
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const float e = expf(-fabsf(hv[v]));
-                own_small[v] = e / (1.0f + e);
-                own_hi[v] = hv[v] > 0.0f;
+                for (int v = 0; v < V; ++v) {
+                    const float e = exp_neg(fabsf(hv[v]));
+                    own_small[v] = e * rcp_f(1.0f + e);
+                    own_hi[v] = hv[v] > 0.0f;
+                }
             }
             CT d[V];
 #pragma unroll
@@ -540,12 +549,13 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
             for (int v = 0; v < V; ++v) {
                 const float x = hv[v];
                 const float ax = fabsf(x);
-                const float e = expf(-ax);
-                const float ope = 1.0f + e;
-                const float pq = e / (ope * ope);
-                const float g = (float)((CT)sc.gamma_d * ((CT)pq * (d[v] + (CT)x * (CT)sc.inv_beta_d)));
+                const float e = exp_neg(ax);
+                const float r = rcp_f(1.0f + e);
+                const float pmin = e * r;            // min(P, 1 - P)
+                const float pq = pmin * r;           // P (1 - P)
+                const float g = (float)((CT)sc.gamma_d * ((CT)pq * fma((CT)x, (CT)sc.inv_beta_d, d[v])));
                 gv[v] = g;
-                if constexpr (EN) eacc[V + v] += log1pf(e) + ax * (e / ope);
+                if constexpr (EN) eacc[V + v] += log1p_f(e) + ax * pmin;
                 const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
                 hv[v] = nh;
                 snew[v] = sat_encode(nh);
@@ -580,7 +590,7 @@ __global__ void init_q1_kernel(int kind, const float* __restrict__ h, int32_t R,
 {
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
         const float hv = h[(k / R) * srow + k % R];
-        float x[1] = {kind == KIND_MAXSAT ? sat_encode(hv) : tanhf(0.5f * hv)};
+        float x[1] = {kind == KIND_MAXSAT ? sat_encode(hv) : tanh_half(hv)};
         st_marg<MT, 1>(out + k, x);
     }
 }
@@ -609,8 +619,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_init_
             for (int s = 1; s < Q; ++s) mx = fmaxf(mx, hv[s]);
             float P[Q], Z = 0.0f;
 #pragma unroll
-            for (int s = 0; s < Q; ++s) { P[s] = expf(hv[s] - mx); Z += P[s]; }
-            const float invZ = 1.0f / Z;
+            for (int s = 0; s < Q; ++s) { P[s] = exp_neg(mx - hv[s]); Z += P[s]; }
+            const float invZ = rcp_f(Z);
 #pragma unroll
             for (int s = 0; s < Q; ++s) P[s] *= invZ;
             colsum_add<Q>(hv, cs, a.nw ? (double)a.nw[i] : 1.0);
@@ -826,9 +836,22 @@ __global__ void __launch_bounds__(1024) eval_graph_kernel(const int64_t* __restr
 #pragma unroll
                 for (int s = 0; s < Q; ++s) cnt[s] += (si == s) ? vi : 0;
             }
-            for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
-                const int2 e = adj[k];
-                if (sigma[(size_t)e.x * R + r] != si) acc[0] += (double)__int_as_float(e.y);
+            int64_t k = row_off[i];
+            const int64_t kend = row_off[i + 1];
+            // rounds of up to eight neighbours in flight, summed in CSR order
+            for (; k < kend; k += 8) {
+                const int nb = (int)min((int64_t)8, kend - k);
+                int2 e[8];
+                uint8_t sj[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < nb) e[u] = adj[k + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < nb) sj[u] = sigma[(size_t)e[u].x * R + r];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < nb && sj[u] != si) acc[0] += (double)__int_as_float(e[u].y);
             }
         }
     }

@@ -100,9 +100,9 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_manip
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const float x = hv[v];
-                const float e = expf(-fabsf(x));
-                const float ope = 1.0f + e;
-                const float pq = e / (ope * ope);   // P(1-P) without cancellation
+                const float e = exp_neg(fabsf(x));
+                const float r = rcp_f(1.0f + e);
+                const float pq = e * r * r;         // P(1-P) without cancellation
                 const float g = (float)(sc.gamma_d * ((double)pq * (c * acc[v] + (double)x * sc.inv_beta_d)));
                 gv[v] = g;
                 const float nh = adam_update(x, g, m1v[v], m2v[v], sc);
@@ -222,8 +222,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_manip
             for (int s = 1; s < Q; ++s) mx = fmaxf(mx, hv[s]);
             float P[Q], Z = 0.0f;
 #pragma unroll
-            for (int s = 0; s < Q; ++s) { P[s] = expf(hv[s] - mx); Z += P[s]; }
-            const float invZ = 1.0f / Z;
+            for (int s = 0; s < Q; ++s) { P[s] = exp_neg(mx - hv[s]); Z += P[s]; }
+            const float invZ = rcp_f(Z);
 #pragma unroll
             for (int s = 0; s < Q; ++s) P[s] *= invZ;
             // mean normalised by the sum of the float32 marginals (their
