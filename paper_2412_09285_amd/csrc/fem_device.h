@@ -258,11 +258,45 @@ __device__ __forceinline__ float adam_update(float x, float g, float& m1, float&
 // 2^-40 fixed point of a probability in [0, 1]
 __device__ __forceinline__ long long to_fixed(double p) { return (long long)rint(p * 1099511627776.0); }
 
-// Column-sum contributions of one replica's softmax, formed in double: the sum
-// over all nodes of float32 marginals would carry their rounding into the
+// rint(x) as an integer for 0 <= x < 2^51: x + 1.5 * 2^52 has a unit ulp, so
+// its low mantissa bits hold x rounded to the nearest integer (ties to even)
+__device__ __forceinline__ long long rint_small_i64(double x)
+{
+    return (long long)__double_as_longlong(x + 6755399441055744.0) - 0x4338000000000000LL;
+}
+
+// exp(d) in double for d <= 0, to about 1e-13 relative: t = d log2(e) =
+// k + f with k = rint(t), and e^(f ln 2), |f ln 2| <= 0.35, by its Taylor
+// polynomial to the 12th power (truncation below 1e-15); large |d| underflow
+// to 0 through the exponent
+__device__ __forceinline__ double exp_dp_neg(double d)
+{
+    const double t = d * 1.4426950408889634;
+    const double k = rint(t);
+    const double y = (t - k) * 0.6931471805599453;
+    double p = 1.0 / 479001600.0;   // 1/12!
+    p = fma(p, y, 1.0 / 39916800.0);
+    p = fma(p, y, 1.0 / 3628800.0);
+    p = fma(p, y, 1.0 / 362880.0);
+    p = fma(p, y, 1.0 / 40320.0);
+    p = fma(p, y, 1.0 / 5040.0);
+    p = fma(p, y, 1.0 / 720.0);
+    p = fma(p, y, 1.0 / 120.0);
+    p = fma(p, y, 1.0 / 24.0);
+    p = fma(p, y, 1.0 / 6.0);
+    p = fma(p, y, 0.5);
+    p = fma(p, y, 1.0);
+    p = fma(p, y, 1.0);
+    return ldexp(p, (int)fmax(k, -2000.0));
+}
+
+// The softmax of one replica's q fields in double: the float marginals P
+// (rounded from the double values) and their column-sum contributions in
+// 2^-40 fixed point, vw P per state (vw the node weight).  Double, because the
+// sum over all nodes of float32 marginals would carry their rounding into the
 // global balance term.
 template <int Q>
-__device__ __forceinline__ void colsum_add(const float (&h)[Q], long long (&cs)[Q], double vw = 1.0)
+__device__ __forceinline__ void softmax_colsum(const float (&h)[Q], long long (&cs)[Q], double vw, float (&P)[Q])
 {
     float mx = h[0];
 #pragma unroll
@@ -270,13 +304,20 @@ __device__ __forceinline__ void colsum_add(const float (&h)[Q], long long (&cs)[
     double e[Q], Z = 0.0;
 #pragma unroll
     for (int s = 0; s < Q; ++s) {
-        e[s] = exp((double)h[s] - (double)mx);
+        e[s] = exp_dp_neg((double)h[s] - (double)mx);
         Z += e[s];
     }
-    const double iz = vw / Z;   // node weight times the normaliser
+    const double iz = 1.0 / Z;
+    const bool unit = vw == 1.0;
 #pragma unroll
-    for (int s = 0; s < Q; ++s) cs[s] += to_fixed(e[s] * iz);
+    for (int s = 0; s < Q; ++s) {
+        const double p = e[s] * iz;
+        P[s] = (float)p;
+        // unit weights: p 2^40 < 2^51, the cheap rounding applies
+        cs[s] += unit ? rint_small_i64(p * 1099511627776.0) : to_fixed(vw * p);
+    }
 }
+
 
 // Max-k-SAT stored marginal: the smaller of P(x=1) and P(x=0), negative (sign
 // bit set) when P(x=1) > 1/2.  Both tails keep full relative precision.
@@ -292,6 +333,15 @@ __device__ __forceinline__ float sat_u(float s, bool pos)
     bool hi = signbit(s);
     float a = fabsf(s);
     return (pos == hi) ? a : 1.0f - a;
+}
+// the same with the polarity as a sign-bit mask (SAT_POS or 0): flipping the
+// stored sign for a positive literal leaves u = s' where s' >= +0, and
+// u = 1 + s' where the sign bit of s' is set
+__device__ __forceinline__ float sat_u_bits(float s, uint32_t pos_mask)
+{
+    const uint32_t b = __float_as_uint(s) ^ pos_mask;
+    const float sp = __uint_as_float(b);
+    return (b & 0x80000000u) ? 1.0f + sp : sp;
 }
 
 // Butterfly over the teams of one wave (lanes that hold the same replicas),

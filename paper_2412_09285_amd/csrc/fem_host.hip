@@ -1224,7 +1224,9 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
     if (e != hipSuccess) return bail(fail(FEM_E_HIP, "hipSetDevice: %s", hipGetErrorString(e)));
     const size_t msz = s->dtype == FEM_BF16 ? 2 : 4;
     // bytes of one marginal-copy buffer
+    // (Max-k-SAT: one row more, row n, read by unused literal slots)
     const size_t mbytes = s->dense_i8 ? 4 * (size_t)dense_rows_padded(s->R) * p.dense_ld
+                          : s->kind == KIND_MAXSAT ? (s->vals + s->R) * msz
                           : !s->manip ? s->vals * msz
                           : s->kind == KIND_MAXCUT ? (size_t)s->n * s->rw * 4 : (size_t)s->n * s->R;
     const size_t IR = (size_t)s->n_inst * s->R;
@@ -1259,6 +1261,13 @@ fem_status fem_solver_create(const fem_problem* fp, const fem_params* prm, void*
         if (e != hipSuccess) return bail(fail(FEM_E_NOMEM, "device allocation of the marginal copy: %s", hipGetErrorString(e)));
         // digit planes: padding rows and replicas are read and must stay zero
         if (s->dense_i8) e = hipMemset(s->marg[k], 0, mbytes);
+        // Max-k-SAT row n: -0.0 in every replica (the stored form of "false
+        // with probability 1" for a negative literal)
+        if (s->kind == KIND_MAXSAT) {
+            unsigned char* row = static_cast<unsigned char*>(s->marg[k]) + s->vals * msz;
+            e = msz == 4 ? hipMemsetD32(reinterpret_cast<hipDeviceptr_t>(row), 0x80000000u, (size_t)s->R)
+                         : hipMemsetD16(reinterpret_cast<hipDeviceptr_t>(row), 0x8000u, (size_t)s->R);
+        }
         if (e != hipSuccess) return bail(fail(FEM_E_HIP, "clearing the marginal copy: %s", hipGetErrorString(e)));
     }
     ALLOC(s->eraw, IR * s->NE);

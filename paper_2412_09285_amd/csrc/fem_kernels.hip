@@ -362,23 +362,15 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q), potts_min_w
             // Adam, then the softmax of the new fields
 #pragma unroll
             for (int s = 0; s < Q; ++s) hv[s] = adam_update(hv[s], gv[s], m1v[s], m2v[s], sc);
-            float mx2 = hv[0];
-#pragma unroll
-            for (int s = 1; s < Q; ++s) mx2 = fmaxf(mx2, hv[s]);
-            float Pn[Q], Z2 = 0.0f;
-#pragma unroll
-            for (int s = 0; s < Q; ++s) { Pn[s] = exp_neg(mx2 - hv[s]); Z2 += Pn[s]; }
-            const float invZ2 = rcp_f(Z2);
-#pragma unroll
-            for (int s = 0; s < Q; ++s) Pn[s] *= invZ2;
-            // column-sum contributions from a double-precision softmax (the
-            // rounding of float32 marginals, summed over all nodes, would
-            // carry into the balance term), whatever the copy's type
+            // the new softmax in double: the stored marginals and their
+            // column-sum contributions (the rounding of float32 marginals,
+            // summed over all nodes, would carry into the balance term)
             if constexpr (LA) {
 #pragma unroll
                 for (int s = 0; s < Q; ++s) cs[s] = 0;
             }
-            colsum_add<Q>(hv, cs, (double)vw);
+            float Pn[Q];
+            softmax_colsum<Q>(hv, cs, (double)vw, Pn);
             if constexpr (LA) {
 #pragma unroll
                 for (int s = 0; s < Q; ++s) cs_l[s * nthr + tid] += cs[s];
@@ -489,52 +481,53 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXSAT, V)) sat_step_ker
                 }
             };
             // the cavity product of one incidence from its gathered rows, added
-            // to d (and to the energy at the owner) in incidence order
+            // to d (and to the energy at the owner) in incidence order; no
+            // branches, so that a round's loads all issue before its waits
             auto combine = [&](const uint32_t (&lit)[W], bool own_pos, bool owner, const float (&x)[W][V]) {
                 float c[V];
 #pragma unroll
-                for (int v = 0; v < V; ++v) c[v] = 1.0f;
+                for (int v = 0; v < V; ++v) c[v] = sat_u_bits(x[0][v], lit[0] & SAT_POS);
 #pragma unroll
-                for (int s = 0; s < W; ++s) {
-                    if ((lit[s] & SAT_VAR_MASK) != SAT_NONE) {
-                        const bool pos = (lit[s] & SAT_POS) != 0;
+                for (int s = 1; s < W; ++s)
 #pragma unroll
-                        for (int v = 0; v < V; ++v) c[v] *= sat_u(x[s][v], pos);
-                    }
-                }
+                    for (int v = 0; v < V; ++v) c[v] *= sat_u_bits(x[s][v], lit[s] & SAT_POS);
+                const float sg = own_pos ? -1.0f : 1.0f;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    d[v] += own_pos ? -(CT)c[v] : (CT)c[v];
+                    d[v] += (CT)(sg * c[v]);
                     if constexpr (EN) {
-                        if (owner) {
-                            const float uo = (own_pos == own_hi[v]) ? own_small[v] : 1.0f - own_small[v];
-                            eacc[v] += uo * c[v];
-                        }
+                        const float uo = (own_pos == own_hi[v]) ? own_small[v] : 1.0f - own_small[v];
+                        eacc[v] += owner ? uo * c[v] : 0.0f;
                     }
                 }
             };
+            // an unused slot (SAT_NONE, a negative literal) reads row n, which
+            // holds -0.0: a literal that is false with probability 1
             auto gather = [&](const uint32_t (&lit)[W], float (&x)[W][V]) {
 #pragma unroll
                 for (int s = 0; s < W; ++s) {
-                    const uint32_t var = lit[s] & SAT_VAR_MASK;
-                    if (var != SAT_NONE) ld_marg<MT, V>(mc + (size_t)var * R + rb, x[s]);
+                    const uint32_t var = min(lit[s] & SAT_VAR_MASK, (uint32_t)a.n);
+                    ld_marg<MT, V>(mc + (size_t)var * R + rb, x[s]);
                 }
             };
             int64_t k = a.row_off[i];
             const int64_t kend = a.row_off[i + 1];
-            // two incidences per round: their records, then all their rows, are
+            // NI incidences per round: their records, then all their rows, are
             // in flight together
-            for (; k + 2 <= kend; k += 2) {
-                const Rec r0 = inc[k], r1 = inc[k + 1];
-                uint32_t l0[W], l1[W];
-                bool p0, o0, p1, o1;
-                decode(r0, l0, p0, o0);
-                decode(r1, l1, p1, o1);
-                float x0[W][V], x1[W][V];
-                gather(l0, x0);
-                gather(l1, x1);
-                combine(l0, p0, o0, x0);
-                combine(l1, p1, o1, x1);
+            constexpr int NI = V <= 2 ? 4 : 2;
+            for (; k + NI <= kend; k += NI) {
+                Rec rr[NI];
+                uint32_t l[NI][W];
+                bool po[NI], ow[NI];
+                float x[NI][W][V];
+#pragma unroll
+                for (int u = 0; u < NI; ++u) rr[u] = inc[k + u];
+#pragma unroll
+                for (int u = 0; u < NI; ++u) decode(rr[u], l[u], po[u], ow[u]);
+#pragma unroll
+                for (int u = 0; u < NI; ++u) gather(l[u], x[u]);
+#pragma unroll
+                for (int u = 0; u < NI; ++u) combine(l[u], po[u], ow[u], x[u]);
             }
             for (; k < kend; ++k) {
                 uint32_t l0[W];
@@ -614,16 +607,8 @@ __global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_init_
             const size_t sbase = (size_t)i * a.srow + (size_t)r * Q;   // h, m1, m2 rows
             float hv[Q];
             ld_f32<Q>(a.h + sbase, hv);
-            float mx = hv[0];
-#pragma unroll
-            for (int s = 1; s < Q; ++s) mx = fmaxf(mx, hv[s]);
-            float P[Q], Z = 0.0f;
-#pragma unroll
-            for (int s = 0; s < Q; ++s) { P[s] = exp_neg(mx - hv[s]); Z += P[s]; }
-            const float invZ = rcp_f(Z);
-#pragma unroll
-            for (int s = 0; s < Q; ++s) P[s] *= invZ;
-            colsum_add<Q>(hv, cs, a.nw ? (double)a.nw[i] : 1.0);
+            float P[Q];
+            softmax_colsum<Q>(hv, cs, a.nw ? (double)a.nw[i] : 1.0, P);
             st_marg<MT, Q>(mn + base, P);
         }
     }
