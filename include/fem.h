@@ -383,7 +383,14 @@ fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* batch, const floa
                                uint64_t seed, int32_t draw0, double lr, double* loss, float* grad_out);
 /* Proposal for R replicas: h_out[i][r] = alpha * z_i, z the logits of
  * replica r's fields state[i][r] with feature draw r; state and h_out are
- * [n][R] float32, both host or both device (they may not overlap). */
+ * [n][R] float32, both host or both device (they may not overlap).  All
+ * replicas go through one pass: the graph inputs and their aggregates are
+ * formed once, and layer 2 recomputes each neighbour's layer-1 activations
+ * for 32 replicas at a time on the matrix cores, with the activations split
+ * into three bfloat16 parts that sum to them exactly; the arithmetic is that
+ * of float32 up to summation order (fem_mpnn_forward's per-replica pass can
+ * differ from it by rounding).  Device work buffers of about 40 n R bytes are
+ * kept between calls. */
 fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* p, int32_t R, const float* state, uint64_t seed,
                           float alpha, float* h_out, int on_device);
 /* parameter file: 8-byte magic "FEMMPNN1", int32 9409, 9409 float32. */

@@ -335,44 +335,272 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) l
     }
 }
 
-// out[i][r] = alpha * z_i (column r of the [n][R] layout)
-__global__ void write_col_kernel(int32_t n, int32_t R, int32_t r, float alpha, const float* __restrict__ z,
-                                 float* __restrict__ out)
+// ------------------------------------------------- batched inference ----
+// Inference of all R replicas in one pass.  The per-replica forward above
+// gathers the 256-byte layer-1 rows of every neighbour, once per replica;
+// here the work is shared across the replicas of a node:
+//  * graph inputs (ln(1+deg), mean weight, 1/max(deg,1)) and their
+//    aggregates, once per call;
+//  * replica inputs r_f (tanh(s/2), clamp(s/4), three uniforms) and their
+//    aggregates a(r_f), stored feature-major [n][5][R];
+//  * layer 2 recomputes each neighbour's layer-1 activations from its 16
+//    inputs on the matrix cores instead of storing and gathering them.
+// A wave owns one node and 32 replicas (the N dimension of a 32 x 32 tile of
+// v_mfma_f32_32x32x16_bf16).  Operands: A = weights (bfloat16, exact), B =
+// activations split into three bfloat16 parts whose sum is the float value
+// exactly (each product is then exact and the tile sums in float32, so the
+// arithmetic is that of float32 up to summation order).  Lane l = 32 g + c
+// holds replica c; in a K block of 16 it supplies inputs 8 g .. 8 g + 7, and
+// of a 32 x 32 output tile t it holds units 32 t + 8 (v/4) + 4 g + v%4,
+// v = 0..15 (so the next layer's K order is permuted to match, and its
+// weights are laid out in that order: nothing is transposed).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+constexpr int NRF = 5;   // replica inputs per node
+
+__device__ __forceinline__ int out_unit(int t, int v, int g) { return 32 * t + 8 * (v >> 2) + 4 * g + (v & 3); }
+
+// x = hi + mid + lo exactly: truncation to 8 significant bits twice, the
+// rest (at most 8 bits) is a bfloat16 value; returned as 16-bit patterns
+__device__ __forceinline__ void split3(float x, uint32_t& h, uint32_t& m, uint32_t& l)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        out[(size_t)i * R + r] = alpha * z[i];
+    const uint32_t hu = __float_as_uint(x) & 0xffff0000u;
+    const float r = x - __uint_as_float(hu);
+    const uint32_t mu = __float_as_uint(r) & 0xffff0000u;
+    const float lo = r - __uint_as_float(mu);
+    h = hu >> 16;
+    m = mu >> 16;
+    l = __float_as_uint(lo) >> 16;
 }
 
-// dst[c][r] = src[r][c] for a rows x cols float matrix, 32 x 32 tiles through
-// LDS (both sides coalesced); workgroup b takes tile (b mod row tiles, b div
-// row tiles) of a one-dimensional grid
-__global__ void __launch_bounds__(256) transpose_kernel(const float* __restrict__ src, int64_t rows, int32_t cols,
-                                                        float* __restrict__ dst)
+// the three bfloat16 operands of eight float values
+__device__ __forceinline__ void split_operands(const float (&v)[8], bf16x8& bh, bf16x8& bm, bf16x8& bl)
 {
-    __shared__ float t[32][33];
-    const int64_t tiles_r = (rows + 31) / 32;
-    const int64_t r0 = ((int64_t)blockIdx.x % tiles_r) * 32;
-    const int c0 = (int)((int64_t)blockIdx.x / tiles_r) * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int k = ty; k < 32; k += 8) {
-        const int64_t r = r0 + k;
-        const int c = c0 + tx;
-        if (r < rows && c < cols) t[k][tx] = src[r * cols + c];
+    u32x4v H, M, L;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t h0, m0, l0, h1, m1, l1;
+        split3(v[2 * q], h0, m0, l0);
+        split3(v[2 * q + 1], h1, m1, l1);
+        H[q] = h0 | (h1 << 16);
+        M[q] = m0 | (m1 << 16);
+        L[q] = l0 | (l1 << 16);
+    }
+    bh = __builtin_bit_cast(bf16x8, H);
+    bm = __builtin_bit_cast(bf16x8, M);
+    bl = __builtin_bit_cast(bf16x8, L);
+}
+
+// graph inputs gf[i] = {ln(1+deg), mean incident weight (0 if isolated),
+// 1/max(deg,1), 0}, as the per-replica forward forms them
+__global__ void inf_graph_kernel(int32_t n, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
+                                 float4* __restrict__ gf)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int64_t b = row_off[i], e = row_off[i + 1];
+        float ws = 0.0f;
+        for (int64_t k = b; k < e; ++k) ws += __int_as_float(adj[k].y);
+        const float deg = (float)(e - b);
+        gf[i] = make_float4(log1pf(deg), e > b ? ws / deg : 0.0f, 1.0f / fmaxf(deg, 1.0f), 0.0f);
+    }
+}
+
+// their aggregates ga[i] = {a(1), a(ln(1+deg)), a(mean weight), 0}, each sum
+// in CSR order, then scaled by 1/max(deg,1)
+__global__ void inf_graph_agg_kernel(int32_t n, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
+                                     const float4* __restrict__ gf, float4* __restrict__ ga)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+        for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
+            const int2 e = adj[k];
+            const float w = __int_as_float(e.y);
+            const float4 q = gf[e.x];
+            a0 = fmaf(w, 1.0f, a0);
+            a1 = fmaf(w, q.x, a1);
+            a2 = fmaf(w, q.y, a2);
+        }
+        const float id = gf[i].z;
+        ga[i] = make_float4(a0 * id, a1 * id, a2 * id, 0.0f);
+    }
+}
+
+// replica inputs Xr[i][f][r] of the fields state[i][r] (draw r)
+__global__ void inf_feat_kernel(int32_t n, int32_t R, const float* __restrict__ state, uint32_t k0, uint32_t k1,
+                                float* __restrict__ Xr)
+{
+    const size_t count = (size_t)n * R;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / R), r = (int)(k % R);
+        const float sv = state[k];
+        const U4 w = philox((uint32_t)i, (uint32_t)r, 0u, 0u, k0, k1);
+        float* x = Xr + (size_t)i * NRF * R + r;
+        x[0] = tanhf(0.5f * sv);
+        x[R] = fminf(fmaxf(0.25f * sv, -2.0f), 2.0f);
+        x[2 * R] = upm1(w.x);
+        x[3 * R] = upm1(w.y);
+        x[4 * R] = upm1(w.z);
+    }
+}
+
+// their aggregates AXr[i][f][r], each sum in CSR order, then scaled
+__global__ void inf_agg_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
+                               const float4* __restrict__ gf, const float* __restrict__ Xr, float* __restrict__ AXr)
+{
+    const size_t count = (size_t)n * R;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / R), r = (int)(k % R);
+        float a[NRF] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (int64_t q = row_off[i]; q < row_off[i + 1]; ++q) {
+            const int2 e = adj[q];
+            const float w = __int_as_float(e.y);
+            const float* x = Xr + (size_t)e.x * NRF * R + r;
+#pragma unroll
+            for (int f = 0; f < NRF; ++f) a[f] = fmaf(w, x[(size_t)f * R], a[f]);
+        }
+        const float id = gf[i].z;
+        float* o = AXr + (size_t)i * NRF * R + r;
+#pragma unroll
+        for (int f = 0; f < NRF; ++f) o[(size_t)f * R] = a[f] * id;
+    }
+}
+
+// Layer 1 (recomputed per neighbour), layer 2 and the output, one wave per
+// (node, block of 32 replicas); h_out[i][r] = alpha z_i^r.
+__global__ void __launch_bounds__(256) inf_layer2_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off,
+                                                         const int2* __restrict__ adj, const float4* __restrict__ gf,
+                                                         const float4* __restrict__ ga, const float* __restrict__ Xr,
+                                                         const float* __restrict__ AXr, const uint16_t* __restrict__ w,
+                                                         float alpha, float* __restrict__ h_out)
+{
+    // A operands of the output layer: [k block][output tile][lane], eight
+    // bfloat16 weights each; k block kb = 4 src + 2 tt + half takes, in lane
+    // group g, slot q, input unit out_unit(tt, 8 half + q, g) of H1 (src 0,
+    // weights A2) or of a(H1) (src 1, weights B2)
+    __shared__ u32x4v sW2[8][2][64];
+    __shared__ float sB2[2][64][16], sC[2][64][16];   // b2 and c in the output layout of each lane
+    for (int t = threadIdx.x; t < 8 * 2 * 64; t += blockDim.x) {
+        const int kb = t >> 7, ot = (t >> 6) & 1, ln = t & 63;
+        const int src = kb >> 2, tt = (kb >> 1) & 1, half = kb & 1, gg = ln >> 5, m = 32 * ot + (ln & 31);
+        u32x4v v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int u0 = out_unit(tt, 8 * half + 2 * q, gg), u1 = out_unit(tt, 8 * half + 2 * q + 1, gg);
+            const int off = src ? OFF_B2 : OFF_A2;
+            v[q] = (uint32_t)w[off + u0 * HID + m] | ((uint32_t)w[off + u1 * HID + m] << 16);
+        }
+        sW2[kb][ot][ln] = v;
+    }
+    for (int t = threadIdx.x; t < 2 * 64 * 16; t += blockDim.x) {
+        const int ot = t >> 10, ln = (t >> 4) & 63, v = t & 15;
+        const int u = out_unit(ot, v, ln >> 5);
+        sB2[ot][ln][v] = bf(w[OFF_b2 + u]);
+        sC[ot][ln][v] = bf(w[OFF_c + u]);
     }
     __syncthreads();
-    for (int k = ty; k < 32; k += 8) {
-        const int c = c0 + k;
-        const int64_t r = r0 + tx;
-        if (r < rows && c < cols) dst[(int64_t)c * rows + r] = t[tx][k];
+    const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
+    // layer-1 A operands (tile t: units 32 t + c; inputs 8 g .. 8 g + 7, which
+    // are x for g = 0 and a(x) for g = 1) and the biases b1 in the output layout
+    bf16x8 aW1[2];
+    f32x16 bias1[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        u32x4v v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int off = g ? OFF_B1 : OFF_A1;
+            v[q] = (uint32_t)w[off + (2 * q) * HID + 32 * t + c] | ((uint32_t)w[off + (2 * q + 1) * HID + 32 * t + c] << 16);
+        }
+        aW1[t] = __builtin_bit_cast(bf16x8, v);
+#pragma unroll
+        for (int v2 = 0; v2 < 16; ++v2) bias1[t][v2] = bf(w[OFF_b1 + out_unit(t, v2, g)]);
     }
-}
-
-static hipError_t transpose(const float* src, int64_t rows, int32_t cols, float* dst)
-{
-    const int64_t tiles = ((rows + 31) / 32) * (((int64_t)cols + 31) / 32);
-    if (tiles < 1) return hipSuccess;
-    transpose_kernel<<<(unsigned)tiles, 256>>>(src, rows, cols, dst);
-    return hipGetLastError();
+    const float dd = bf(w[OFF_d]);
+    const float4* gp = g ? ga : gf;
+    const float* xp = g ? AXr : Xr;
+    const int nrb = (R + 31) / 32;
+    const int64_t items = (int64_t)n * nrb;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t it = wave; it < items; it += nw) {
+        const int i = (int)(it / nrb);
+        const int r = (int)(it % nrb) * 32 + c;
+        const bool ract = r < R;
+        // layer-1 pre-activations of node j for this lane's replica, bias included
+        auto pre1 = [&](int j, f32x16 (&acc)[2]) {
+            const float4 q = gp[j];
+            float v[8];
+            v[0] = g ? q.x : 1.0f;
+            v[1] = g ? q.y : q.x;
+            v[2] = g ? q.z : q.y;
+            const float* x = xp + (size_t)j * NRF * R + r;
+#pragma unroll
+            for (int f = 0; f < NRF; ++f) v[3 + f] = ract ? x[(size_t)f * R] : 0.0f;
+            bf16x8 bh, bm, bl;
+            split_operands(v, bh, bm, bl);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aW1[t], bh, bias1[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aW1[t], bm, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aW1[t], bl, acc[t], 0, 0, 0);
+            }
+        };
+        f32x16 h1[2], ag[2];
+        pre1(i, h1);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v2 = 0; v2 < 16; ++v2) {
+                h1[t][v2] = fmaxf(h1[t][v2], 0.0f);
+                ag[t][v2] = 0.0f;
+            }
+        for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
+            const int2 e = adj[k];
+            const float wij = __int_as_float(e.y);
+            f32x16 hj[2];
+            pre1(e.x, hj);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int v2 = 0; v2 < 16; ++v2) ag[t][v2] = fmaf(wij, fmaxf(hj[t][v2], 0.0f), ag[t][v2]);
+        }
+        const float id = gf[i].z;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v2 = 0; v2 < 16; ++v2) ag[t][v2] *= id;
+        // output layer: pre2 = [H1 | a(H1)] [A2; B2] + b2
+        f32x16 o[2];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+            for (int v2 = 0; v2 < 16; ++v2) o[ot][v2] = sB2[ot][lane][v2];
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+            const int src = kb >> 2, tt = (kb >> 1) & 1, half = kb & 1;
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = src ? ag[tt][8 * half + q] : h1[tt][8 * half + q];
+            bf16x8 bh, bm, bl;
+            split_operands(v, bh, bm, bl);
+#pragma unroll
+            for (int ot = 0; ot < 2; ++ot) {
+                const bf16x8 aw = __builtin_bit_cast(bf16x8, sW2[kb][ot][lane]);
+                o[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, bh, o[ot], 0, 0, 0);
+                o[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, bm, o[ot], 0, 0, 0);
+                o[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, bl, o[ot], 0, 0, 0);
+            }
+        }
+        // z = relu(pre2) c + d: this lane's 32 units, then its partner's
+        float zp = 0.0f;
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+            for (int v2 = 0; v2 < 16; ++v2) zp = fmaf(fmaxf(o[ot][v2], 0.0f), sC[ot][lane][v2], zp);
+        zp += __shfl_xor(zp, 32, 64);
+        if (g == 0 && ract) h_out[(size_t)i * R + r] = alpha * (zp + dd);
+    }
 }
 
 // ------------------------------------------------------------ training ----
@@ -623,7 +851,7 @@ struct fem_mpnn {
     float* state = nullptr;   // one replica's fields (training input)
     int32_t *y = nullptr, *inst_of = nullptr, *inst_off = nullptr;
     double* L = nullptr;
-    float* tbuf = nullptr;   // inference: replica-major copies of the fields and the proposal
+    float* tbuf = nullptr;   // inference: graph and replica inputs with their aggregates
     size_t tcap = 0;         // floats tbuf holds
 };
 
@@ -842,9 +1070,8 @@ fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, const f
     if (p.kind != KIND_MAXCUT) return mfail(FEM_E_UNSUPPORTED, "the warm-start network is for MaxCut problems");
     if (R < 1) return mfail(FEM_E_INVAL, "need R >= 1");
     MCHK(hipSetDevice(m->device));
-    fem_status s = ensure_work(m, (size_t)p.n, (size_t)p.n_inst);
-    if (s != FEM_OK) return s;
-    const size_t bytes = (size_t)p.n * R * 4;
+    const size_t n = (size_t)p.n, nR = n * (size_t)R;
+    const size_t bytes = nR * 4;
     const float* src = state;
     float* dst = h_out;
     float* tmp = nullptr;
@@ -856,47 +1083,41 @@ fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, const f
             return mfail(FEM_E_HIP, "copy of the state", e);
         }
         src = tmp;
-        dst = tmp + (size_t)p.n * R;
+        dst = tmp + nR;
     }
-    // replica-major copies: each forward reads its replica's fields, and
-    // writes its proposal, contiguously; one transposition each way
-    const size_t nR = (size_t)p.n * R;
-    float* tin = nullptr;
-    float* tout = nullptr;
-    if (R > 1) {
-        if (m->tcap < 2 * nR) {
-            mfree(m->tbuf);
-            m->tcap = 0;
-            hipError_t ea = hipMalloc(&m->tbuf, 2 * nR * 4);
-            if (ea != hipSuccess) {
-                m->tbuf = nullptr;
-                if (tmp) (void)hipFree(tmp);
-                return mfail(FEM_E_NOMEM, "device allocation of the replica-major copies", ea);
-            }
-            m->tcap = 2 * nR;
+    // work: graph inputs and their aggregates (float4 per node each), replica
+    // inputs and their aggregates (NRF x R floats per node each)
+    const size_t need = 8 * (n + 1) + 2 * NRF * nR;
+    if (m->tcap < need) {
+        mfree(m->tbuf);
+        m->tcap = 0;
+        hipError_t ea = hipMalloc(&m->tbuf, need * 4);
+        if (ea != hipSuccess) {
+            m->tbuf = nullptr;
+            if (tmp) (void)hipFree(tmp);
+            return mfail(FEM_E_NOMEM, "device allocation of the inference buffers", ea);
         }
-        tin = m->tbuf;
-        tout = m->tbuf + nR;
-        hipError_t et = transpose(src, p.n, R, tin);
-        if (et != hipSuccess) s = mfail(FEM_E_HIP, "transpose_kernel", et);
+        m->tcap = need;
     }
-    const int blocks = (int)std::min<int64_t>(((int64_t)p.n + 255) / 256, 65536);
-    for (int32_t r = 0; r < R && s == FEM_OK; ++r) {
-        if (R > 1) {
-            s = forward(m, p, tin + (size_t)r * p.n, 1, seed, r, false, nullptr, r > 0);
-            if (s != FEM_OK) break;
-            write_col_kernel<<<blocks > 0 ? blocks : 1, 256>>>(p.n, 1, 0, alpha, m->z, tout + (size_t)r * p.n);
-        } else {
-            s = forward(m, p, src, 1, seed, r, false, nullptr, false);
-            if (s != FEM_OK) break;
-            write_col_kernel<<<blocks > 0 ? blocks : 1, 256>>>(p.n, 1, 0, alpha, m->z, dst);
-        }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) s = mfail(FEM_E_HIP, "write_col_kernel", e);
-    }
-    if (s == FEM_OK && R > 1) {
-        hipError_t et = transpose(tout, R, p.n, dst);
-        if (et != hipSuccess) s = mfail(FEM_E_HIP, "transpose_kernel", et);
+    float4* gf = reinterpret_cast<float4*>(m->tbuf);
+    float4* ga = gf + (n + 1);
+    float* Xr = m->tbuf + 8 * (n + 1);
+    float* AXr = Xr + NRF * nR;
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    const unsigned gn = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    const unsigned gnr = (unsigned)std::min<size_t>((nR + 255) / 256, 65536);
+    fem_status s = FEM_OK;
+    (void)hipGetLastError();
+    if (n > 0) {
+        inf_graph_kernel<<<gn, 256>>>(p.n, p.row_off, p.adj, gf);
+        inf_graph_agg_kernel<<<gn, 256>>>(p.n, p.row_off, p.adj, gf, ga);
+        inf_feat_kernel<<<gnr, 256>>>(p.n, R, src, k0, k1, Xr);
+        inf_agg_kernel<<<gnr, 256>>>(p.n, R, p.row_off, p.adj, gf, Xr, AXr);
+        const int64_t items = (int64_t)n * ((R + 31) / 32);
+        const unsigned gl = (unsigned)std::min<int64_t>((items + 3) / 4, 8192);
+        inf_layer2_kernel<<<gl, 256>>>(p.n, R, p.row_off, p.adj, gf, ga, Xr, AXr, m->wbf, alpha, dst);
+        hipError_t el = hipGetLastError();
+        if (el != hipSuccess) s = mfail(FEM_E_HIP, "inference kernels", el);
     }
     hipError_t e = hipDeviceSynchronize();
     if (s == FEM_OK && e != hipSuccess) s = mfail(FEM_E_HIP, "fem_mpnn_infer", e);

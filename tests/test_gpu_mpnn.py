@@ -84,8 +84,42 @@ def test_save_load_and_infer_layout(tmp_path):
     st = state_of(batch.n, 3, R)
     h = other.infer(batch, st, seed=5, alpha=alpha)
     for r in range(R):
-        z = other.forward(batch, st[:, r], seed=5, draw=r)
-        assert np.array_equal(h[:, r], np.float32(alpha) * z)
+        zr = M.forward(ops, theta, st[:, r], 5, r)["z"]
+        err = np.abs(h[:, r] / alpha - zr).max() / np.abs(zr).max()
+        assert err <= 1e-5, (r, err)
+
+
+@pytest.mark.parametrize("R", [1, 32, 37])
+def test_batched_inference_matches_reference(R):
+    """All replicas in one pass (blocks of 32 replicas on the matrix cores,
+    a ragged last block at R = 37): every replica's proposal against the FP64
+    reference forward of that replica, 1e-5 of its largest logit."""
+    graphs, off, ops, batch = small_batch((260, 411))
+    theta = W.mpnn_init_weights(14)
+    net = fem.MPNN(theta)
+    st = state_of(batch.n, 11, R)
+    h = net.infer(batch, st, seed=77, alpha=1.0)
+    worst = 0.0
+    for r in range(R):
+        zr = M.forward(ops, theta, st[:, r], 77, r)["z"]
+        err = np.abs(h[:, r] - zr).max() / np.abs(zr).max()
+        worst = max(worst, err)
+    assert worst <= 1e-5, worst
+    print(f"[mpnn batched inference R={R}] max rel err {worst:.2e}", flush=True)
+
+
+def test_batched_inference_of_an_instance_does_not_depend_on_its_batch():
+    """Every (node, block of replicas) is formed from its own inputs in a
+    fixed order, so the first instance of a batch gets bit-identical
+    proposals alone and inside the batch."""
+    graphs, off, _, batch = small_batch((301, 517))
+    g = graphs[0]
+    alone = fem.Problem.maxcut(g.n, g.u, g.v, g.w)
+    net = fem.MPNN(W.mpnn_init_weights(22))
+    st = state_of(batch.n, 9, 40)
+    hb = net.infer(batch, st, seed=3, alpha=1.0)
+    ha = net.infer(alone, np.ascontiguousarray(st[:g.n]), seed=3, alpha=1.0)
+    assert np.array_equal(hb[:g.n], ha)
 
 
 def test_infer_on_device_tensors():
