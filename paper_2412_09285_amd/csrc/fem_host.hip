@@ -1315,8 +1315,10 @@ static hipError_t copy_state_rows(const fem_solver* s, float* dst, bool dst_stat
     const size_t sp = (size_t)s->srow * 4;
     const size_t n = (size_t)s->n;
     if (sp == w) return hipMemcpyAsync(dst, src, w * n, kd, s->stream);
-    if (kd == hipMemcpyDeviceToDevice)
-        return hipMemcpy2DAsync(dst, dst_state ? sp : w, src, dst_state ? w : sp, w, n, kd, s->stream);
+    if (kd == hipMemcpyDeviceToDevice) {
+        const int64_t rs = s->srow, rd = (int64_t)s->R * s->Q;
+        return launch_rows(s->n, rd, dst, dst_state ? rs : rd, src, dst_state ? rd : rs, nullptr, nullptr, s->stream);
+    }
     void* tmp = nullptr;
     hipError_t e = hipMalloc(&tmp, w * n);
     if (e != hipSuccess) return e;
@@ -1332,18 +1334,20 @@ static hipError_t copy_state_rows(const fem_solver* s, float* dst, bool dst_stat
     return e != hipSuccess ? e : e2;
 }
 
-static hipError_t zero_state_rows(const fem_solver* s, float* dst)
-{
-    return hipMemset2DAsync(dst, (size_t)s->srow * 4, 0, (size_t)s->R * s->Q * 4, (size_t)s->n, s->stream);
-}
 
 fem_status fem_set_fields(fem_solver* s, const float* h, int on_device)
 {
     if (!s || !h) return fail(FEM_E_INVAL, "NULL argument");
     HIPCHK(hipSetDevice(s->prob->device));
-    HIPCHK(copy_state_rows(s, s->h, true, h, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
-    HIPCHK(zero_state_rows(s, s->m1));
-    HIPCHK(zero_state_rows(s, s->m2));
+    // the fields, and zero Adam moments, in one pass over the state rows
+    // (host fields are copied first)
+    const int64_t rq = (int64_t)s->R * s->Q;
+    if (on_device) {
+        HIPCHK(launch_rows(s->n, rq, s->h, s->srow, h, rq, s->m1, s->m2, s->stream));
+    } else {
+        HIPCHK(copy_state_rows(s, s->h, true, h, hipMemcpyHostToDevice));
+        HIPCHK(launch_rows(s->n, rq, nullptr, s->srow, nullptr, rq, s->m1, s->m2, s->stream));
+    }
     s->t = 0;
     s->last_energy_step = -1;
     STCHK(init_marginals(s));

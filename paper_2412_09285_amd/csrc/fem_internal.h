@@ -75,11 +75,6 @@ __host__ __device__ constexpr int step_max_threads(int kind, int per_lane)
                                 : (per_lane >= 8 ? 512 : 1024);
 }
 
-// Waves per SIMD the bMinCut step kernel is compiled for: at q = 8 the
-// register budget of four waves (128 VGPRs) holds eight gathered rows in
-// flight with double field sums; other q take what the compiler chooses.
-__host__ __device__ constexpr int potts_min_waves(int q) { return q == 8 ? 4 : 1; }
-
 // bMinCut step kernel: per-lane running sums in LDS up to q = 16 (q + 3
 // doubles per thread); the block reduction reuses that space
 __host__ __device__ constexpr bool potts_lds_acc(int q) { return q <= 16; }
@@ -222,6 +217,10 @@ hipError_t launch_colsum_combine(int R, int q, int n_inst, const long long* fx, 
                                  double* ctil, hipStream_t st);
 hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* h, int64_t srow, uint8_t* sigma,
                         hipStream_t st);
+// n rows of w floats: dst[i ds + c] = src[i ss + c] (src not null), and zeros
+// into z1[i ds + c] and z2[i ds + c] (where not null)
+hipError_t launch_rows(int32_t n, int64_t w, float* dst, int64_t ds, const float* src, int64_t ss, float* z1,
+                       float* z2, hipStream_t st);
 hipError_t launch_transpose_sigma(int32_t n, int32_t R, const int32_t* sig_rn, uint8_t* sig_nr,
                                   hipStream_t st);
 hipError_t launch_eval(const Problem& p, const LaunchGeom& g, int waves, const Tile* tiles,

@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
 // in flight (at q = 8: 121 VGPRs, 4 waves per SIMD, instead of 164 and 3).
 // The sums are formed in the same order either way.
 template <int Q, typename MT, bool EN, bool NT>
-__global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q), potts_min_waves(Q)) potts_step_kernel(StepArgs a)
+__global__ void __launch_bounds__(step_max_threads(KIND_BMINCUT, Q)) potts_step_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blk_tile(a.seg_major)];
     const int seg = blk_seg(a.seg_major);
@@ -785,6 +785,26 @@ __global__ void round_kernel(int kind, int32_t n, int32_t R, int32_t q, const fl
     }
 }
 
+// Rows of w floats between arrays with row strides ds and ss (floats), and
+// zeros into z1 and z2 (row stride ds) where they are given; src null copies
+// nothing.  Four floats per lane when every stride, w and pointer allow it.
+template <typename V>
+__global__ void rows_kernel(int32_t n, int64_t w, float* __restrict__ dst, int64_t ds, const float* __restrict__ src,
+                            int64_t ss, float* __restrict__ z1, float* __restrict__ z2)
+{
+    constexpr int L = sizeof(V) / sizeof(float);
+    const int64_t wv = w / L;
+    const size_t count = (size_t)n * wv;
+    const V zero{};
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = k / wv, c = (k % wv) * L;
+        const size_t od = i * ds + c;
+        if (src) *reinterpret_cast<V*>(dst + od) = *reinterpret_cast<const V*>(src + i * ss + c);
+        if (z1) *reinterpret_cast<V*>(z1 + od) = zero;
+        if (z2) *reinterpret_cast<V*>(z2 + od) = zero;
+    }
+}
+
 // host [R][n] int32 -> device [n][R] uint8
 __global__ void transpose_sigma_kernel(int32_t n, int32_t R, const int32_t* __restrict__ in, uint8_t* __restrict__ out)
 {
@@ -851,6 +871,53 @@ __global__ void __launch_bounds__(1024) eval_graph_kernel(const int64_t* __restr
             if (rr < R) spart[((size_t)tile.slot * R + rr) * Q + s] = v;
         });
     }
+}
+
+// MaxCut with R a multiple of 4: the ordered cut sums of eval_graph_kernel<1>
+// for four replicas per lane, with one 32-bit load of their four sigma bytes
+// per neighbour.
+__global__ void __launch_bounds__(1024) eval_cut4_kernel(const int64_t* __restrict__ row_off,
+                                                        const int2* __restrict__ adj, const Tile* __restrict__ tiles,
+                                                        int32_t R, int lanes_log2, const uint8_t* __restrict__ sigma,
+                                                        double* __restrict__ vpart)
+{
+    const Tile tile = tiles[blockIdx.x];
+    const TeamIdx ti = team_idx(lanes_log2);
+    const int r0 = 4 * (blockIdx.y * ti.L + ti.tl);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (r0 < R) {
+        for (int i = tile.row_begin + ti.team; i < tile.row_end; i += ti.teams) {
+            const uint32_t si = *reinterpret_cast<const uint32_t*>(sigma + (size_t)i * R + r0);
+            int64_t k = row_off[i];
+            const int64_t kend = row_off[i + 1];
+            // rounds of up to eight neighbours in flight, summed in CSR order
+            for (; k < kend; k += 8) {
+                const int nb = (int)min((int64_t)8, kend - k);
+                int2 e[8];
+                uint32_t sj[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < nb) e[u] = adj[k + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < nb) sj[u] = *reinterpret_cast<const uint32_t*>(sigma + (size_t)e[u].x * R + r0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < nb) {
+                        const uint32_t d = si ^ sj[u];
+                        const double w = (double)__int_as_float(e[u].y);
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            if ((d >> (8 * b)) & 0xffu) acc[b] += w;
+                    }
+            }
+        }
+    }
+    extern __shared__ double lds_d[];
+    block_reduce_store<double, 4>(acc, ti, lanes_log2, lds_d, [&](int b, int l, double v) {
+        const int rr = 4 * (blockIdx.y * ti.L + l) + b;
+        if (rr < R) vpart[(size_t)tile.slot * R + rr] = v;
+    });
 }
 
 template <int W>
@@ -1108,6 +1175,20 @@ hipError_t launch_round(int kind, int32_t n, int32_t R, int32_t q, const float* 
     return hipGetLastError();
 }
 
+hipError_t launch_rows(int32_t n, int64_t w, float* dst, int64_t ds, const float* src, int64_t ss, float* z1,
+                       float* z2, hipStream_t st)
+{
+    (void)hipGetLastError();   // drop stale errors of earlier calls
+    const size_t count = (size_t)n * w;
+    if (count == 0) return hipSuccess;
+    auto al = [](const void* q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+    if (w % 4 == 0 && ds % 4 == 0 && ss % 4 == 0 && al(dst) && al(src) && al(z1) && al(z2))
+        rows_kernel<float4><<<grid_for(count / 4), 256, 0, st>>>(n, w, dst, ds, src, ss, z1, z2);
+    else
+        rows_kernel<float><<<grid_for(count), 256, 0, st>>>(n, w, dst, ds, src, ss, z1, z2);
+    return hipGetLastError();
+}
+
 hipError_t launch_transpose_sigma(int32_t n, int32_t R, const int32_t* sig_rn, uint8_t* sig_nr, hipStream_t st)
 {
     (void)hipGetLastError();   // drop stale errors of earlier calls
@@ -1131,6 +1212,12 @@ hipError_t launch_eval(const Problem& p, const LaunchGeom& geo, int waves, const
             eval_sat_kernel<2><<<g, b, lds, st>>>(p.row_off, (const void*)p.inc2, tiles, R, lanes_log2, sigma, vpart);
         else
             eval_sat_kernel<3><<<g, b, lds, st>>>(p.row_off, (const void*)p.inc4, tiles, R, lanes_log2, sigma, vpart);
+    } else if (p.kind == KIND_MAXCUT && R % 4 == 0 && (reinterpret_cast<uintptr_t>(sigma) & 3) == 0) {
+        const LaunchGeom g4 = make_geom(4, R, waves);
+        int l4 = 0;
+        while ((1 << l4) < g4.lanes) ++l4;
+        eval_cut4_kernel<<<dim3(geo.n_tiles, g4.nseg), b, lds_bytes(waves, g4.lanes, 4), st>>>(
+            p.row_off, p.adj, tiles, R, l4, sigma, vpart);
     } else if (p.kind == KIND_MAXCUT) {
         eval_graph_kernel<1><<<g, b, lds_bytes(waves, L, 1), st>>>(p.row_off, p.adj, nullptr, tiles, R, lanes_log2,
                                                                     sigma, vpart, spart);
