@@ -362,17 +362,18 @@ constexpr int NRF = 5;   // replica inputs per node
 __device__ __forceinline__ int out_unit(int t, int v, int g) { return 32 * t + 8 * (v >> 2) + 4 * g + (v & 3); }
 
 // x = hi + mid + lo exactly: truncation to 8 significant bits twice, the
-// rest (at most 8 bits) is a bfloat16 value; returned as 16-bit patterns
-__device__ __forceinline__ void split3(float x, uint32_t& h, uint32_t& m, uint32_t& l)
+// rest (at most 8 significant bits) is a bfloat16 value; the three parts are
+// the upper halves of x, r = x - hi and lo
+__device__ __forceinline__ void split3(float x, uint32_t& xh, uint32_t& rm, uint32_t& lo)
 {
-    const uint32_t hu = __float_as_uint(x) & 0xffff0000u;
-    const float r = x - __uint_as_float(hu);
-    const uint32_t mu = __float_as_uint(r) & 0xffff0000u;
-    const float lo = r - __uint_as_float(mu);
-    h = hu >> 16;
-    m = mu >> 16;
-    l = __float_as_uint(lo) >> 16;
+    const float r = x - __uint_as_float(__float_as_uint(x) & 0xffff0000u);
+    xh = __float_as_uint(x);
+    rm = __float_as_uint(r);
+    lo = __float_as_uint(r - __uint_as_float(rm & 0xffff0000u));
 }
+
+// the upper halves of a (low) and b (high) in one word
+__device__ __forceinline__ uint32_t pack_hi(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x07060302u); }
 
 // the three bfloat16 operands of eight float values
 __device__ __forceinline__ void split_operands(const float (&v)[8], bf16x8& bh, bf16x8& bm, bf16x8& bl)
@@ -383,59 +384,74 @@ __device__ __forceinline__ void split_operands(const float (&v)[8], bf16x8& bh, 
         uint32_t h0, m0, l0, h1, m1, l1;
         split3(v[2 * q], h0, m0, l0);
         split3(v[2 * q + 1], h1, m1, l1);
-        H[q] = h0 | (h1 << 16);
-        M[q] = m0 | (m1 << 16);
-        L[q] = l0 | (l1 << 16);
+        H[q] = pack_hi(h0, h1);
+        M[q] = pack_hi(m0, m1);
+        L[q] = pack_hi(l0, l1);
     }
     bh = __builtin_bit_cast(bf16x8, H);
     bm = __builtin_bit_cast(bf16x8, M);
     bl = __builtin_bit_cast(bf16x8, L);
 }
 
-// graph inputs gf[i] = {ln(1+deg), mean incident weight (0 if isolated),
-// 1/max(deg,1), 0}, as the per-replica forward forms them
+// max(x, 0) for finite x as one integer maximum (a negative float is a
+// negative integer); -0 gives +0
+__device__ __forceinline__ float relu_f(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+// The constant input 1 of the layer-1 products as stored: its three bfloat16
+// parts are 1, 2^-8 and 0, so the product of the middle parts can carry the
+// bias (weights 256 b1 times 2^-8, exact) and no operand needs patching.
+constexpr float ONE_B1 = 1.00390625f;
+
+// The inputs of node i sit side by side for the two lane groups of the
+// layer-1 products: G[2 i] = gf_i and G[2 i + 1] = ga_i; XA[2 i] and
+// XA[2 i + 1] (blocks of NRF R floats) hold Xr_i and AXr_i.
+
+// graph inputs gf[i] = G[2 i] = {ONE_B1, ln(1+deg), mean incident weight (0
+// if isolated), 1/max(deg,1)}, as the per-replica forward forms them; slot x
+// is the constant input 1 of lane group 0 in the layer-1 products, stored as
+// 1 + 2^-8 (see inf_layer2_kernel)
 __global__ void inf_graph_kernel(int32_t n, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
-                                 float4* __restrict__ gf)
+                                 float4* __restrict__ G)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int64_t b = row_off[i], e = row_off[i + 1];
         float ws = 0.0f;
         for (int64_t k = b; k < e; ++k) ws += __int_as_float(adj[k].y);
         const float deg = (float)(e - b);
-        gf[i] = make_float4(log1pf(deg), e > b ? ws / deg : 0.0f, 1.0f / fmaxf(deg, 1.0f), 0.0f);
+        G[2 * (size_t)i] = make_float4(ONE_B1, log1pf(deg), e > b ? ws / deg : 0.0f, 1.0f / fmaxf(deg, 1.0f));
     }
 }
 
-// their aggregates ga[i] = {a(1), a(ln(1+deg)), a(mean weight), 0}, each sum
-// in CSR order, then scaled by 1/max(deg,1)
+// their aggregates ga[i] = G[2 i + 1] = {a(1), a(ln(1+deg)), a(mean weight),
+// 0}, each sum in CSR order, then scaled by 1/max(deg,1)
 __global__ void inf_graph_agg_kernel(int32_t n, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
-                                     const float4* __restrict__ gf, float4* __restrict__ ga)
+                                     float4* __restrict__ G)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
         for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
             const int2 e = adj[k];
             const float w = __int_as_float(e.y);
-            const float4 q = gf[e.x];
+            const float4 q = G[2 * (size_t)e.x];
             a0 = fmaf(w, 1.0f, a0);
-            a1 = fmaf(w, q.x, a1);
-            a2 = fmaf(w, q.y, a2);
+            a1 = fmaf(w, q.y, a1);
+            a2 = fmaf(w, q.z, a2);
         }
-        const float id = gf[i].z;
-        ga[i] = make_float4(a0 * id, a1 * id, a2 * id, 0.0f);
+        const float id = G[2 * (size_t)i].w;
+        G[2 * (size_t)i + 1] = make_float4(a0 * id, a1 * id, a2 * id, 0.0f);
     }
 }
 
-// replica inputs Xr[i][f][r] of the fields state[i][r] (draw r)
+// replica inputs Xr_i[f][r] of the fields state[i][r] (draw r)
 __global__ void inf_feat_kernel(int32_t n, int32_t R, const float* __restrict__ state, uint32_t k0, uint32_t k1,
-                                float* __restrict__ Xr)
+                                float* __restrict__ XA)
 {
     const size_t count = (size_t)n * R;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(k / R), r = (int)(k % R);
         const float sv = state[k];
         const U4 w = philox((uint32_t)i, (uint32_t)r, 0u, 0u, k0, k1);
-        float* x = Xr + (size_t)i * NRF * R + r;
+        float* x = XA + 2 * (size_t)i * NRF * R + r;
         x[0] = tanhf(0.5f * sv);
         x[R] = fminf(fmaxf(0.25f * sv, -2.0f), 2.0f);
         x[2 * R] = upm1(w.x);
@@ -444,35 +460,66 @@ __global__ void inf_feat_kernel(int32_t n, int32_t R, const float* __restrict__ 
     }
 }
 
-// their aggregates AXr[i][f][r], each sum in CSR order, then scaled
+// their aggregates AXr_i[f][r], each sum in CSR order, then scaled
 __global__ void inf_agg_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
-                               const float4* __restrict__ gf, const float* __restrict__ Xr, float* __restrict__ AXr)
+                               const float4* __restrict__ G, float* __restrict__ XA)
 {
     const size_t count = (size_t)n * R;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(k / R), r = (int)(k % R);
         float a[NRF] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        for (int64_t q = row_off[i]; q < row_off[i + 1]; ++q) {
-            const int2 e = adj[q];
-            const float w = __int_as_float(e.y);
-            const float* x = Xr + (size_t)e.x * NRF * R + r;
+        int64_t q = row_off[i];
+        const int64_t qend = row_off[i + 1];
+        // rounds of up to four neighbours in flight, summed in CSR order
+        for (; q < qend; q += 4) {
+            const int nb = (int)min((int64_t)4, qend - q);
+            int2 e[4];
+            float xv[4][NRF];
 #pragma unroll
-            for (int f = 0; f < NRF; ++f) a[f] = fmaf(w, x[(size_t)f * R], a[f]);
+            for (int u = 0; u < 4; ++u)
+                if (u < nb) e[u] = adj[q + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < nb) {
+                    const float* x = XA + 2 * (size_t)e[u].x * NRF * R + r;
+#pragma unroll
+                    for (int f = 0; f < NRF; ++f) xv[u][f] = x[(size_t)f * R];
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < nb) {
+                    const float w = __int_as_float(e[u].y);
+#pragma unroll
+                    for (int f = 0; f < NRF; ++f) a[f] = fmaf(w, xv[u][f], a[f]);
+                }
         }
-        const float id = gf[i].z;
-        float* o = AXr + (size_t)i * NRF * R + r;
+        const float id = G[2 * (size_t)i].w;
+        float* o = XA + (2 * (size_t)i + 1) * NRF * R + r;
 #pragma unroll
         for (int f = 0; f < NRF; ++f) o[(size_t)f * R] = a[f] * id;
     }
 }
 
+#ifndef INF_NBUF
+#define INF_NBUF 4
+#endif
+
 // Layer 1 (recomputed per neighbour), layer 2 and the output, one wave per
 // (node, block of 32 replicas); h_out[i][r] = alpha z_i^r.
-__global__ void __launch_bounds__(256) inf_layer2_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off,
-                                                         const int2* __restrict__ adj, const float4* __restrict__ gf,
-                                                         const float4* __restrict__ ga, const float* __restrict__ Xr,
-                                                         const float* __restrict__ AXr, const uint16_t* __restrict__ w,
-                                                         float alpha, float* __restrict__ h_out)
+// Blocks go to the 8 XCDs in turn (block b to XCD b mod 8); the items are
+// cut into 8 contiguous ranges of about equal work, and XCD x's blocks take
+// range x, so that the neighbours one XCD gathers (nodes of the same
+// instances) stay in its own L2.
+constexpr int N_XCD = 8;
+struct XcdRanges {
+    int64_t b[N_XCD + 1];
+};
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
+inf_layer2_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
+                  const float4* __restrict__ G, const float* __restrict__ XA, const uint16_t* __restrict__ w,
+                  float alpha, XcdRanges xr,
+                  float* __restrict__ h_out)
 {
     // A operands of the output layer: [k block][output tile][lane], eight
     // bfloat16 weights each; k block kb = 4 src + 2 tt + half takes, in lane
@@ -502,8 +549,12 @@ __global__ void __launch_bounds__(256) inf_layer2_kernel(int32_t n, int32_t R, c
     const int lane = threadIdx.x & 63, c = lane & 31, g = lane >> 5;
     // layer-1 A operands (tile t: units 32 t + c; inputs 8 g .. 8 g + 7, which
     // are x for g = 0 and a(x) for g = 1) and the biases b1 in the output layout
-    bf16x8 aW1[2];
-    f32x16 bias1[2];
+    // The bias enters through the product of the middle parts: input 0 of
+    // lane group 0 is the constant 1, stored as ONE_B1 = 1 + 2^-8, whose parts
+    // are 1, 2^-8 and 0; that product takes the weights 256 b1 in place of
+    // A1[0] (b1 is a bfloat16 value, so 256 b1 is one too and the product
+    // 256 b1 2^-8 = b1 is exact), so the accumulator needs no bias registers.
+    bf16x8 aW1[2], aW1m[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         u32x4v v;
@@ -513,63 +564,137 @@ __global__ void __launch_bounds__(256) inf_layer2_kernel(int32_t n, int32_t R, c
             v[q] = (uint32_t)w[off + (2 * q) * HID + 32 * t + c] | ((uint32_t)w[off + (2 * q + 1) * HID + 32 * t + c] << 16);
         }
         aW1[t] = __builtin_bit_cast(bf16x8, v);
-#pragma unroll
-        for (int v2 = 0; v2 < 16; ++v2) bias1[t][v2] = bf(w[OFF_b1 + out_unit(t, v2, g)]);
+        if (g == 0) {
+            const uint32_t b256 = __float_as_uint(bf(w[OFF_b1 + 32 * t + c]) * 256.0f) >> 16;
+            v[0] = b256 | (v[0] & 0xffff0000u);
+        }
+        aW1m[t] = __builtin_bit_cast(bf16x8, v);
     }
     const float dd = bf(w[OFF_d]);
-    const float4* gp = g ? ga : gf;
-    const float* xp = g ? AXr : Xr;
     const int nrb = (R + 31) / 32;
-    const int64_t items = (int64_t)n * nrb;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t it = wave; it < items; it += nw) {
+    // this XCD's range and the wave's place among the XCD's waves, stated
+    // uniform so that node and neighbour indices live in scalar registers
+    // and the branches on them are scalar
+    const int x = (int)(blockIdx.x % N_XCD);
+    const int wpb = (int)(blockDim.x >> 6);
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x / N_XCD) * wpb + (threadIdx.x >> 6)));
+    const int64_t nw = (int64_t)((gridDim.x - x + N_XCD - 1) / N_XCD) * wpb;
+    const int64_t it_end = xr.b[x + 1];
+    for (int64_t it = xr.b[x] + wave; it < it_end; it += nw) {
+        // the output layer's weights, b2 and c are read from LDS where they
+        // are used, not held in registers across the loop (they would cost
+        // 128 registers per lane and the occupancy)
+        asm volatile("" ::: "memory");
         const int i = (int)(it / nrb);
         const int r = (int)(it % nrb) * 32 + c;
         const bool ract = r < R;
-        // layer-1 pre-activations of node j for this lane's replica, bias included
-        auto pre1 = [&](int j, f32x16 (&acc)[2]) {
-            const float4 q = gp[j];
-            float v[8];
-            v[0] = g ? q.x : 1.0f;
-            v[1] = g ? q.y : q.x;
-            v[2] = g ? q.z : q.y;
-            const float* x = xp + (size_t)j * NRF * R + r;
+        // the 8 inputs this lane supplies for node j, and the layer-1
+        // pre-activations (bias included) from them
+        // The raw loads of node j's inputs for this lane (a lane past R reads
+        // replica 0); assemble() forms the 8 operand values where they are
+        // used, so that no instruction needs a load's result early and the
+        // loads of later neighbours stay in flight.
+        struct In {
+            float4 q;
+            float x[NRF];
+        };
+        const int rl = ract ? r : 0;
+        const int lane_off = g * NRF * R + rl;
+        auto inputs = [&](int j, In& in) {
+            // node j's block (uniform) plus this lane's offset in it
+            in.q = G[2 * (size_t)j + g];
+            const float* x = XA + 2 * (size_t)j * NRF * R + lane_off;
 #pragma unroll
-            for (int f = 0; f < NRF; ++f) v[3 + f] = ract ? x[(size_t)f * R] : 0.0f;
+            for (int f = 0; f < NRF; ++f) in.x[f] = x[(size_t)f * R];
+        };
+        // (lanes past R compute a column of their own from replica 0's
+        // inputs and store nothing)
+        auto assemble = [&](const In& in, float (&v)[8]) {
+            v[0] = in.q.x;
+            v[1] = in.q.y;
+            v[2] = in.q.z;
+#pragma unroll
+            for (int f = 0; f < NRF; ++f) v[3 + f] = in.x[f];
+        };
+        auto pre1 = [&](const float (&v)[8], f32x16 (&acc)[2]) {
             bf16x8 bh, bm, bl;
             split_operands(v, bh, bm, bl);
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aW1[t], bh, bias1[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aW1[t], bm, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aW1[t], bh, f32x16{}, 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aW1m[t], bm, acc[t], 0, 0, 0);
                 acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aW1[t], bl, acc[t], 0, 0, 0);
             }
         };
-        f32x16 h1[2], ag[2];
-        pre1(i, h1);
+        f32x16 ag[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int v2 = 0; v2 < 16; ++v2) {
-                h1[t][v2] = fmaxf(h1[t][v2], 0.0f);
-                ag[t][v2] = 0.0f;
+            for (int v2 = 0; v2 < 16; ++v2) ag[t][v2] = 0.0f;
+        // Neighbours in CSR order, in chunks of up to 64: one load gives the
+        // chunk's entries (one per lane) and readlane hands them out, so no
+        // load waits on another.  NBUF input buffers in a fixed rotation (the
+        // loop is unrolled by NBUF, so no register is copied): while
+        // neighbour u's products run, the inputs of the next NBUF - 1
+        // neighbours are in flight.  Reads past the chunk's end repeat its
+        // last entry (in bounds, and skipped by a uniform branch).
+        constexpr int NBUF = INF_NBUF;
+        const int64_t kb = row_off[i], ke = row_off[i + 1];
+        for (int64_t c0 = kb; c0 < ke; c0 += 64) {
+            const int cnt = (int)min((int64_t)64, ke - c0);
+            const int2 me = adj[c0 + min(lane, cnt - 1)];
+            auto col = [&](int u) { return __builtin_amdgcn_readlane(me.x, min(u, cnt - 1)); };
+            auto wgt = [&](int u) { return __int_as_float(__builtin_amdgcn_readlane(me.y, u)); };
+            auto accumulate = [&](const In& in, float wij) {
+                float v[8];
+                assemble(in, v);
+                f32x16 hj[2];
+                pre1(v, hj);
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int v2 = 0; v2 < 16; ++v2) ag[t][v2] = fmaf(wij, relu_f(hj[t][v2]), ag[t][v2]);
+            };
+            In buf[NBUF];
+            // issued in the order the loop consumes them (the barriers keep
+            // the scheduler from reordering), so each use waits only on the
+            // oldest loads
+#pragma unroll
+            for (int b = 0; b < NBUF; ++b) {
+                inputs(col(b), buf[b]);
+                asm volatile("" ::: "memory");
             }
-        for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
-            const int2 e = adj[k];
-            const float wij = __int_as_float(e.y);
-            f32x16 hj[2];
-            pre1(e.x, hj);
+            for (int u = 0; u < cnt; u += NBUF) {
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int v2 = 0; v2 < 16; ++v2) ag[t][v2] = fmaf(wij, fmaxf(hj[t][v2], 0.0f), ag[t][v2]);
+                for (int b = 0; b < NBUF; ++b) {
+                    if (u + b < cnt) accumulate(buf[b], wgt(u + b));
+                    inputs(col(u + NBUF + b), buf[b]);
+                }
+                // keeps the compiler from turning the loads carried into the
+                // next iteration into loads at its top (which would wait on
+                // them at once)
+                asm volatile("" ::: "memory");
+            }
         }
-        const float id = gf[i].z;
+        const float id = G[2 * (size_t)i].w;
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v2 = 0; v2 < 16; ++v2) ag[t][v2] *= id;
+        // the node's own layer-1 activations, formed after the loop so that
+        // they do not hold registers during it
+        f32x16 h1[2];
+        {
+            In in;
+            inputs(i, in);
+            float v[8];
+            assemble(in, v);
+            pre1(v, h1);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v2 = 0; v2 < 16; ++v2) h1[t][v2] = relu_f(h1[t][v2]);
         // output layer: pre2 = [H1 | a(H1)] [A2; B2] + b2
         f32x16 o[2];
 #pragma unroll
@@ -597,7 +722,7 @@ __global__ void __launch_bounds__(256) inf_layer2_kernel(int32_t n, int32_t R, c
 #pragma unroll
         for (int ot = 0; ot < 2; ++ot)
 #pragma unroll
-            for (int v2 = 0; v2 < 16; ++v2) zp = fmaf(fmaxf(o[ot][v2], 0.0f), sC[ot][lane][v2], zp);
+            for (int v2 = 0; v2 < 16; ++v2) zp = fmaf(relu_f(o[ot][v2]), sC[ot][lane][v2], zp);
         zp += __shfl_xor(zp, 32, 64);
         if (g == 0 && ract) h_out[(size_t)i * R + r] = alpha * (zp + dd);
     }
@@ -1099,23 +1224,35 @@ fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, const f
         }
         m->tcap = need;
     }
-    float4* gf = reinterpret_cast<float4*>(m->tbuf);
-    float4* ga = gf + (n + 1);
-    float* Xr = m->tbuf + 8 * (n + 1);
-    float* AXr = Xr + NRF * nR;
+    float4* G = reinterpret_cast<float4*>(m->tbuf);
+    float* XA = m->tbuf + 8 * (n + 1);
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     const unsigned gn = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
     const unsigned gnr = (unsigned)std::min<size_t>((nR + 255) / 256, 65536);
     fem_status s = FEM_OK;
     (void)hipGetLastError();
     if (n > 0) {
-        inf_graph_kernel<<<gn, 256>>>(p.n, p.row_off, p.adj, gf);
-        inf_graph_agg_kernel<<<gn, 256>>>(p.n, p.row_off, p.adj, gf, ga);
-        inf_feat_kernel<<<gnr, 256>>>(p.n, R, src, k0, k1, Xr);
-        inf_agg_kernel<<<gnr, 256>>>(p.n, R, p.row_off, p.adj, gf, Xr, AXr);
-        const int64_t items = (int64_t)n * ((R + 31) / 32);
-        const unsigned gl = (unsigned)std::min<int64_t>((items + 3) / 4, 8192);
-        inf_layer2_kernel<<<gl, 256>>>(p.n, R, p.row_off, p.adj, gf, ga, Xr, AXr, m->wbf, alpha, dst);
+        inf_graph_kernel<<<gn, 256>>>(p.n, p.row_off, p.adj, G);
+        inf_graph_agg_kernel<<<gn, 256>>>(p.n, p.row_off, p.adj, G);
+        inf_feat_kernel<<<gnr, 256>>>(p.n, R, src, k0, k1, XA);
+        inf_agg_kernel<<<gnr, 256>>>(p.n, R, p.row_off, p.adj, G, XA);
+        // XCD ranges of about equal work: a node costs about as much as
+        // NODE_COST neighbours (its output layer)
+        const int nrb = (R + 31) / 32;
+        const int64_t items = (int64_t)n * nrb;
+        constexpr int64_t NODE_COST = 5;
+        const int64_t total = p.h_row_off[n] + NODE_COST * (int64_t)n;
+        XcdRanges xr;
+        xr.b[0] = 0;
+        int32_t lo = 0;
+        for (int x = 1; x < N_XCD; ++x) {
+            const int64_t want = total * x / N_XCD;
+            while (lo < n && p.h_row_off[lo] + NODE_COST * (int64_t)lo < want) ++lo;
+            xr.b[x] = (int64_t)lo * nrb;
+        }
+        xr.b[N_XCD] = items;
+        const unsigned gl = (unsigned)std::min<int64_t>(((items + 3) / 4 + N_XCD - 1) / N_XCD * N_XCD, 8192);
+        inf_layer2_kernel<<<gl, 256>>>(p.n, R, p.row_off, p.adj, G, XA, m->wbf, alpha, xr, dst);
         hipError_t el = hipGetLastError();
         if (el != hipSuccess) s = mfail(FEM_E_HIP, "inference kernels", el);
     }
