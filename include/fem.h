@@ -393,6 +393,15 @@ fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* batch, const floa
  * kept between calls. */
 fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* p, int32_t R, const float* state, uint64_t seed,
                           float alpha, float* h_out, int on_device);
+/* fem_mpnn_infer for device arrays, enqueued on the HIP stream `stream`
+ * (NULL: the null stream) without waiting for it: the proposal is ready when
+ * work queued after it on that stream runs, and execution errors show at the
+ * caller's next synchronisation.  The work buffers belong to the network
+ * object, so calls on one object must be ordered (one stream, or events);
+ * calls that overlap on different streams race.  A call that has to grow
+ * the buffers frees the old ones, which waits for the device. */
+fem_status fem_mpnn_infer_async(fem_mpnn* m, const fem_problem* p, int32_t R, const float* state, uint64_t seed,
+                                float alpha, float* h_out, void* stream);
 /* parameter file: 8-byte magic "FEMMPNN1", int32 9409, 9409 float32. */
 fem_status fem_mpnn_save(fem_mpnn* m, const char* path);
 fem_status fem_mpnn_load(fem_mpnn* m, const char* path);

@@ -203,9 +203,8 @@ def warm(b: Batch, plain, T_plain, K, stream, t_early, T_warm, beta_start, net=N
         s1.fields(out=h_mid)
         if net is None:
             return h_mid
-        # the network runs on the null stream: order it after the solver's
-        torch.cuda.current_stream().wait_stream(stream)
-        net.infer(b.union, h_mid, seed=seed, alpha=alpha, out=h_prop)
+        # queued on the solvers' stream after the fields copy, no host wait
+        net.infer(b.union, h_mid, seed=seed, alpha=alpha, out=h_prop, stream=stream)
         return h_prop
 
     s1.set_fields(b.h0)

@@ -1187,15 +1187,73 @@ fem_status fem_mpnn_train_step(fem_mpnn* m, const fem_problem* fp, const float* 
     return FEM_OK;
 }
 
+// The inference kernels for device state src and proposal dst, enqueued on
+// st (the work buffer grows first if it has to; hipFree waits for the device).
+static fem_status infer_enqueue(fem_mpnn* m, const Problem& p, int32_t R, const float* src, uint64_t seed,
+                                float alpha, float* dst, hipStream_t st)
+{
+    const size_t n = (size_t)p.n, nR = n * (size_t)R;
+    // work: graph inputs and their aggregates (float4 per node each), replica
+    // inputs and their aggregates (NRF x R floats per node each)
+    const size_t need = 8 * (n + 1) + 2 * NRF * nR;
+    if (m->tcap < need) {
+        mfree(m->tbuf);
+        m->tcap = 0;
+        hipError_t ea = hipMalloc(&m->tbuf, need * 4);
+        if (ea != hipSuccess) {
+            m->tbuf = nullptr;
+            return mfail(FEM_E_NOMEM, "device allocation of the inference buffers", ea);
+        }
+        m->tcap = need;
+    }
+    if (n == 0) return FEM_OK;
+    float4* G = reinterpret_cast<float4*>(m->tbuf);
+    float* XA = m->tbuf + 8 * (n + 1);
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    const unsigned gn = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    const unsigned gnr = (unsigned)std::min<size_t>((nR + 255) / 256, 65536);
+    (void)hipGetLastError();
+    inf_graph_kernel<<<gn, 256, 0, st>>>(p.n, p.row_off, p.adj, G);
+    inf_graph_agg_kernel<<<gn, 256, 0, st>>>(p.n, p.row_off, p.adj, G);
+    inf_feat_kernel<<<gnr, 256, 0, st>>>(p.n, R, src, k0, k1, XA);
+    inf_agg_kernel<<<gnr, 256, 0, st>>>(p.n, R, p.row_off, p.adj, G, XA);
+    // XCD ranges of about equal work: a node costs about as much as
+    // NODE_COST neighbours (its output layer)
+    const int nrb = (R + 31) / 32;
+    const int64_t items = (int64_t)n * nrb;
+    constexpr int64_t NODE_COST = 5;
+    const int64_t total = p.h_row_off[n] + NODE_COST * (int64_t)n;
+    XcdRanges xr;
+    xr.b[0] = 0;
+    int32_t lo = 0;
+    for (int x = 1; x < N_XCD; ++x) {
+        const int64_t want = total * x / N_XCD;
+        while ((size_t)lo < n && p.h_row_off[lo] + NODE_COST * (int64_t)lo < want) ++lo;
+        xr.b[x] = (int64_t)lo * nrb;
+    }
+    xr.b[N_XCD] = items;
+    const unsigned gl = (unsigned)std::min<int64_t>(((items + 3) / 4 + N_XCD - 1) / N_XCD * N_XCD, 8192);
+    inf_layer2_kernel<<<gl, 256, 0, st>>>(p.n, R, p.row_off, p.adj, G, XA, m->wbf, alpha, xr, dst);
+    hipError_t el = hipGetLastError();
+    if (el != hipSuccess) return mfail(FEM_E_HIP, "inference kernels", el);
+    return FEM_OK;
+}
+
+static fem_status infer_check(fem_mpnn* m, const fem_problem* fp, int32_t R)
+{
+    if (fp->p.kind != KIND_MAXCUT) return mfail(FEM_E_UNSUPPORTED, "the warm-start network is for MaxCut problems");
+    if (R < 1) return mfail(FEM_E_INVAL, "need R >= 1");
+    MCHK(hipSetDevice(m->device));
+    return FEM_OK;
+}
+
 fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, const float* state, uint64_t seed,
                           float alpha, float* h_out, int on_device)
 {
     if (!m || !fp || !state || !h_out) return mfail(FEM_E_INVAL, "NULL argument");
-    const Problem& p = fp->p;
-    if (p.kind != KIND_MAXCUT) return mfail(FEM_E_UNSUPPORTED, "the warm-start network is for MaxCut problems");
-    if (R < 1) return mfail(FEM_E_INVAL, "need R >= 1");
-    MCHK(hipSetDevice(m->device));
-    const size_t n = (size_t)p.n, nR = n * (size_t)R;
+    fem_status s = infer_check(m, fp, R);
+    if (s != FEM_OK) return s;
+    const size_t nR = (size_t)fp->p.n * (size_t)R;
     const size_t bytes = nR * 4;
     const float* src = state;
     float* dst = h_out;
@@ -1210,52 +1268,7 @@ fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, const f
         src = tmp;
         dst = tmp + nR;
     }
-    // work: graph inputs and their aggregates (float4 per node each), replica
-    // inputs and their aggregates (NRF x R floats per node each)
-    const size_t need = 8 * (n + 1) + 2 * NRF * nR;
-    if (m->tcap < need) {
-        mfree(m->tbuf);
-        m->tcap = 0;
-        hipError_t ea = hipMalloc(&m->tbuf, need * 4);
-        if (ea != hipSuccess) {
-            m->tbuf = nullptr;
-            if (tmp) (void)hipFree(tmp);
-            return mfail(FEM_E_NOMEM, "device allocation of the inference buffers", ea);
-        }
-        m->tcap = need;
-    }
-    float4* G = reinterpret_cast<float4*>(m->tbuf);
-    float* XA = m->tbuf + 8 * (n + 1);
-    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
-    const unsigned gn = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
-    const unsigned gnr = (unsigned)std::min<size_t>((nR + 255) / 256, 65536);
-    fem_status s = FEM_OK;
-    (void)hipGetLastError();
-    if (n > 0) {
-        inf_graph_kernel<<<gn, 256>>>(p.n, p.row_off, p.adj, G);
-        inf_graph_agg_kernel<<<gn, 256>>>(p.n, p.row_off, p.adj, G);
-        inf_feat_kernel<<<gnr, 256>>>(p.n, R, src, k0, k1, XA);
-        inf_agg_kernel<<<gnr, 256>>>(p.n, R, p.row_off, p.adj, G, XA);
-        // XCD ranges of about equal work: a node costs about as much as
-        // NODE_COST neighbours (its output layer)
-        const int nrb = (R + 31) / 32;
-        const int64_t items = (int64_t)n * nrb;
-        constexpr int64_t NODE_COST = 5;
-        const int64_t total = p.h_row_off[n] + NODE_COST * (int64_t)n;
-        XcdRanges xr;
-        xr.b[0] = 0;
-        int32_t lo = 0;
-        for (int x = 1; x < N_XCD; ++x) {
-            const int64_t want = total * x / N_XCD;
-            while (lo < n && p.h_row_off[lo] + NODE_COST * (int64_t)lo < want) ++lo;
-            xr.b[x] = (int64_t)lo * nrb;
-        }
-        xr.b[N_XCD] = items;
-        const unsigned gl = (unsigned)std::min<int64_t>(((items + 3) / 4 + N_XCD - 1) / N_XCD * N_XCD, 8192);
-        inf_layer2_kernel<<<gl, 256>>>(p.n, R, p.row_off, p.adj, G, XA, m->wbf, alpha, xr, dst);
-        hipError_t el = hipGetLastError();
-        if (el != hipSuccess) s = mfail(FEM_E_HIP, "inference kernels", el);
-    }
+    s = infer_enqueue(m, fp->p, R, src, seed, alpha, dst, nullptr);
     hipError_t e = hipDeviceSynchronize();
     if (s == FEM_OK && e != hipSuccess) s = mfail(FEM_E_HIP, "fem_mpnn_infer", e);
     if (tmp) {
@@ -1266,6 +1279,15 @@ fem_status fem_mpnn_infer(fem_mpnn* m, const fem_problem* fp, int32_t R, const f
         (void)hipFree(tmp);
     }
     return s;
+}
+
+fem_status fem_mpnn_infer_async(fem_mpnn* m, const fem_problem* fp, int32_t R, const float* state, uint64_t seed,
+                                float alpha, float* h_out, void* stream)
+{
+    if (!m || !fp || !state || !h_out) return mfail(FEM_E_INVAL, "NULL argument");
+    fem_status s = infer_check(m, fp, R);
+    if (s != FEM_OK) return s;
+    return infer_enqueue(m, fp->p, R, state, seed, alpha, h_out, static_cast<hipStream_t>(stream));
 }
 
 fem_status fem_mpnn_save(fem_mpnn* m, const char* path)

@@ -108,6 +108,7 @@ _SIGS = {
     "fem_mpnn_forward": (C.c_int, [_P, _P, _P, C.c_uint64, C.c_int32, _P, C.c_int]),
     "fem_mpnn_train_step": (C.c_int, [_P, _P, _P, _P, C.c_uint64, C.c_int32, C.c_double, _P, _P]),
     "fem_mpnn_infer": (C.c_int, [_P, _P, C.c_int32, _P, C.c_uint64, C.c_float, _P, C.c_int]),
+    "fem_mpnn_infer_async": (C.c_int, [_P, _P, C.c_int32, _P, C.c_uint64, C.c_float, _P, _P]),
     "fem_mpnn_save": (C.c_int, [_P, C.c_char_p]),
     "fem_mpnn_load": (C.c_int, [_P, C.c_char_p]),
     "fem_profile": (C.c_int, [_P, C.c_int32]),
@@ -501,16 +502,23 @@ class MPNN:
                                          None if g is None else g.ctypes.data_as(C.c_void_p)))
         return (loss.value, g) if want_grad else loss.value
 
-    def infer(self, problem: Problem, state, seed: int, alpha: float, out=None):
+    def infer(self, problem: Problem, state, seed: int, alpha: float, out=None, stream=None):
         """Proposal alpha * z for every replica of state [n][R] (host array,
-        or a device tensor together with a device tensor `out`)."""
+        or a device tensor together with a device tensor `out`).  With a
+        torch stream (device tensors only) the work is queued on it and the
+        call returns without waiting."""
         if _is_torch(state) and state.is_cuda:
             assert out is not None and _is_torch(out) and out.is_cuda
             assert state.is_contiguous() and out.is_contiguous() and state.dtype == out.dtype
             R = state.shape[1]
-            _check(lib().fem_mpnn_infer(self._h, problem._h, R, C.c_void_p(state.data_ptr()), seed, alpha,
-                                        C.c_void_p(out.data_ptr()), 1))
+            if stream is not None:
+                _check(lib().fem_mpnn_infer_async(self._h, problem._h, R, C.c_void_p(state.data_ptr()), seed, alpha,
+                                                  C.c_void_p(out.data_ptr()), C.c_void_p(stream.cuda_stream)))
+            else:
+                _check(lib().fem_mpnn_infer(self._h, problem._h, R, C.c_void_p(state.data_ptr()), seed, alpha,
+                                            C.c_void_p(out.data_ptr()), 1))
             return out
+        assert stream is None, "stream-ordered inference takes device tensors"
         st, ps = _host(state, np.float32)
         st = st.reshape(problem.n, -1)
         h = np.empty_like(st)

@@ -135,6 +135,27 @@ def test_infer_on_device_tensors():
     assert np.array_equal(out.cpu().numpy(), host)
 
 
+def test_infer_queued_on_a_stream():
+    """fem_mpnn_infer_async: the same proposal, queued on a torch stream
+    behind work that writes its input (twice, the second at a smaller R)."""
+    import torch
+
+    _, off, ops, batch = small_batch((250, 400))
+    net = fem.MPNN(W.mpnn_init_weights(12))
+    stream = torch.cuda.Stream()
+    for R in (40, 7):
+        st = state_of(batch.n, 5 + R, R)
+        host = net.infer(batch, st, seed=9, alpha=1.5)
+        src = torch.from_numpy(st).cuda()
+        with torch.cuda.stream(stream):
+            dst = torch.zeros_like(src)
+            dst.copy_(src)          # queued on the stream before the inference
+            out = torch.empty_like(dst)
+        net.infer(batch, dst, seed=9, alpha=1.5, out=out, stream=stream)
+        stream.synchronize()
+        assert np.array_equal(out.cpu().numpy(), host)
+
+
 def test_forward_of_an_instance_does_not_depend_on_its_batch():
     """Each node's output is formed from its own inputs in a fixed order
     (layer 2's matrix-core steps included), so the first instance of a batch
