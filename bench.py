@@ -231,12 +231,14 @@ def main():
     ap.add_argument("--cpu-one-thread", type=int, default=32,
                     help="batch512: instances in the one-thread CPU baseline sample")
     ap.add_argument("--workload", choices=["batch512", "maxcut1e5", "bmincut1e6", "max3sat1e5", "k2000dense", "er800",
-                                           "copy"],
+                                           "infer512", "copy"],
                     default="batch512",
                     help="batch512 (default): 512 uneven MaxCut instances, R = 32, in one launch per step, with time "
                          "to target; maxcut1e5: N = 10^5, R = 256; bmincut1e6 / max3sat1e5: the Potts and Max-3-SAT "
                          "kernels at full size; er800: a G-set-sized instance (800 nodes, R = 16), launch-bound; "
                          "k2000dense: the dense-W (matrix-core) path on a complete 2000-node graph; "
+                         "infer512: the warm-start network's proposal for every replica of the 512-instance batch "
+                         "(--steps calls, timed on the device); "
                          "copy: a plain device copy (calibrates HBM counters)")
     ap.add_argument("--order", choices=["draw", "rcm"], default="rcm",
                     help="bmincut1e6: node order of the graph (rcm: relabelled by fem_graph_order before the "
@@ -286,7 +288,40 @@ def main():
     if args.workload == "batch512":
         batch_headline(args)
         return
+    if args.workload == "infer512":
+        infer_batch(args)
+        return
     throughput(args)
+
+
+def infer_batch(args):
+    """The warm-start network's proposal for all 32 replicas of the
+    512-instance union (inputs on the device), queued on one stream; one
+    JSON line with the time per call."""
+    import numpy as np
+    import torch
+
+    from paper_2412_09285_amd import batchbench as BB
+    from paper_2412_09285_amd import fem
+
+    b = BB.Batch(BB.instances(args.instances))
+    net = fem.MPNN(np.zeros(fem.N_MPNN_PARAMS, dtype=np.float32))
+    net.load(args.params)
+    stream = torch.cuda.Stream()
+    out = torch.empty_like(b.h0)
+    K = args.steps if args.steps else 10
+    for _ in range(2):
+        net.infer(b.union, b.h0, seed=5, alpha=1.0, out=out, stream=stream)
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(K):
+        net.infer(b.union, b.h0, seed=5, alpha=1.0, out=out, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    print(json.dumps({"workload": "infer512", "instances": len(b.graphs), "n": b.n, "nnz": b.nnz, "replicas": b.R,
+                      "calls": K, "ms_per_call": ms, "data": "synthetic (the batch512 instances and fields h0)"}))
 
 
 def batch_headline(args):
