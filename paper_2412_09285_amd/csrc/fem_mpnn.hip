@@ -402,56 +402,52 @@ __device__ __forceinline__ float relu_f(float x) { return __int_as_float(max(__f
 // bias (weights 256 b1 times 2^-8, exact) and no operand needs patching.
 constexpr float ONE_B1 = 1.00390625f;
 
-// The inputs of node i sit side by side for the two lane groups of the
-// layer-1 products: G[2 i] = gf_i and G[2 i + 1] = ga_i; XA[2 i] and
-// XA[2 i + 1] (blocks of NRF R floats) hold Xr_i and AXr_i.
-
-// graph inputs gf[i] = G[2 i] = {ONE_B1, ln(1+deg), mean incident weight (0
-// if isolated), 1/max(deg,1)}, as the per-replica forward forms them; slot x
-// is the constant input 1 of lane group 0 in the layer-1 products, stored as
+// graph inputs gf[i] = {ONE_B1, ln(1+deg), mean incident weight (0 if
+// isolated), 1/max(deg,1)}, as the per-replica forward forms them; slot x is
+// the constant input 1 of lane group 0 in the layer-1 products, stored as
 // 1 + 2^-8 (see inf_layer2_kernel)
 __global__ void inf_graph_kernel(int32_t n, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
-                                 float4* __restrict__ G)
+                                 float4* __restrict__ gf)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int64_t b = row_off[i], e = row_off[i + 1];
         float ws = 0.0f;
         for (int64_t k = b; k < e; ++k) ws += __int_as_float(adj[k].y);
         const float deg = (float)(e - b);
-        G[2 * (size_t)i] = make_float4(ONE_B1, log1pf(deg), e > b ? ws / deg : 0.0f, 1.0f / fmaxf(deg, 1.0f));
+        gf[i] = make_float4(ONE_B1, log1pf(deg), e > b ? ws / deg : 0.0f, 1.0f / fmaxf(deg, 1.0f));
     }
 }
 
-// their aggregates ga[i] = G[2 i + 1] = {a(1), a(ln(1+deg)), a(mean weight),
-// 0}, each sum in CSR order, then scaled by 1/max(deg,1)
+// their aggregates ga[i] = {a(1), a(ln(1+deg)), a(mean weight), 0}, each sum
+// in CSR order, then scaled by 1/max(deg,1)
 __global__ void inf_graph_agg_kernel(int32_t n, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
-                                     float4* __restrict__ G)
+                                     const float4* __restrict__ gf, float4* __restrict__ ga)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
         for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
             const int2 e = adj[k];
             const float w = __int_as_float(e.y);
-            const float4 q = G[2 * (size_t)e.x];
+            const float4 q = gf[e.x];
             a0 = fmaf(w, 1.0f, a0);
             a1 = fmaf(w, q.y, a1);
             a2 = fmaf(w, q.z, a2);
         }
-        const float id = G[2 * (size_t)i].w;
-        G[2 * (size_t)i + 1] = make_float4(a0 * id, a1 * id, a2 * id, 0.0f);
+        const float id = gf[i].w;
+        ga[i] = make_float4(a0 * id, a1 * id, a2 * id, 0.0f);
     }
 }
 
-// replica inputs Xr_i[f][r] of the fields state[i][r] (draw r)
+// replica inputs Xr[i][f][r] of the fields state[i][r] (draw r)
 __global__ void inf_feat_kernel(int32_t n, int32_t R, const float* __restrict__ state, uint32_t k0, uint32_t k1,
-                                float* __restrict__ XA)
+                                float* __restrict__ Xr)
 {
     const size_t count = (size_t)n * R;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(k / R), r = (int)(k % R);
         const float sv = state[k];
         const U4 w = philox((uint32_t)i, (uint32_t)r, 0u, 0u, k0, k1);
-        float* x = XA + 2 * (size_t)i * NRF * R + r;
+        float* x = Xr + (size_t)i * NRF * R + r;
         x[0] = tanhf(0.5f * sv);
         x[R] = fminf(fmaxf(0.25f * sv, -2.0f), 2.0f);
         x[2 * R] = upm1(w.x);
@@ -460,9 +456,9 @@ __global__ void inf_feat_kernel(int32_t n, int32_t R, const float* __restrict__ 
     }
 }
 
-// their aggregates AXr_i[f][r], each sum in CSR order, then scaled
+// their aggregates AXr[i][f][r], each sum in CSR order, then scaled
 __global__ void inf_agg_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
-                               const float4* __restrict__ G, float* __restrict__ XA)
+                               const float4* __restrict__ gf, const float* __restrict__ Xr, float* __restrict__ AXr)
 {
     const size_t count = (size_t)n * R;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
@@ -481,7 +477,7 @@ __global__ void inf_agg_kernel(int32_t n, int32_t R, const int64_t* __restrict__
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (u < nb) {
-                    const float* x = XA + 2 * (size_t)e[u].x * NRF * R + r;
+                    const float* x = Xr + (size_t)e[u].x * NRF * R + r;
 #pragma unroll
                     for (int f = 0; f < NRF; ++f) xv[u][f] = x[(size_t)f * R];
                 }
@@ -493,8 +489,8 @@ __global__ void inf_agg_kernel(int32_t n, int32_t R, const int64_t* __restrict__
                     for (int f = 0; f < NRF; ++f) a[f] = fmaf(w, xv[u][f], a[f]);
                 }
         }
-        const float id = G[2 * (size_t)i].w;
-        float* o = XA + (2 * (size_t)i + 1) * NRF * R + r;
+        const float id = gf[i].w;
+        float* o = AXr + (size_t)i * NRF * R + r;
 #pragma unroll
         for (int f = 0; f < NRF; ++f) o[(size_t)f * R] = a[f] * id;
     }
@@ -517,7 +513,8 @@ struct XcdRanges {
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
 inf_layer2_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off, const int2* __restrict__ adj,
-                  const float4* __restrict__ G, const float* __restrict__ XA, const uint16_t* __restrict__ w,
+                  const float4* __restrict__ gf, const float4* __restrict__ ga, const float* __restrict__ Xr,
+                  const float* __restrict__ AXr, const uint16_t* __restrict__ w,
                   float alpha, XcdRanges xr,
                   float* __restrict__ h_out)
 {
@@ -571,6 +568,8 @@ inf_layer2_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off, con
         aW1m[t] = __builtin_bit_cast(bf16x8, v);
     }
     const float dd = bf(w[OFF_d]);
+    const float4* gp = g ? ga : gf;
+    const float* xp = g ? AXr : Xr;
     const int nrb = (R + 31) / 32;
     // this XCD's range and the wave's place among the XCD's waves, stated
     // uniform so that node and neighbour indices live in scalar registers
@@ -599,11 +598,9 @@ inf_layer2_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off, con
             float x[NRF];
         };
         const int rl = ract ? r : 0;
-        const int lane_off = g * NRF * R + rl;
         auto inputs = [&](int j, In& in) {
-            // node j's block (uniform) plus this lane's offset in it
-            in.q = G[2 * (size_t)j + g];
-            const float* x = XA + 2 * (size_t)j * NRF * R + lane_off;
+            in.q = gp[j];
+            const float* x = xp + (size_t)j * NRF * R + rl;
 #pragma unroll
             for (int f = 0; f < NRF; ++f) in.x[f] = x[(size_t)f * R];
         };
@@ -676,7 +673,7 @@ inf_layer2_kernel(int32_t n, int32_t R, const int64_t* __restrict__ row_off, con
                 asm volatile("" ::: "memory");
             }
         }
-        const float id = G[2 * (size_t)i].w;
+        const float id = gf[i].w;
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -1207,16 +1204,18 @@ static fem_status infer_enqueue(fem_mpnn* m, const Problem& p, int32_t R, const 
         m->tcap = need;
     }
     if (n == 0) return FEM_OK;
-    float4* G = reinterpret_cast<float4*>(m->tbuf);
-    float* XA = m->tbuf + 8 * (n + 1);
+    float4* gf = reinterpret_cast<float4*>(m->tbuf);
+    float4* ga = gf + (n + 1);
+    float* Xr = m->tbuf + 8 * (n + 1);
+    float* AXr = Xr + NRF * nR;
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     const unsigned gn = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
     const unsigned gnr = (unsigned)std::min<size_t>((nR + 255) / 256, 65536);
     (void)hipGetLastError();
-    inf_graph_kernel<<<gn, 256, 0, st>>>(p.n, p.row_off, p.adj, G);
-    inf_graph_agg_kernel<<<gn, 256, 0, st>>>(p.n, p.row_off, p.adj, G);
-    inf_feat_kernel<<<gnr, 256, 0, st>>>(p.n, R, src, k0, k1, XA);
-    inf_agg_kernel<<<gnr, 256, 0, st>>>(p.n, R, p.row_off, p.adj, G, XA);
+    inf_graph_kernel<<<gn, 256, 0, st>>>(p.n, p.row_off, p.adj, gf);
+    inf_graph_agg_kernel<<<gn, 256, 0, st>>>(p.n, p.row_off, p.adj, gf, ga);
+    inf_feat_kernel<<<gnr, 256, 0, st>>>(p.n, R, src, k0, k1, Xr);
+    inf_agg_kernel<<<gnr, 256, 0, st>>>(p.n, R, p.row_off, p.adj, gf, Xr, AXr);
     // XCD ranges of about equal work: a node costs about as much as
     // NODE_COST neighbours (its output layer)
     const int nrb = (R + 31) / 32;
@@ -1233,7 +1232,7 @@ static fem_status infer_enqueue(fem_mpnn* m, const Problem& p, int32_t R, const 
     }
     xr.b[N_XCD] = items;
     const unsigned gl = (unsigned)std::min<int64_t>(((items + 3) / 4 + N_XCD - 1) / N_XCD * N_XCD, 8192);
-    inf_layer2_kernel<<<gl, 256, 0, st>>>(p.n, R, p.row_off, p.adj, G, XA, m->wbf, alpha, xr, dst);
+    inf_layer2_kernel<<<gl, 256, 0, st>>>(p.n, R, p.row_off, p.adj, gf, ga, Xr, AXr, m->wbf, alpha, xr, dst);
     hipError_t el = hipGetLastError();
     if (el != hipSuccess) return mfail(FEM_E_HIP, "inference kernels", el);
     return FEM_OK;
