@@ -95,6 +95,7 @@ static void free_problem_device(Problem& p)
 {
     dfree(p.row_off);
     dfree(p.adj);
+    dfree(p.adj_pm1);
     dfree(p.inc2);
     dfree(p.inc4);
     dfree(p.wdeg);
@@ -114,6 +115,23 @@ static fem_status upload_problem(Problem& p)
     if (!p.h_adj.empty()) {
         HIPCHK(dalloc(&p.adj, p.h_adj.size()));
         HIPCHK(hipMemcpy(p.adj, p.h_adj.data(), p.h_adj.size() * sizeof(int2), hipMemcpyHostToDevice));
+        // MaxCut with every weight +-1: the step kernel reads 4-byte entries,
+        // the sign in bit 31 of the column (the Potts kernel keeps the 8-byte
+        // form: unpacking there cost it 23 registers and a wave per SIMD)
+        auto wt = [&](size_t k) {
+            float w;
+            std::memcpy(&w, &p.h_adj[k].y, sizeof w);
+            return w;
+        };
+        bool pm1 = p.kind == KIND_MAXCUT;
+        for (size_t k = 0; pm1 && k < p.h_adj.size(); ++k) pm1 = (wt(k) == 1.0f || wt(k) == -1.0f) && p.h_adj[k].x >= 0;
+        if (pm1) {
+            std::vector<int32_t> c(p.h_adj.size());
+            for (size_t k = 0; k < c.size(); ++k)
+                c[k] = (int32_t)((uint32_t)p.h_adj[k].x | (wt(k) < 0.0f ? 0x80000000u : 0u));
+            HIPCHK(dalloc(&p.adj_pm1, c.size()));
+            HIPCHK(hipMemcpy(p.adj_pm1, c.data(), c.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        }
     }
     if (!p.h_inc2.empty()) {
         HIPCHK(dalloc(&p.inc2, p.h_inc2.size()));
@@ -641,6 +659,7 @@ static StepArgs base_args(const fem_solver* s)
     StepArgs a{};
     a.row_off = p.row_off;
     a.adj = p.adj;
+    a.adj_pm1 = p.adj_pm1;
     a.inc2 = p.inc2;
     a.inc4 = p.inc4;
     a.wdeg = p.wdeg;

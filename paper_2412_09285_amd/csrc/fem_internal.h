@@ -33,6 +33,7 @@ struct Problem {
     // device arrays
     int64_t* row_off = nullptr;      // [n+1]
     int2* adj = nullptr;             // graphs: {col, float bits of w}
+    int32_t* adj_pm1 = nullptr;      // MaxCut with every weight +-1: col | (w < 0) << 31 (4 B per entry)
     int2* inc2 = nullptr;            // Max-k-SAT, <= 2 other literals per incidence
     int4* inc4 = nullptr;            // Max-k-SAT, <= 3 other literals per incidence
     float* wdeg = nullptr;           // bMinCut: sum_j W_ij per node
@@ -157,6 +158,7 @@ inline LaunchGeom make_geom(int per_lane, int R, int waves, int max_lanes = 64)
 struct StepArgs {
     const int64_t* row_off;
     const int2* adj;
+    const int32_t* adj_pm1;       // the same entries in 4 bytes when every weight is +-1, else null
     const int2* inc2;
     const int4* inc4;
     const float* wdeg;

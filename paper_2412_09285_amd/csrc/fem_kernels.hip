@@ -29,13 +29,26 @@
 
 namespace fem {
 
+// Adjacency entry k as {column, float bits of the weight}; with PM1 (every
+// weight +-1) from the 4-byte form, the sign in bit 31 of the column.
+template <bool PM1>
+__device__ __forceinline__ int2 ld_adj(const StepArgs& a, int64_t k)
+{
+    if constexpr (PM1) {
+        const uint32_t e = (uint32_t)a.adj_pm1[k];
+        return make_int2((int)(e & 0x7fffffffu), (int)(0x3f800000u | (e & 0x80000000u)));
+    } else {
+        return a.adj[k];
+    }
+}
+
 // ========================================================= MaxCut step ====
 // phi_i = sum_j W_ij m_j with m = tanh(h/2) = 2P - 1 (the stored copy);
 // g_i = P_i (1 - P_i) [2 phi_i + h_i / beta]: the explicit gradient of the
 // ordered-pair F through the one-logit reduction.  Energies: U = -W_tot +
 // (1/2) sum_i m_i phi_i and S = sum_i H2(P_i), accumulated here as
 // [sum m phi, sum H2] per replica.
-template <int V, typename MT, bool EN, bool NT>
+template <int V, typename MT, bool EN, bool NT, bool PM1>
 __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_kernel(StepArgs a)
 {
     const Tile tile = a.tiles[blk_tile(a.seg_major)];
@@ -80,7 +93,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                     int2 e[16];
                     float x[16][1];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) e[u] = a.adj[k + u];
+                    for (int u = 0; u < 16; ++u) e[u] = ld_adj<PM1>(a, k + u);
 #pragma unroll
                     for (int u = 0; u < 16; ++u) ld_marg<MT, 1>(mc + (size_t)e[u].x * R + rb, x[u]);
 #pragma unroll
@@ -90,7 +103,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                     int2 e[8];
                     float x[8][1];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) e[u] = a.adj[k + u];
+                    for (int u = 0; u < 8; ++u) e[u] = ld_adj<PM1>(a, k + u);
 #pragma unroll
                     for (int u = 0; u < 8; ++u) ld_marg<MT, 1>(mc + (size_t)e[u].x * R + rb, x[u]);
 #pragma unroll
@@ -98,7 +111,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 }
             }
             for (; k + 4 <= kend; k += 4) {
-                const int2 e0 = a.adj[k], e1 = a.adj[k + 1], e2 = a.adj[k + 2], e3 = a.adj[k + 3];
+                const int2 e0 = ld_adj<PM1>(a, k), e1 = ld_adj<PM1>(a, k + 1), e2 = ld_adj<PM1>(a, k + 2), e3 = ld_adj<PM1>(a, k + 3);
                 float x0[V], x1[V], x2[V], x3[V];
                 ld_marg<MT, V>(mc + (size_t)e0.x * R + rb, x0);
                 ld_marg<MT, V>(mc + (size_t)e1.x * R + rb, x1);
@@ -115,7 +128,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 }
             }
             if (k + 2 <= kend) {   // a remaining pair in one round
-                const int2 e0 = a.adj[k], e1 = a.adj[k + 1];
+                const int2 e0 = ld_adj<PM1>(a, k), e1 = ld_adj<PM1>(a, k + 1);
                 float x0[V], x1[V];
                 ld_marg<MT, V>(mc + (size_t)e0.x * R + rb, x0);
                 ld_marg<MT, V>(mc + (size_t)e1.x * R + rb, x1);
@@ -128,7 +141,7 @@ __global__ void __launch_bounds__(step_max_threads(KIND_MAXCUT, V)) maxcut_step_
                 k += 2;
             }
             if (k < kend) {
-                const int2 e0 = a.adj[k];
+                const int2 e0 = ld_adj<PM1>(a, k);
                 float x0[V];
                 ld_marg<MT, V>(mc + (size_t)e0.x * R + rb, x0);
                 const CT w0 = __int_as_float(e0.y);
@@ -1010,8 +1023,14 @@ __global__ void best_update_kernel(int kind, int R, int n_inst, int q, double la
 template <int V, typename MT, bool NT>
 static void launch_maxcut(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStream_t st)
 {
-    if (en) maxcut_step_kernel<V, MT, true, NT><<<g, b, lds_bytes(b.x / 64, L, 2 * V), st>>>(a);
-    else maxcut_step_kernel<V, MT, false, NT><<<g, b, 0, st>>>(a);
+    const size_t lds = en ? lds_bytes(b.x / 64, L, 2 * V) : 0;
+    if (a.adj_pm1) {
+        if (en) maxcut_step_kernel<V, MT, true, NT, true><<<g, b, lds, st>>>(a);
+        else maxcut_step_kernel<V, MT, false, NT, true><<<g, b, lds, st>>>(a);
+    } else {
+        if (en) maxcut_step_kernel<V, MT, true, NT, false><<<g, b, lds, st>>>(a);
+        else maxcut_step_kernel<V, MT, false, NT, false><<<g, b, lds, st>>>(a);
+    }
 }
 template <int V, typename MT, int W, bool NT>
 static void launch_sat(bool en, dim3 g, dim3 b, int L, const StepArgs& a, hipStream_t st)
