@@ -79,7 +79,10 @@ typedef struct fem_solver fem_solver;     /* R replicas: h, Adam moments, margin
  * E(sigma) = -sum_{(i,j) in E} W_ij [1 - delta(sigma_i, sigma_j)].
  * u, v: n_edges endpoints (host, 0 <= u,v < n, u != v, no duplicate pair);
  * w: host weights or NULL for all +1.  Self-loops, duplicate edges,
- * out-of-range ids, non-finite weights and n < 1 give FEM_E_INVAL. */
+ * out-of-range ids, non-finite weights and n < 1 give FEM_E_INVAL.
+ * Device memory: the symmetric CSR (8-byte row offsets, 8-byte entries) and,
+ * when every weight is +1 or -1, a second 4-byte copy of the entries (column
+ * and sign) that the step kernel reads. */
 fem_status fem_maxcut_create(int device, int32_t n, int64_t n_edges, const int32_t* u,
                              const int32_t* v, const float* w, fem_problem** out);
 
