@@ -257,7 +257,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(replicas would shard with no communication; see the design notes). "
+              "(replicas would shard across GPUs with no per-step communication). "
               f"Requested --gpus {args.gpus} (WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
 

@@ -12,7 +12,7 @@
  * Everything is double precision and single-threaded.  Loops follow the
  * definitions in the paper's order; no blocking, fusion or reordering.
  *
- * Readings of the paper taken here (each is listed in the design notes):
+ * Readings of the paper taken here:
  *  - Edge sums run over ordered pairs: each undirected edge {i,j} appears as
  *    (i,j) and (j,i).  This is the convention under which the explicit
  *    gradients printed in the supplementary section "The explicit gradients
