@@ -87,6 +87,16 @@ def test_ragged_shapes(R, n):
     lockstep_maxcut(g, R=R, T=200, n_steps=25, seed=7 + R, tag=f"n{n}_R{R}")
 
 
+@pytest.mark.parametrize("tile", [None, (1, 4, 2, 1, 0), (4, 4, 4, 1, 8)])
+def test_real_weights_read_the_eight_byte_entries(tile):
+    """Weights other than +-1 keep the {col, weight} entries (graphs of +-1
+    weights read the 4-byte form); lockstep over the first 20 steps in
+    several launch shapes."""
+    g = W.random_sparse_graph(700, 2800, seed=21, weights="pm1")
+    g.w = np.random.default_rng(21).uniform(-2.0, 2.0, size=g.n_edges).astype(np.float32)
+    lockstep_maxcut(g, R=32, T=100, n_steps=20, seed=13, tile=tile, tag=f"real weights, tile {tile}")
+
+
 def test_isolated_nodes_and_tiny_graphs():
     # nodes 4, 5, 6 isolated, weighted path elsewhere
     g = W.Graph(7, np.array([0, 1, 2], np.int32), np.array([1, 2, 3], np.int32), np.array([1, -2, 3], np.float32))
