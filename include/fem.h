@@ -332,8 +332,8 @@ typedef struct {
 } fem_tile;
 fem_status fem_get_tile(const fem_solver* s, fem_tile* t);
 fem_status fem_set_tile(fem_solver* s, const fem_tile* t);
-/* Autotune: time every valid shape for trial_steps steps (state is restored
- * afterwards), keep the fastest, and cache it on disk under the key (kind, n,
+/* Autotune: time every valid shape twice for trial_steps steps from the same
+ * state (restored afterwards), keep the shape with the fastest run, and cache it on disk under the key (kind, n,
  * nnz, R, q, dtype, instances, energies on/off, gradient mode) in
  * $FEM_TUNE_CACHE (default ~/.cache/femx/tune.txt).  use_cache = 1 returns a
  * cached choice without timing: the user's cache first, then the shapes

@@ -1932,15 +1932,22 @@ fem_status fem_tune(fem_solver* s, int32_t trial_steps, int32_t use_cache, fem_t
         if (st != FEM_OK) break;
         st = fem_step(s, 1);   // warm-up
         if (st != FEM_OK) break;
-        st = save_restore(false);
+        // the faster of two timed runs from the same state: one run of a few
+        // steps varies by a few percent, about the gap between the best shapes
+        float ms = std::numeric_limits<float>::infinity();
+        for (int rep = 0; rep < 2 && st == FEM_OK; ++rep) {
+            st = save_restore(false);
+            if (st != FEM_OK) break;
+            (void)hipEventRecord(e0, s->stream);
+            st = fem_step(s, trial);
+            (void)hipEventRecord(e1, s->stream);
+            if (st != FEM_OK) break;
+            (void)hipEventSynchronize(e1);
+            float m = 0.0f;
+            (void)hipEventElapsedTime(&m, e0, e1);
+            ms = std::min(ms, m);
+        }
         if (st != FEM_OK) break;
-        (void)hipEventRecord(e0, s->stream);
-        st = fem_step(s, trial);
-        (void)hipEventRecord(e1, s->stream);
-        if (st != FEM_OK) break;
-        (void)hipEventSynchronize(e1);
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best_ms) {
             best_ms = ms;
             best_sh = sh;

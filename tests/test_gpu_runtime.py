@@ -97,6 +97,25 @@ def test_determinism():
     assert np.array_equal(sa.energies()[2], sb.energies()[2])
 
 
+def test_tuning_restores_the_state(tmp_path, monkeypatch):
+    """fem_tune times every shape (twice each) from a device-side backup:
+    afterwards the solver continues exactly as one that was never tuned, the
+    chosen shape is reported, and it is cached under FEM_TUNE_CACHE."""
+    monkeypatch.setenv("FEM_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    g, prob = maxcut_problem(n=900, seed=12)
+    R = 64
+    h0 = W.initial_fields(g.n, R, seed=12)
+    ref, _ = run_fields(prob, h0, R, 30, energy_every=1)
+    s = fem.Solver(prob, fem.default_params(replicas=R, steps=200, energy_every=1))
+    s.set_fields(h0)
+    s.step(10)
+    tile = s.tune(trial_steps=3, use_cache=False)
+    assert tile == s.tile()
+    s.step(20)
+    assert np.array_equal(s.fields(), ref)
+    assert (tmp_path / "tune.txt").read_text().split()[-5:] == [str(v) for v in tile]
+
+
 @pytest.mark.parametrize("kind", ["maxcut", "maxcut_dense_rows", "maxsat", "bmincut"])
 def test_every_tile_shape_gives_identical_fields(kind):
     R = 64
