@@ -425,13 +425,26 @@ __global__ void inf_graph_agg_kernel(int32_t n, const int64_t* __restrict__ row_
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-        for (int64_t k = row_off[i]; k < row_off[i + 1]; ++k) {
-            const int2 e = adj[k];
-            const float w = __int_as_float(e.y);
-            const float4 q = gf[e.x];
-            a0 = fmaf(w, 1.0f, a0);
-            a1 = fmaf(w, q.y, a1);
-            a2 = fmaf(w, q.z, a2);
+        const int64_t kend = row_off[i + 1];
+        // rounds of up to four neighbours in flight, summed in CSR order
+        for (int64_t k = row_off[i]; k < kend; k += 4) {
+            const int nb = (int)min((int64_t)4, kend - k);
+            int2 e[4];
+            float4 q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < nb) e[u] = adj[k + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < nb) q[u] = gf[e[u].x];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < nb) {
+                    const float w = __int_as_float(e[u].y);
+                    a0 = fmaf(w, 1.0f, a0);
+                    a1 = fmaf(w, q[u].y, a1);
+                    a2 = fmaf(w, q[u].z, a2);
+                }
         }
         const float id = gf[i].w;
         ga[i] = make_float4(a0 * id, a1 * id, a2 * id, 0.0f);
